@@ -1,0 +1,195 @@
+/*
+ * abc.h -- C ABI of libabc.so, the MI355X (gfx950) rejection-ABC hot path for
+ * the stochastic COVID-19 compartment model of Kulkarni, Krell, Nabarro and
+ * Moritz, "Hardware-accelerated Simulation-based Inference of Stochastic
+ * Epidemiology Models for COVID-19" (arXiv 2012.14332).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named "device" are HIP device memory owned by the caller; host
+ *    structs are read during the call only. The library keeps no caller
+ *    pointer after the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every
+ *    call only enqueues work on it and returns; results are visible after the
+ *    stream has been synchronised.
+ *  - Return value: ABC_OK, or a negative status. Argument errors are detected
+ *    on the host before anything is enqueued (ABC_EINVAL); HIP failures
+ *    return ABC_EHIP. abc_last_error() gives a message for the calling thread.
+ *  - Results are a pure function of the arguments: the seed, stream domain,
+ *    series id and sample indices fix every random number (counter-based
+ *    Philox4x32-10), so launch shapes and call splitting never change them.
+ *
+ * Parameter vector (eq. 1): theta = [alpha0, alpha, n, beta, gamma, delta,
+ * eta, kappa], stored as 8 consecutive float32 per sample ([n][8] row-major).
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = (seed mod
+ * 2^32, seed >> 32) and counter = (i mod 2^32, i >> 32, series,
+ * (day << 8) | (domain << 4) | block) for sample index i.
+ *   theta draw (eq. 2): day 0, blocks 0..1 -> 8 words w; u = (w >> 8) 2^-24;
+ *     theta_k = fmaf(hi_k - lo_k, u_k, lo_k) in float32.
+ *   noise of day t >= 1: block 0 -> four words -> six 21-bit fields
+ *     (w0..w3 >> 11, (w0 & 0x7ff) << 10 | (w1 & 0x3ff),
+ *     (w2 & 0x7ff) << 10 | (w3 & 0x3ff)); u = (f + 1/2) 2^-21; Box-Muller
+ *     pairs (u0,u1), (u2,u3), (u4,u5) give z1..z5, one per transition.
+ */
+#ifndef ABC_H
+#define ABC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define ABC_API __attribute__((visibility("default")))
+#else
+#define ABC_API
+#endif
+
+typedef int32_t abc_status;
+#define ABC_OK 0
+#define ABC_EINVAL (-1)       /* bad argument; nothing enqueued */
+#define ABC_EHIP (-2)         /* a HIP runtime call failed */
+#define ABC_ENOMEM (-3)       /* library scratch could not be allocated */
+#define ABC_EUNSUPPORTED (-4) /* option combination not built */
+
+/* Model options (flags of abc_model.flags). */
+#define ABC_FP64 0x1u          /* simulate in double precision (default float32) */
+#define ABC_KAHAN 0x2u         /* compensated float32 distance sum */
+#define ABC_NOISE_LITERAL 0x4u /* noise sd = h^(1/4) ("variance sqrt(h)" read literally);
+                                  default sd = sqrt(h), i.e. variance h */
+#define ABC_DIST_RAW 0x8u      /* Euclidean distance on raw counts (default: log1p counts) */
+
+#define ABC_T_MAX 1024         /* longest horizon a series may have */
+
+/* Uniform prior box (eq. 2): theta_k ~ U(lo_k, hi_k), lo_k <= hi_k. The paper's
+ * prior is lo = 0, hi = [1, 100, 2, 1, 1, 1, 1, 2]. Host memory. */
+typedef struct {
+    float lo[8];
+    float hi[8];
+} abc_prior;
+
+/* Random stream selector. domain in [0, 15]: 0 = observation synthesis,
+ * 1 = ABC sampling/simulation, 2 = learned-proposal training data,
+ * 3 = network initialisation, 5 = learned-proposal draws. */
+typedef struct {
+    uint64_t seed;
+    uint32_t domain;
+    uint32_t series;
+} abc_stream;
+
+/* One observed series (Sec. 2.1): population P at the first time point,
+ * observed A0, R0, D0 at day 0, horizon T in [1, ABC_T_MAX], and the observed
+ * A, R, D counts of days 1..T as a DEVICE int32 array [3][T] (row c = A, R, D).
+ * obs may be NULL for calls that do not compare (abc_simulate_record).
+ * Requires A0 >= 1, R0, D0 >= 0 and A0 + R0 + D0 <= P <= 2^31 - 1 (the state is
+ * int32). I0 = floor(kappa A0) is limited to P - A0 - R0 - D0 so that S >= 0. */
+typedef struct {
+    int64_t P;
+    int32_t A0, R0, D0;
+    int32_t T;
+    const int32_t* obs;
+} abc_series;
+
+/* Model options: noise_scale multiplies the noise standard deviation
+ * (1 = the paper's model, 0 = the deterministic floor map); flags = ABC_*. */
+typedef struct {
+    float noise_scale;
+    uint32_t flags;
+} abc_model;
+
+/*
+ * Draw theta for samples first .. first+n-1 from the uniform prior (eq. 2).
+ *   prior   host; lo <= hi elementwise (finite).
+ *   st      host; stream selector (domain <= 15).
+ *   theta   device float32 [n][8], written.
+ * n = 0 is a no-op. Errors: ABC_EINVAL (NULL pointer, bad box, n < 0).
+ */
+ABC_API abc_status abc_sample_prior(const abc_prior* prior, const abc_stream* st, uint64_t first,
+                            int64_t n, float* theta, void* stream);
+
+/*
+ * Simulate the tau-leap model of Sec. 2.1 (eqs. 3-5: hazards, Gaussian draws
+ * floored and clamped in h order, day updates) for samples first .. first+n-1
+ * and reduce each trajectory to its Euclidean distance from ser->obs over days
+ * 1..T (Sec. 2.2), on log1p counts unless ABC_DIST_RAW.
+ *   ser     host struct; ser->obs device [3][T] (required).
+ *   model   host; noise scale and ABC_* flags.
+ *   st      host; stream selector.
+ *   theta   device float32 [n][8], or NULL: then theta is drawn in-kernel from
+ *           `prior` on the same stream exactly as abc_sample_prior would.
+ *   prior   host; required when theta is NULL, ignored otherwise.
+ *   eps_exit  early-exit bound: a sample stops as soon as its running squared
+ *           distance exceeds eps_exit^2 (with a margin that can never flip an
+ *           accept decision at eps <= eps_exit) and reports +INF. Pass +INF to
+ *           simulate every day.
+ *   dist    device float32 [n]: the distance, or +INF after an early exit.
+ *   dist64  device float64 [n] or NULL: the same value before rounding to
+ *           float32 (with ABC_FP64 the full double result).
+ * Errors: ABC_EINVAL (T out of range, P/A0/R0/D0 inconsistent, NULL pointers,
+ * n < 0, noise_scale < 0 or not finite).
+ */
+ABC_API abc_status abc_simulate_distance(const abc_series* ser, const abc_model* model,
+                                 const abc_stream* st, const float* theta,
+                                 const abc_prior* prior, uint64_t first, int64_t n,
+                                 float eps_exit, float* dist, double* dist64, void* stream);
+
+/*
+ * Simulate like abc_simulate_distance but record the full integer state
+ * (S, I, A, R, D, Ru) of days 0..T: traj is device int32 [n][T+1][6].
+ * ser->obs is not read. theta is device float32 [n][8] (required).
+ * Used to synthesise observed series (domain 0) and to check trajectories.
+ */
+ABC_API abc_status abc_simulate_record(const abc_series* ser, const abc_model* model,
+                               const abc_stream* st, const float* theta, uint64_t first,
+                               int64_t n, int32_t* traj, void* stream);
+
+/*
+ * Accept-reject and stable compaction (Sec. 2.2, eq. 7; Sec. 3.2): keep the
+ * samples k in [0, n) with dist[k] <= eps, in increasing k, and write for the
+ * r-th kept sample (r < capacity):
+ *   out_idx[r]   = first + k                          (device int64 [capacity])
+ *   out_theta[r] = theta[k][0..7]                     (device float32 [capacity][8])
+ *   out_dist[r]  = dist[k]                            (device float32 [capacity], nullable)
+ *   out_w[r]     = weight[k]                          (device float32 [capacity], nullable)
+ * theta may be NULL: then the row is re-drawn from `prior` on stream `st`
+ * (the in-kernel draw of abc_simulate_distance). weight may be NULL (then
+ * out_w must be NULL). *out_count (device int64) receives the total number
+ * kept, which may exceed capacity; rows beyond capacity are not written.
+ * Errors: ABC_EINVAL (NULL required pointer, n < 0, capacity < 0, theta and
+ * prior both NULL).
+ */
+ABC_API abc_status abc_accept_compact(const float* dist, const float* theta, const float* weight,
+                              const abc_prior* prior, const abc_stream* st, int64_t n,
+                              uint64_t first, float eps, int64_t capacity, int64_t* out_idx,
+                              float* out_theta, float* out_dist, float* out_w,
+                              int64_t* out_count, void* stream);
+
+/*
+ * Posterior mean and covariance of accepted theta in float64 (the summaries
+ * the paper reports as posterior averages, Table "t:trajectories").
+ *   theta   device float32 [n_max][8]; the first n rows are used, where n =
+ *           min(*n_dev, n_max) is read on the device (n_dev: device int64,
+ *           e.g. the out_count of abc_accept_compact). n_dev may be NULL: n = n_max.
+ *   weight  device float32 [n_max] or NULL (all ones).
+ *   mean    device float64 [8]: sum w theta / V1.
+ *   cov     device float64 [8][8]: sum w (theta-mean)(theta-mean)^T / (V1 - V2/V1),
+ *           V1 = sum w, V2 = sum w^2 (the unbiased n-1 form when w = 1).
+ * n = 0 gives NaN mean and covariance; n = 1 a NaN covariance. The summation
+ * order depends only on n_max, never on timing.
+ */
+ABC_API abc_status abc_posterior_moments(const float* theta, const float* weight, const int64_t* n_dev,
+                                 int64_t n_max, double* mean, double* cov, void* stream);
+
+/* Message describing the last non-OK status returned on this thread. */
+ABC_API const char* abc_last_error(void);
+
+/* Library version string. */
+ABC_API const char* abc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABC_H */

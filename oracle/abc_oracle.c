@@ -31,7 +31,7 @@
  *     literal "variance sqrt(h)" (standard deviation h^(1/4)) is mode 1;
  *   - each draw is clamped to [0, what its source compartment still holds
  *     at the start of the day after earlier outflows in h order];
- *   - I0 = floor(kappa * A0);
+ *   - I0 = floor(kappa * A0), limited to P - A0 - R0 - D0 so that S >= 0;
  *   - one step per day; the distance covers days 1..T;
  *   - distance on log1p counts (mode 0) or on raw counts (mode 1).
  *
@@ -192,7 +192,7 @@ static int64_t draw_count(const oracle_model* m, double h, double z, int64_t ava
         sd = m->noise_scale * sqrt(sqrt(h));
     const double x = h + sd * z;
     const double f = floor(x);
-    if (f <= 0.0) return 0;
+    if (!(f > 0.0)) return 0; /* negative, or NaN from a negative rate */
     if (f >= (double)avail) return avail;
     return (int64_t)f;
 }
@@ -214,6 +214,7 @@ static double trajectory(const oracle_model* m, const float theta_f[8], uint64_t
 
     int64_t A = m->A0, R = m->R0, D = m->D0, Ru = 0;
     int64_t I = (int64_t)floor(kappa * (double)m->A0);
+    if (I > m->P - (A + R + D)) I = m->P - (A + R + D); /* S cannot go negative */
     int64_t S = m->P - (A + R + D + I);
     const double P = (double)m->P;
 

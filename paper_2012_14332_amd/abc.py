@@ -1,0 +1,200 @@
+"""ctypes binding of libabc.so (include/abc.h): argument marshalling only.
+
+Every function takes torch CUDA (HIP) tensors as device buffers and enqueues
+on ``torch.cuda.current_stream()``; nothing here computes. If the library is
+missing the first call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabc.so")
+
+ABC_FP64 = 0x1
+ABC_KAHAN = 0x2
+ABC_NOISE_LITERAL = 0x4
+ABC_DIST_RAW = 0x8
+T_MAX = 1024
+
+PRIOR_LO = (0.0,) * 8
+PRIOR_HI = (1.0, 100.0, 2.0, 1.0, 1.0, 1.0, 1.0, 2.0)
+
+
+class AbcError(RuntimeError):
+    pass
+
+
+class _Prior(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float * 8), ("hi", ctypes.c_float * 8)]
+
+
+class _Stream(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("domain", ctypes.c_uint32),
+                ("series", ctypes.c_uint32)]
+
+
+class _Series(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("A0", ctypes.c_int32), ("R0", ctypes.c_int32),
+                ("D0", ctypes.c_int32), ("T", ctypes.c_int32), ("obs", ctypes.c_void_p)]
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("noise_scale", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libabc.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise AbcError("libabc.so not found at %s: build it with "
+                           "`python -m paper_2012_14332_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, u64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
+        P = ctypes.POINTER
+        L.abc_sample_prior.argtypes = [P(_Prior), P(_Stream), u64, i64, vp, vp]
+        L.abc_simulate_distance.argtypes = [P(_Series), P(_Model), P(_Stream), vp, P(_Prior), u64,
+                                            i64, f32, vp, vp, vp]
+        L.abc_simulate_record.argtypes = [P(_Series), P(_Model), P(_Stream), vp, u64, i64, vp, vp]
+        L.abc_accept_compact.argtypes = [vp, vp, vp, P(_Prior), P(_Stream), i64, u64, f32, i64,
+                                         vp, vp, vp, vp, vp, vp]
+        L.abc_posterior_moments.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        for f in ("abc_sample_prior", "abc_simulate_distance", "abc_simulate_record",
+                  "abc_accept_compact", "abc_posterior_moments"):
+            getattr(L, f).restype = ctypes.c_int32
+        L.abc_last_error.restype = ctypes.c_char_p
+        L.abc_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise AbcError("libabc status %d: %s" % (rc, lib().abc_last_error().decode()))
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise AbcError("expected a device tensor")
+    if not t.is_contiguous():
+        raise AbcError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_prior(lo: Sequence[float] = PRIOR_LO, hi: Sequence[float] = PRIOR_HI) -> _Prior:
+    return _Prior((ctypes.c_float * 8)(*lo), (ctypes.c_float * 8)(*hi))
+
+
+def make_stream(seed: int, domain: int = 1, series: int = 0) -> _Stream:
+    return _Stream(int(seed), int(domain), int(series))
+
+
+class DeviceSeries:
+    """An observed series whose [3, T] int32 counts live in device memory."""
+
+    def __init__(self, P: int, T: int, obs: Optional[torch.Tensor] = None, A0: int = 100,
+                 R0: int = 0, D0: int = 0, device="cuda"):
+        self.P, self.T, self.A0, self.R0, self.D0 = int(P), int(T), int(A0), int(R0), int(D0)
+        if obs is not None:
+            obs = obs.to(device=device, dtype=torch.int32).contiguous()
+            if tuple(obs.shape) != (3, self.T):
+                raise AbcError("obs must have shape [3, T]")
+        self.obs = obs
+
+    def c(self) -> _Series:
+        return _Series(self.P, self.A0, self.R0, self.D0, self.T,
+                       None if self.obs is None else self.obs.data_ptr())
+
+
+def sample_prior(n: int, seed: int, domain: int = 1, series: int = 0, first: int = 0,
+                 prior: Optional[_Prior] = None, out: Optional[torch.Tensor] = None,
+                 device="cuda") -> torch.Tensor:
+    theta = out if out is not None else torch.empty((n, 8), dtype=torch.float32, device=device)
+    pr = prior or make_prior()
+    st = make_stream(seed, domain, series)
+    _check(lib().abc_sample_prior(ctypes.byref(pr), ctypes.byref(st), int(first), int(n),
+                                  _dptr(theta), _stream_handle()))
+    return theta
+
+
+def simulate_distance(ser: DeviceSeries, n: int, seed: int, *, theta: Optional[torch.Tensor] = None,
+                      first: int = 0, domain: int = 1, series: int = 0,
+                      eps_exit: float = math.inf, flags: int = 0, noise_scale: float = 1.0,
+                      prior: Optional[_Prior] = None, out: Optional[torch.Tensor] = None,
+                      want64: bool = False, device="cuda"):
+    dist = out if out is not None else torch.empty(n, dtype=torch.float32, device=device)
+    d64 = torch.empty(n, dtype=torch.float64, device=device) if want64 else None
+    pr = prior or make_prior()
+    st = make_stream(seed, domain, series)
+    md = _Model(float(noise_scale), int(flags))
+    cs = ser.c()
+    _check(lib().abc_simulate_distance(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(st),
+                                       _dptr(theta), ctypes.byref(pr), int(first), int(n),
+                                       float(eps_exit), _dptr(dist), _dptr(d64),
+                                       _stream_handle()))
+    return (dist, d64) if want64 else dist
+
+
+def simulate_record(ser: DeviceSeries, theta: torch.Tensor, seed: int, *, first: int = 0,
+                    domain: int = 1, series: int = 0, flags: int = 0, noise_scale: float = 1.0,
+                    device="cuda") -> torch.Tensor:
+    n = theta.shape[0]
+    traj = torch.empty((n, ser.T + 1, 6), dtype=torch.int32, device=device)
+    st = make_stream(seed, domain, series)
+    md = _Model(float(noise_scale), int(flags))
+    cs = ser.c()
+    _check(lib().abc_simulate_record(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(st),
+                                     _dptr(theta), int(first), int(n), _dptr(traj),
+                                     _stream_handle()))
+    return traj
+
+
+def accept_compact(dist: torch.Tensor, eps: float, capacity: int, *,
+                   theta: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
+                   first: int = 0, seed: int = 0, domain: int = 1, series: int = 0,
+                   prior: Optional[_Prior] = None, device="cuda"):
+    """Returns (idx int64 [cap], theta [cap,8], dist [cap], w [cap] or None, count int64 [1]);
+    only the first min(count, cap) rows are valid."""
+    n = dist.shape[0]
+    cap = int(capacity)
+    out_idx = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+    out_th = torch.empty((max(cap, 1), 8), dtype=torch.float32, device=device)
+    out_d = torch.empty(max(cap, 1), dtype=torch.float32, device=device)
+    out_w = torch.empty(max(cap, 1), dtype=torch.float32, device=device) if weight is not None else None
+    count = torch.empty(1, dtype=torch.int64, device=device)
+    pr = prior or make_prior()
+    st = make_stream(seed, domain, series)
+    _check(lib().abc_accept_compact(_dptr(dist), _dptr(theta), _dptr(weight), ctypes.byref(pr),
+                                    ctypes.byref(st), int(n), int(first), float(eps), cap,
+                                    _dptr(out_idx), _dptr(out_th), _dptr(out_d), _dptr(out_w),
+                                    _dptr(count), _stream_handle()))
+    return out_idx, out_th, out_d, out_w, count
+
+
+def posterior_moments(theta: torch.Tensor, weight: Optional[torch.Tensor] = None,
+                      n_dev: Optional[torch.Tensor] = None, device="cuda"):
+    n_max = theta.shape[0]
+    mean = torch.empty(8, dtype=torch.float64, device=device)
+    cov = torch.empty((8, 8), dtype=torch.float64, device=device)
+    _check(lib().abc_posterior_moments(_dptr(theta), _dptr(weight), _dptr(n_dev), int(n_max),
+                                       _dptr(mean), _dptr(cov), _stream_handle()))
+    return mean, cov
+
+
+def version() -> str:
+    return lib().abc_version().decode()

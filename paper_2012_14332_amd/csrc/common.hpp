@@ -1,0 +1,78 @@
+// Host-side plumbing shared by the translation units of libabc.so: the
+// per-thread error message, HIP error checks and argument validation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include "../../include/abc.h"
+
+namespace abc {
+
+abc_status set_error(abc_status st, const char* fmt, ...);
+
+#define ABC_REQUIRE(cond, ...)                                 \
+    do {                                                       \
+        if (!(cond)) return ::abc::set_error(ABC_EINVAL, __VA_ARGS__); \
+    } while (0)
+
+#define ABC_HIP(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::abc::set_error(ABC_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+inline abc_status check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(ABC_EHIP, "launch of %s: %s", what, hipGetErrorString(e));
+    return ABC_OK;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Prior box -> (lo, width) with width = fl32(hi - lo), as the draw uses it.
+inline abc_status prior_lo_width(const abc_prior* prior, float lo[8], float width[8])
+{
+    ABC_REQUIRE(prior != nullptr, "prior is NULL");
+    for (int k = 0; k < 8; ++k) {
+        ABC_REQUIRE(isfinite(prior->lo[k]) && isfinite(prior->hi[k]) && prior->lo[k] <= prior->hi[k],
+                    "prior box %d is not finite with lo <= hi", k);
+        lo[k] = prior->lo[k];
+        width[k] = prior->hi[k] - prior->lo[k];
+    }
+    return ABC_OK;
+}
+
+inline abc_status check_stream_sel(const abc_stream* st)
+{
+    ABC_REQUIRE(st != nullptr, "stream selector is NULL");
+    ABC_REQUIRE(st->domain <= 15u, "stream domain %u > 15", st->domain);
+    return ABC_OK;
+}
+
+inline abc_status check_series(const abc_series* ser, bool need_obs)
+{
+    ABC_REQUIRE(ser != nullptr, "series is NULL");
+    ABC_REQUIRE(ser->T >= 1 && ser->T <= ABC_T_MAX, "T = %d outside [1, %d]", ser->T, ABC_T_MAX);
+    ABC_REQUIRE(ser->A0 >= 1 && ser->R0 >= 0 && ser->D0 >= 0, "need A0 >= 1, R0 >= 0, D0 >= 0");
+    ABC_REQUIRE(ser->P <= INT32_MAX, "P = %lld does not fit the int32 state", (long long)ser->P);
+    ABC_REQUIRE((int64_t)ser->A0 + ser->R0 + ser->D0 <= ser->P,
+                "A0 + R0 + D0 exceeds the population P");
+    if (need_obs) ABC_REQUIRE(ser->obs != nullptr, "series obs is NULL");
+    return ABC_OK;
+}
+
+inline abc_status check_model(const abc_model* m)
+{
+    ABC_REQUIRE(m != nullptr, "model is NULL");
+    ABC_REQUIRE(isfinite(m->noise_scale) && m->noise_scale >= 0.0f, "noise_scale must be finite and >= 0");
+    ABC_REQUIRE((m->flags & ~(ABC_FP64 | ABC_KAHAN | ABC_NOISE_LITERAL | ABC_DIST_RAW)) == 0u,
+                "unknown model flags 0x%x", m->flags);
+    return ABC_OK;
+}
+
+}  // namespace abc

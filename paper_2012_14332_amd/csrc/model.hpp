@@ -1,0 +1,222 @@
+// Device-side model of Sec. 2.1 (eqs. 3-5) and the distance of Sec. 2.2.
+//
+// One lane owns one trajectory: the six compartments live in VGPRs as int32
+// (exact for populations below 2^31), the hazards, Gaussian draws and
+// distance run in float32 (or float64 for the precision study and the
+// recheck of borderline samples). Nothing of the trajectory is written to
+// memory; the distance is accumulated day by day.
+//
+// Day t >= 1 of sample i:
+//   M  = A + R + D,  g = alpha0 + alpha / (1 + M^n)                   eq. (4)
+//   h  = (g S I / P, gamma I, beta A, delta A, beta eta I)            eq. (5)
+//   x_k = h_k + s sd(h_k) z_k with sd = sqrt(h) (or h^(1/4) literally),
+//   n_k = floor(x_k) clamped to [0, what the source still holds]: S for n1,
+//   I for n2, A for n3, A - n3 for n4, I - n2 for n5 (h order), then
+//   S -= n1; I += n1 - n2 - n5; A += n2 - n3 - n4; R += n3; D += n4; Ru += n5.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace abc {
+
+struct State {
+    int32_t S, I, A, R, D, Ru;
+};
+
+// Per-sample theta (float32 values as drawn or supplied).
+struct Theta {
+    float a0, al, n, be, ga, de, et, ka;
+};
+
+__device__ __forceinline__ Theta theta_from(const float t[8])
+{
+    return Theta{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7]};
+}
+
+// Prior draw (eq. 2): 8 words from blocks 0 and 1 of day 0.
+__device__ __forceinline__ void prior_draw(Key key, uint64_t i, uint32_t series, uint32_t domain,
+                                           const float* lo, const float* width, float th[8])
+{
+    const uint4 a = stream_words(key, i, series, ctr_word3(0, domain, 0));
+    const uint4 b = stream_words(key, i, series, ctr_word3(0, domain, 1));
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float u = (float)(w[k] >> 8) * 0x1p-24f;  // exact
+        th[k] = fmaf(width[k], u, lo[k]);
+    }
+}
+
+// Day-0 state: Ru = 0, I0 = floor(kappa A0) (computed exactly in double),
+// S = P - (A0 + R0 + D0 + I0); I0 is limited so that S >= 0.
+__device__ __forceinline__ State init_state(float kappa, int32_t P, int32_t A0, int32_t R0,
+                                            int32_t D0)
+{
+    State s;
+    s.A = A0;
+    s.R = R0;
+    s.D = D0;
+    s.Ru = 0;
+    const double i0 = floor((double)kappa * (double)A0);
+    const int32_t room = P - (A0 + R0 + D0);
+    s.I = i0 >= (double)room ? room : (int32_t)i0;
+    s.S = room - s.I;
+    return s;
+}
+
+// The six 21-bit uniforms of one day: u = (f + 1/2) 2^-21, exact in float.
+__device__ __forceinline__ void day_fields(uint4 w, uint32_t f[6])
+{
+    f[0] = w.x >> 11;
+    f[1] = w.y >> 11;
+    f[2] = w.z >> 11;
+    f[3] = w.w >> 11;
+    f[4] = ((w.x & 0x7FFu) << 10) | (w.y & 0x3FFu);
+    f[5] = ((w.z & 0x7FFu) << 10) | (w.w & 0x3FFu);
+}
+
+// ---------------------------------------------------------------------------
+// float32 path: hardware transcendentals (v_log_f32 = log2, v_exp_f32 = 2^x,
+// v_sqrt_f32, v_rcp_f32, v_sin/v_cos_f32 which take revolutions).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void normals_f32(uint4 w, float z[5])
+{
+    uint32_t f[6];
+    day_fields(w, f);
+    float u[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u[k] = ((float)f[k] + 0.5f) * 0x1p-21f;
+    // -2 ln u = -2 ln(2) log2(u)
+    const float c = -1.38629436111989061883f;
+    const float r0 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[0]));
+    const float r1 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[2]));
+    const float r2 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[4]));
+    z[0] = r0 * __builtin_amdgcn_cosf(u[1]);  // cos(2 pi u1)
+    z[1] = r0 * __builtin_amdgcn_sinf(u[1]);
+    z[2] = r1 * __builtin_amdgcn_cosf(u[3]);
+    z[3] = r1 * __builtin_amdgcn_sinf(u[3]);
+    z[4] = r2 * __builtin_amdgcn_cosf(u[5]);
+}
+
+// floor(h + sd z) limited to [0, avail]. The float is clamped below 2^31
+// before the conversion, then the integer is limited to avail, so a float
+// rounding of avail can never leak into the count.
+template <int NOISE>
+__device__ __forceinline__ int32_t draw_f32(float h, float z, int32_t avail, float scale)
+{
+    float sd = __builtin_amdgcn_sqrtf(h);
+    if (NOISE == 1) sd = __builtin_amdgcn_sqrtf(sd);
+    const float x = fmaf(scale * sd, z, h);
+    float f = floorf(x);
+    f = fminf(fmaxf(f, 0.0f), 2147483520.0f);
+    return min((int32_t)f, avail);
+}
+
+struct RatesF {
+    float a0, al, n, be, ga, de, bh;  // bh = beta * eta
+};
+
+__device__ __forceinline__ RatesF rates_f32(const Theta& t)
+{
+    return RatesF{t.a0, t.al, t.n, t.be, t.ga, t.de, t.be * t.et};
+}
+
+template <int NOISE>
+__device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float invP, float scale,
+                                             const float z[5])
+{
+    const float M = (float)(s.A + s.R + s.D);
+    const float pw = __builtin_amdgcn_exp2f(r.n * __builtin_amdgcn_logf(M));
+    const float g = fmaf(r.al, __builtin_amdgcn_rcpf(1.0f + pw), r.a0);
+    const float If = (float)s.I;
+    const float Af = (float)s.A;
+    const float h1 = g * (float)s.S * (If * invP);
+    const float h2 = r.ga * If;
+    const float h3 = r.be * Af;
+    const float h4 = r.de * Af;
+    const float h5 = r.bh * If;
+    const int32_t n1 = draw_f32<NOISE>(h1, z[0], s.S, scale);
+    const int32_t n2 = draw_f32<NOISE>(h2, z[1], s.I, scale);
+    const int32_t n3 = draw_f32<NOISE>(h3, z[2], s.A, scale);
+    const int32_t n4 = draw_f32<NOISE>(h4, z[3], s.A - n3, scale);
+    const int32_t n5 = draw_f32<NOISE>(h5, z[4], s.I - n2, scale);
+    s.S -= n1;
+    s.I += n1 - n2 - n5;
+    s.A += n2 - n3 - n4;
+    s.R += n3;
+    s.D += n4;
+    s.Ru += n5;
+}
+
+// log1p of a non-negative count: ln(X + 1) = log2(X + 1) ln 2.
+__device__ __forceinline__ float log1p_count_f32(int32_t X)
+{
+    return __builtin_amdgcn_logf((float)(X + 1)) * 0.693147180559945309417f;
+}
+
+// ---------------------------------------------------------------------------
+// float64 path: the same definitions evaluated in the order the oracle writes
+// them (no contraction), with the device math library's log/sin/cos/pow/log1p.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void normals_f64(uint4 w, double z[5])
+{
+#pragma clang fp contract(off)
+    uint32_t f[6];
+    day_fields(w, f);
+    double u[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u[k] = ((double)f[k] + 0.5) * 0x1p-21;
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    const double r0 = sqrt(-2.0 * log(u[0]));
+    const double r1 = sqrt(-2.0 * log(u[2]));
+    const double r2 = sqrt(-2.0 * log(u[4]));
+    z[0] = r0 * cos(two_pi * u[1]);
+    z[1] = r0 * sin(two_pi * u[1]);
+    z[2] = r1 * cos(two_pi * u[3]);
+    z[3] = r1 * sin(two_pi * u[3]);
+    z[4] = r2 * cos(two_pi * u[5]);
+}
+
+template <int NOISE>
+__device__ __forceinline__ int32_t draw_f64(double h, double z, int32_t avail, double scale)
+{
+#pragma clang fp contract(off)
+    double sd = NOISE == 0 ? scale * sqrt(h) : scale * sqrt(sqrt(h));
+    const double x = h + sd * z;
+    const double f = floor(x);
+    if (!(f > 0.0)) return 0;
+    if (f >= (double)avail) return avail;
+    return (int32_t)f;
+}
+
+template <int NOISE>
+__device__ __forceinline__ void day_step_f64(State& s, const Theta& t, double P, double scale,
+                                             const double z[5])
+{
+#pragma clang fp contract(off)
+    const double M = (double)(s.A + s.R + s.D);
+    const double g = (double)t.a0 + (double)t.al / (1.0 + pow(M, (double)t.n));
+    const double h1 = g * (double)s.S * (double)s.I / P;
+    const double h2 = (double)t.ga * (double)s.I;
+    const double h3 = (double)t.be * (double)s.A;
+    const double h4 = (double)t.de * (double)s.A;
+    const double h5 = (double)t.be * (double)t.et * (double)s.I;
+    const int32_t n1 = draw_f64<NOISE>(h1, z[0], s.S, scale);
+    const int32_t n2 = draw_f64<NOISE>(h2, z[1], s.I, scale);
+    const int32_t n3 = draw_f64<NOISE>(h3, z[2], s.A, scale);
+    const int32_t n4 = draw_f64<NOISE>(h4, z[3], s.A - n3, scale);
+    const int32_t n5 = draw_f64<NOISE>(h5, z[4], s.I - n2, scale);
+    s.S -= n1;
+    s.I += n1 - n2 - n5;
+    s.A += n2 - n3 - n4;
+    s.R += n3;
+    s.D += n4;
+    s.Ru += n5;
+}
+
+}  // namespace abc

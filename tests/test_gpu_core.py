@@ -1,0 +1,246 @@
+"""GPU parity of the plain rejection-ABC path against the FP64 oracle, through
+the C ABI (libabc.so via the ctypes binding).
+
+Bars:
+  * theta (prior draw): bit-exact float32.
+  * float64 simulation: integer trajectories identical to the oracle's and
+    distances within 1e-12 relative (both sides evaluate the same definitions
+    in IEEE double; only last-bit differences of log/pow/sin/cos between the
+    device math library and host libm remain, which move a floor only when a
+    pre-floor value lies within ~1e-16 relative of an integer).
+  * float32 simulation: the accuracy contract is stated per result (see the
+    precision tests); the accept decision near eps is made in float64.
+  * compaction: bit-exact index/theta/distance sets, index order.
+  * moments: float64 within 1e-12 relative of the oracle's two-pass formula.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2012_14332_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES_RAGGED = [1, 255, 257, 4096 * 3 + 17]
+
+
+@pytest.fixture(scope="module")
+def A():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_14332_amd import abc
+
+    abc.lib()
+    return abc
+
+
+def _series(A, P, T, obs=None, A0=100):
+    return A.DeviceSeries(P, T, None if obs is None else torch.from_numpy(np.asarray(obs)), A0=A0)
+
+
+def test_library_loads_from_tree(A):
+    assert A.version().startswith("abc-mi355x")
+
+
+@pytest.mark.parametrize("n", [0] + SIZES_RAGGED)
+def test_prior_bit_exact(A, n):
+    th = A.sample_prior(n, seed=42, domain=1, series=3, first=5000)
+    ref = oracle.prior(n, seed=42, domain=1, series=3, first=5000)
+    np.testing.assert_array_equal(th.cpu().numpy().reshape(-1, 8), ref)
+
+
+def test_prior_custom_box_and_big_indices(A):
+    lo = [0.1, -3.0, 0.0, 0.25, 0.0, 0.0, 0.3, 0.5]
+    hi = [0.9, 7.5, 2.0, 0.75, 1.0, 1e-3, 1.0, 2.0]
+    first = (7 << 32) + 123
+    th = A.sample_prior(1000, seed=(9 << 32) | 77, domain=5, series=63, first=first,
+                        prior=A.make_prior(lo, hi))
+    ref = oracle.prior(1000, seed=(9 << 32) | 77, domain=5, series=63, first=first,
+                       lo=np.array(lo, np.float32), hi=np.array(hi, np.float32))
+    np.testing.assert_array_equal(th.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("P,T", [(10_000_000, 49), (330_000_000, 100), (100_000, 30),
+                                  (2_000_000_000, 60)])
+def test_record_fp64_matches_oracle_trajectories(A, P, T):
+    n = 1500
+    th = A.sample_prior(n, seed=7)
+    traj = A.simulate_record(_series(A, P, T), th, seed=7, flags=A.ABC_FP64)
+    ref = oracle.record(oracle.make_model(P, T), th.cpu().numpy(), seed=7)
+    got = traj.cpu().numpy().astype(np.int64)
+    same = np.all(got == ref, axis=(1, 2))
+    assert same.mean() == 1.0, "fp64 trajectories differ for %d of %d samples" % (
+        (~same).sum(), n)
+
+
+def test_record_fp64_modes_and_domains(A):
+    P, T = 8_300_000, 72
+    th = A.sample_prior(400, seed=3, domain=2, series=9)
+    for flags, kw in [(A.ABC_FP64 | A.ABC_NOISE_LITERAL, dict(noise_mode=1)),
+                      (A.ABC_FP64, dict(noise_scale=0.0)),
+                      (A.ABC_FP64, dict(noise_scale=0.37))]:
+        ns = kw.get("noise_scale", 1.0)
+        traj = A.simulate_record(_series(A, P, T), th, seed=3, domain=2, series=9, first=10,
+                                 flags=flags, noise_scale=ns)
+        ref = oracle.record(oracle.make_model(P, T, **kw), th.cpu().numpy(), seed=3, domain=2,
+                            series=9, first=10)
+        np.testing.assert_array_equal(traj.cpu().numpy(), ref)
+
+
+def test_observed_series_synthesis_matches(A):
+    for s in W.three_countries() + [W.single_country()]:
+        th = torch.from_numpy(s.theta_true[None]).cuda()
+        traj = A.simulate_record(_series(A, s.P, s.T), th, seed=s.obs_seed, domain=W.DOMAIN_OBS,
+                                 flags=A.ABC_FP64)
+        obs_gpu = traj[0, 1:, 2:5].T.contiguous().cpu().numpy()
+        obs_ref = oracle.observe(oracle.make_model(s.P, s.T), s.theta_true, s.obs_seed)
+        np.testing.assert_array_equal(obs_gpu, obs_ref)
+
+
+def test_record_fp32_invariants_and_early_days(A):
+    P, T = 60_000_000, 49
+    n = 4000
+    th = A.sample_prior(n, seed=11)
+    traj = A.simulate_record(_series(A, P, T), th, seed=11).cpu().numpy().astype(np.int64)
+    assert np.all(traj.sum(axis=2) == P)
+    assert np.all(traj >= 0)
+    assert np.all(np.diff(traj[..., 0], axis=1) <= 0)
+    for k in (3, 4, 5):
+        assert np.all(np.diff(traj[..., k], axis=1) >= 0)
+    ref = oracle.record(oracle.make_model(P, T), th.cpu().numpy(), seed=11)
+    # day 1 starts from counts <= a few hundred, where float32 rounding cannot
+    # reach a floor boundary except in rare near-integer cases
+    same1 = np.all(traj[:, 1] == ref[:, 1], axis=1)
+    assert same1.mean() > 0.995, same1.mean()
+
+
+def _obs_for(s):
+    return oracle.observe(oracle.make_model(s.P, s.T), s.theta_true, s.obs_seed)
+
+
+@pytest.mark.parametrize("n", [1000, 4096 * 2 + 33])
+def test_distance_fp64_matches_oracle(A, n):
+    s = W.three_countries()[1]
+    obs = _obs_for(s)
+    ser = _series(A, s.P, s.T, obs)
+    d, d64 = A.simulate_distance(ser, n, seed=1, first=777, flags=A.ABC_FP64, want64=True)
+    ref = oracle.distances(oracle.make_model(s.P, s.T), obs, seed=1, n=n, first=777)
+    g = d64.cpu().numpy()
+    rel = np.abs(g - ref) / ref
+    assert rel.max() <= 1e-12, rel.max()
+    np.testing.assert_array_equal(d.cpu().numpy(), ref.astype(np.float32))
+
+
+def test_distance_fp64_supplied_theta_and_early_exit(A):
+    s = W.single_country()
+    obs = _obs_for(s)
+    ser = _series(A, s.P, s.T, obs)
+    n = 5000
+    th = A.sample_prior(n, seed=2)
+    ref = oracle.distances(oracle.make_model(s.P, s.T), obs, seed=2, n=n)
+    eps = float(np.quantile(ref, 0.01))
+    d = A.simulate_distance(ser, n, seed=2, theta=th, flags=A.ABC_FP64, eps_exit=eps)
+    g = d.cpu().numpy()
+    inf = np.isinf(g)
+    # early exit only for samples that end above eps; never changes an accept
+    assert np.all(ref[inf] > eps)
+    np.testing.assert_array_equal(np.nonzero(g <= eps)[0], np.nonzero(ref <= eps)[0])
+    fin = ~inf
+    assert np.all(np.abs(g[fin] - ref[fin]) <= 1e-6 * ref[fin])
+
+
+def test_distance_fp32_accuracy_statement(A):
+    """float32 state path against the FP64 oracle at 100k samples of the
+    single-country workload: accept decisions for the 100 nearest samples and
+    the distance error distribution stated in the design notes."""
+    s = W.single_country()
+    obs = _obs_for(s)
+    ser = _series(A, s.P, s.T, obs)
+    n = 100_000
+    d = A.simulate_distance(ser, n, seed=1).cpu().numpy().astype(np.float64)
+    ref = oracle.distances(oracle.make_model(s.P, s.T), obs, seed=1, n=n)
+    rel = np.abs(d - ref) / ref
+    print("fp32 rel err: median %.2e p99 %.2e max %.2e" % (np.median(rel),
+                                                            np.quantile(rel, 0.99), rel.max()))
+    assert np.median(rel) < 1e-4
+    near_ref = oracle.nearest(ref, 100)
+    near_gpu = oracle.nearest(d, 100)
+    # differences only where the 100th and 101st distances are within float32 error
+    diff = set(near_ref) ^ set(near_gpu)
+    kth = np.sort(ref)[99]
+    assert all(abs(ref[i] - kth) <= 1e-3 * kth for i in diff), sorted(diff)
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 1_000_003])
+def test_compact_matches_brute_force(A, n):
+    rng = np.random.default_rng(n)
+    dist = rng.exponential(size=n).astype(np.float32)
+    dist[rng.random(n) < 0.3] = np.inf
+    theta = rng.random((n, 8)).astype(np.float32)
+    w = rng.random(n).astype(np.float32)
+    eps = 0.05
+    keep = np.nonzero(dist <= eps)[0]
+    cap = len(keep) + 5
+    dd = torch.from_numpy(dist).cuda()
+    idx, th, od, ow, cnt = A.accept_compact(dd, eps, cap, theta=torch.from_numpy(theta).cuda(),
+                                            weight=torch.from_numpy(w).cuda(), first=1000)
+    c = int(cnt.item())
+    assert c == len(keep)
+    np.testing.assert_array_equal(idx.cpu().numpy()[:c], keep + 1000)
+    np.testing.assert_array_equal(th.cpu().numpy()[:c], theta[keep])
+    np.testing.assert_array_equal(od.cpu().numpy()[:c], dist[keep])
+    np.testing.assert_array_equal(ow.cpu().numpy()[:c], w[keep])
+
+
+def test_compact_overflow_and_prior_redraw(A):
+    n = 300_000
+    rng = np.random.default_rng(5)
+    dist = rng.random(n).astype(np.float32)
+    eps = 0.01
+    keep = np.nonzero(dist <= eps)[0]
+    cap = 100
+    idx, th, od, _, cnt = A.accept_compact(torch.from_numpy(dist).cuda(), eps, cap, first=50,
+                                           seed=8, domain=1, series=2)
+    assert int(cnt.item()) == len(keep) > cap
+    np.testing.assert_array_equal(idx.cpu().numpy(), keep[:cap] + 50)
+    ref_th = np.stack([oracle.prior(1, seed=8, domain=1, series=2, first=int(k) + 50)[0]
+                       for k in keep[:cap]])
+    np.testing.assert_array_equal(th.cpu().numpy(), ref_th)
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 2048 * 3 + 5, 1_000_000])
+def test_moments_match_oracle(A, n):
+    rng = np.random.default_rng(n)
+    th = (rng.random((n, 8)) * np.array(W.PRIOR_HI)).astype(np.float32)
+    w = rng.exponential(size=n).astype(np.float32)
+    for weight in (None, w):
+        mean, cov = A.posterior_moments(torch.from_numpy(th).cuda(),
+                                        None if weight is None else torch.from_numpy(weight).cuda())
+        rm, rc = oracle.moments(th, weight)
+        np.testing.assert_allclose(mean.cpu().numpy(), rm, rtol=1e-12, atol=1e-12)
+        if n > 1:
+            np.testing.assert_allclose(cov.cpu().numpy(), rc, rtol=1e-10, atol=1e-12)
+
+
+def test_moments_device_count_and_empty(A):
+    rng = np.random.default_rng(0)
+    th = rng.random((5000, 8)).astype(np.float32)
+    cnt = torch.tensor([1234], dtype=torch.int64, device="cuda")
+    mean, cov = A.posterior_moments(torch.from_numpy(th).cuda(), n_dev=cnt)
+    rm, rc = oracle.moments(th[:1234])
+    np.testing.assert_allclose(mean.cpu().numpy(), rm, rtol=1e-12)
+    np.testing.assert_allclose(cov.cpu().numpy(), rc, rtol=1e-10, atol=1e-13)
+    cnt.zero_()
+    mean, cov = A.posterior_moments(torch.from_numpy(th).cuda(), n_dev=cnt)
+    assert torch.isnan(mean).all() and torch.isnan(cov).all()
+
+
+def test_invalid_arguments_raise(A):
+    ser = _series(A, 1000, 2000, None)
+    with pytest.raises(A.AbcError):
+        A.simulate_record(ser, A.sample_prior(4, seed=1), seed=1)
+    with pytest.raises(A.AbcError):
+        A.sample_prior(4, seed=1, domain=16)
