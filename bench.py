@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain rejection-ABC hot path on one MI355X.
+
+Workload (one step): three synthetic countries run separately -- P = 6e7,
+8.3e7, 3.3e8 with T = 49, 72, 100 days, observed series from one model run
+at the Italy / New Zealand / USA parameter averages (observation seeds 2-4)
+-- 1e7 fresh prior samples per country per step at a fixed eps, the
+distance that a fraction 1e-4 of a 1e5-sample pilot falls under. Per country
+and step: float32 simulate+distance with the prior drawn in-kernel and early
+exit, ballot compaction, float64 decision of the borderline band, float64
+posterior mean/covariance. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "accepted ABC samples/s at fixed ε (sim-days/s, VALU %); plain vs learned proposal"
+# VALU instructions of one simulated day in the float32 kernel, counted from
+# its gfx950 assembly (16 v_mad_u64_u32, 22 transcendental, 111 other).
+VALU_PER_SAMPLE_DAY = 149
+# FP32 operations of one simulated day (FMA = 2, transcendental = 1).
+FP32_FLOP_PER_SAMPLE_DAY = 72
+# Peak VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
+SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/csrc/model.hpp",
+               "paper_2012_14332_amd/csrc/philox.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_f32_traffic.json")
+
+
+def sim_source_hash():
+    h = hashlib.sha256()
+    for p in SIM_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the simulate kernel from the committed PMC
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != sim_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(countries, eps, first, n_sample):
+    """The FP64 oracle on the host cores, on the first n_sample indices of each
+    country's main range, at the same eps."""
+    import numpy as np
+
+    import oracle
+
+    t_total = 0.0
+    acc = 0
+    days = 0
+    for c, (s, e) in enumerate(zip(countries, eps)):
+        m = oracle.make_model(s.P, s.T)
+        obs = oracle.observe(m, s.theta_true, s.obs_seed, series=s.series_id)
+        t0 = time.perf_counter()
+        d = oracle.distances(m, obs, seed=1, n=n_sample, first=first, series=c)
+        t_total += time.perf_counter() - t0
+        acc += int(np.sum(d <= e))
+        days += n_sample * s.T
+    return {
+        "value": acc / t_total,
+        "unit": "accepted samples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "%d prior samples of each country (indices %d..%d), same eps; %d accepted in "
+                  "%.2f s; %.3e trajectories/s, %.3e sample-days/s (no early exit)"
+                  % (n_sample, first, first + n_sample - 1, acc, t_total,
+                     3 * n_sample / t_total, days / t_total),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples", type=int, default=10_000_000, help="prior samples per country per step")
+    ap.add_argument("--band", type=float, default=0.02)
+    ap.add_argument("--pilot", type=int, default=100_000)
+    ap.add_argument("--q", type=float, default=1e-4)
+    ap.add_argument("--cpu-samples", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--launch", type=str, default="", help="spl,block,blocks_per_cu")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (scales HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the ABC path is built for one device's share "
+              "(see the sharding notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2012_14332_amd import abc
+    from paper_2012_14332_amd import pipeline as PL
+    from paper_2012_14332_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    abc.lib()
+    if args.launch:
+        abc.set_launch_config(*[int(x) for x in args.launch.split(",")])
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    countries = W.three_countries()
+    sers = [PL.observed_series(s) for s in countries]
+    eps = [PL.pilot_eps(ser, 1, n=args.pilot, q=args.q, series=c) for c, ser in enumerate(sers)]
+    N = args.samples
+    first0 = args.pilot  # main-run indices follow the pilot prefix
+    runs = [PL.PlainABC(ser, 1, e, N, series=c, band_w=args.band) for c, (ser, e) in
+            enumerate(zip(sers, eps))]
+    sA = torch.cuda.current_stream()
+    sB = torch.cuda.Stream()
+    days = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def step(s, keep, ev):
+        first = first0 + s * N
+        for c, r in enumerate(runs):
+            e_hi = r.eps * (1 + r.band_w)
+            if ev is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e0.record(sA)
+            abc.simulate_distance(r.ser, N, r.seed, first=first, series=c, eps_exit=e_hi,
+                                  out=r.dist, days=days if ev is not None else None)
+            if ev is not None:
+                e1 = torch.cuda.Event(enable_timing=True)
+                e1.record(sA)
+                ev.append((e0, e1, c))
+            idx, th, d, _, cnt = abc.accept_compact(r.dist, e_hi, r.cap, first=first, seed=r.seed,
+                                                    series=c)
+            done = torch.cuda.Event()
+            done.record(sA)
+            with torch.cuda.stream(sB):
+                sB.wait_event(done)
+                abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
+                mean, cov = abc.posterior_moments(th, n_dev=cnt)
+            keep.append((c, idx, th, cnt, mean, cov))
+
+    keep = []
+    for s in range(args.warmup):
+        step(s, keep, None)
+    torch.cuda.synchronize()
+    keep = []
+    ev = []
+    days.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.warmup, args.warmup + args.steps):
+        step(s, keep, ev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    accepted = sum(int(k[3].item()) for k in keep)
+    sim_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    eff_days = int(days.item())
+    nominal_days = args.steps * N * sum(s.T for s in countries)
+    traj = args.steps * N * len(countries)
+    launches = len(sim_ms)
+    avg_ms = float(np.mean(sim_ms))
+    days_per_launch = eff_days / launches
+    achieved = VALU_PER_SAMPLE_DAY * days_per_launch / (avg_ms * 1e-3) / 1e12
+    flops = FP32_FLOP_PER_SAMPLE_DAY * days_per_launch / (avg_ms * 1e-3) / 1e12
+    traffic = traffic_per_launch()
+    per_country = {}
+    for c, s in enumerate(countries):
+        last = [k for k in keep if k[0] == c][-1]
+        n_c = sum(int(k[3].item()) for k in keep if k[0] == c)
+        per_country[s.name] = {"eps": eps[c], "accepted": n_c,
+                               "posterior_mean_last_step": [round(float(x), 5) for x in
+                                                            last[4].cpu().numpy()]}
+    out = {
+        "metric": METRIC,
+        "value": accepted / wall,
+        "unit": "accepted samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain rejection ABC, 3 synthetic countries run separately (P=6e7/8.3e7/"
+                        "3.3e8, T=49/72/100, 100 active at day 0), 1e7 prior samples per country "
+                        "per step, eps = 1e-4 quantile of a 1e5-sample pilot",
+            "samples_per_step": N * len(countries),
+            "eps": eps,
+            "band_w": args.band,
+            "launch_config": list(abc.get_launch_config()),
+        },
+        "trajectories_per_s": traj / wall,
+        "sim_days_per_s_effective": eff_days / wall,
+        "sim_days_per_s_nominal": nominal_days / wall,
+        "simulate_kernel_ms_avg": avg_ms,
+        "valu_frac": achieved / VALU_PEAK_TOPS,
+        "fp32_flops": {"achieved_tflops": flops, "peak_tflops": FP32_PEAK_TFLOPS,
+                       "frac": flops / FP32_PEAK_TFLOPS},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_simulate_f32",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": traffic,
+            "ops_per_sample_day": VALU_PER_SAMPLE_DAY,
+            "sample_days_per_launch": days_per_launch,
+        },
+        "per_country": per_country,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -117,8 +117,9 @@ ABC_API abc_status abc_sample_prior(const abc_prior* prior, const abc_stream* st
  *   ser     host struct; ser->obs device [3][T] (required).
  *   model   host; noise scale and ABC_* flags.
  *   st      host; stream selector.
- *   theta   device float32 [n][8], or NULL: then theta is drawn in-kernel from
- *           `prior` on the same stream exactly as abc_sample_prior would.
+ *   theta   device float32 [n][8] with non-negative rates, or NULL: then theta
+ *           is drawn in-kernel from `prior` (lo >= 0) on the same stream exactly
+ *           as abc_sample_prior would.
  *   prior   host; required when theta is NULL, ignored otherwise.
  *   eps_exit  early-exit bound: a sample stops as soon as its running squared
  *           distance exceeds eps_exit^2 (with a margin that can never flip an
@@ -127,13 +128,16 @@ ABC_API abc_status abc_sample_prior(const abc_prior* prior, const abc_stream* st
  *   dist    device float32 [n]: the distance, or +INF after an early exit.
  *   dist64  device float64 [n] or NULL: the same value before rounding to
  *           float32 (with ABC_FP64 the full double result).
+ *   days    device uint64 or NULL: the float32 kernel adds the number of
+ *           sample-days it simulated (after early exits) to *days.
  * Errors: ABC_EINVAL (T out of range, P/A0/R0/D0 inconsistent, NULL pointers,
  * n < 0, noise_scale < 0 or not finite).
  */
 ABC_API abc_status abc_simulate_distance(const abc_series* ser, const abc_model* model,
                                  const abc_stream* st, const float* theta,
                                  const abc_prior* prior, uint64_t first, int64_t n,
-                                 float eps_exit, float* dist, double* dist64, void* stream);
+                                 float eps_exit, float* dist, double* dist64,
+                                 unsigned long long* days, void* stream);
 
 /*
  * Simulate like abc_simulate_distance but record the full integer state
@@ -144,6 +148,29 @@ ABC_API abc_status abc_simulate_distance(const abc_series* ser, const abc_model*
 ABC_API abc_status abc_simulate_record(const abc_series* ser, const abc_model* model,
                                const abc_stream* st, const float* theta, uint64_t first,
                                int64_t n, int32_t* traj, void* stream);
+
+/*
+ * Float64 decision for borderline samples of a float32 pass. The float32
+ * distance of a trajectory can differ from its float64 value by more than a
+ * few ulps once a rounding moves a floored count (Sec. 2.1 draws); this call
+ * makes the accept decision (dist <= eps, eq. 7) in float64 wherever the
+ * float32 distance falls inside the band (eps (1 - band_w), eps (1 + band_w)].
+ * Input: the candidate rows of abc_accept_compact run with eps (1 + band_w)
+ * (idx, theta, dist, optional weight, all device, `capacity` rows) and their
+ * device count. Each in-band row is simulated again in float64 (same stream,
+ * sample idx[r], theta[r]) and its dist replaced by the float64 distance
+ * rounded to float32; rows outside the band keep their float32 decision.
+ * Kept rows are compacted in place in their original order and *count is set
+ * to their number. If *count > capacity on entry (an overflowed candidate
+ * set) nothing is changed. rechecked (device int32, nullable) receives the
+ * number of rows simulated in float64. ser, model, st as for
+ * abc_simulate_distance (the ABC_FP64 and ABC_KAHAN flags are ignored).
+ */
+ABC_API abc_status abc_recheck_band(const abc_series* ser, const abc_model* model,
+                                    const abc_stream* st, float eps, float band_w,
+                                    int64_t capacity, int64_t* idx, float* theta, float* dist,
+                                    float* weight, int64_t* count, int32_t* rechecked,
+                                    void* stream);
 
 /*
  * Accept-reject and stable compaction (Sec. 2.2, eq. 7; Sec. 3.2): keep the
@@ -181,6 +208,17 @@ ABC_API abc_status abc_accept_compact(const float* dist, const float* theta, con
  */
 ABC_API abc_status abc_posterior_moments(const float* theta, const float* weight, const int64_t* n_dev,
                                  int64_t n_max, double* mean, double* cov, void* stream);
+
+/*
+ * Launch shape of the float32 simulate+distance kernel for later calls made
+ * by the calling thread (the autotuner's knob): spl = independent samples
+ * per lane (1, 2, 4 or 8; more than 1 only for the default noise and
+ * distance), block = workgroup size (multiple of 64 in [64, 1024/spl]),
+ * blocks_per_cu = resident workgroups per compute unit (1..64). 0 selects the
+ * default (1, 512, 4). Results never depend on these settings, only speed.
+ */
+ABC_API abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu);
+ABC_API abc_status abc_get_launch_config(int32_t* spl, int32_t* block, int32_t* blocks_per_cu);
 
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);

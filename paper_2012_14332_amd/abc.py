@@ -63,7 +63,7 @@ def lib():
         P = ctypes.POINTER
         L.abc_sample_prior.argtypes = [P(_Prior), P(_Stream), u64, i64, vp, vp]
         L.abc_simulate_distance.argtypes = [P(_Series), P(_Model), P(_Stream), vp, P(_Prior), u64,
-                                            i64, f32, vp, vp, vp]
+                                            i64, f32, vp, vp, vp, vp]
         L.abc_simulate_record.argtypes = [P(_Series), P(_Model), P(_Stream), vp, u64, i64, vp, vp]
         L.abc_accept_compact.argtypes = [vp, vp, vp, P(_Prior), P(_Stream), i64, u64, f32, i64,
                                          vp, vp, vp, vp, vp, vp]
@@ -71,6 +71,13 @@ def lib():
         for f in ("abc_sample_prior", "abc_simulate_distance", "abc_simulate_record",
                   "abc_accept_compact", "abc_posterior_moments"):
             getattr(L, f).restype = ctypes.c_int32
+        L.abc_recheck_band.argtypes = [P(_Series), P(_Model), P(_Stream), f32, f32, i64, vp, vp,
+                                       vp, vp, vp, vp, vp]
+        L.abc_recheck_band.restype = ctypes.c_int32
+        L.abc_set_launch_config.argtypes = [ctypes.c_int32] * 3
+        L.abc_set_launch_config.restype = ctypes.c_int32
+        L.abc_get_launch_config.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
+        L.abc_get_launch_config.restype = ctypes.c_int32
         L.abc_last_error.restype = ctypes.c_char_p
         L.abc_version.restype = ctypes.c_char_p
         _lib = L
@@ -136,7 +143,10 @@ def simulate_distance(ser: DeviceSeries, n: int, seed: int, *, theta: Optional[t
                       first: int = 0, domain: int = 1, series: int = 0,
                       eps_exit: float = math.inf, flags: int = 0, noise_scale: float = 1.0,
                       prior: Optional[_Prior] = None, out: Optional[torch.Tensor] = None,
-                      want64: bool = False, device="cuda"):
+                      want64: bool = False, days: Optional[torch.Tensor] = None,
+                      device="cuda"):
+    """Distances of samples first..first+n-1 ([n] float32; + float64 copy if want64).
+    days: optional int64 [1] device tensor that accumulates the sample-days simulated."""
     dist = out if out is not None else torch.empty(n, dtype=torch.float32, device=device)
     d64 = torch.empty(n, dtype=torch.float64, device=device) if want64 else None
     pr = prior or make_prior()
@@ -145,7 +155,7 @@ def simulate_distance(ser: DeviceSeries, n: int, seed: int, *, theta: Optional[t
     cs = ser.c()
     _check(lib().abc_simulate_distance(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(st),
                                        _dptr(theta), ctypes.byref(pr), int(first), int(n),
-                                       float(eps_exit), _dptr(dist), _dptr(d64),
+                                       float(eps_exit), _dptr(dist), _dptr(d64), _dptr(days),
                                        _stream_handle()))
     return (dist, d64) if want64 else dist
 
@@ -186,6 +196,22 @@ def accept_compact(dist: torch.Tensor, eps: float, capacity: int, *,
     return out_idx, out_th, out_d, out_w, count
 
 
+def recheck_band(ser: DeviceSeries, seed: int, eps: float, band_w: float, idx: torch.Tensor,
+                 theta: torch.Tensor, dist: torch.Tensor, count: torch.Tensor, *,
+                 weight: Optional[torch.Tensor] = None, domain: int = 1, series: int = 0,
+                 flags: int = 0, noise_scale: float = 1.0, want_rechecked: bool = False):
+    """Float64 decision of the in-band candidate rows; edits the rows and count in place."""
+    st = make_stream(seed, domain, series)
+    md = _Model(float(noise_scale), int(flags))
+    cs = ser.c()
+    nre = torch.zeros(1, dtype=torch.int32, device=idx.device) if want_rechecked else None
+    _check(lib().abc_recheck_band(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(st),
+                                  float(eps), float(band_w), int(idx.shape[0]), _dptr(idx),
+                                  _dptr(theta), _dptr(dist), _dptr(weight), _dptr(count),
+                                  _dptr(nre), _stream_handle()))
+    return nre
+
+
 def posterior_moments(theta: torch.Tensor, weight: Optional[torch.Tensor] = None,
                       n_dev: Optional[torch.Tensor] = None, device="cuda"):
     n_max = theta.shape[0]
@@ -194,6 +220,17 @@ def posterior_moments(theta: torch.Tensor, weight: Optional[torch.Tensor] = None
     _check(lib().abc_posterior_moments(_dptr(theta), _dptr(weight), _dptr(n_dev), int(n_max),
                                        _dptr(mean), _dptr(cov), _stream_handle()))
     return mean, cov
+
+
+def set_launch_config(spl: int = 0, block: int = 0, blocks_per_cu: int = 0):
+    """Launch shape of the float32 simulate kernel for this thread (0 = default)."""
+    _check(lib().abc_set_launch_config(int(spl), int(block), int(blocks_per_cu)))
+
+
+def get_launch_config():
+    v = [ctypes.c_int32() for _ in range(3)]
+    _check(lib().abc_get_launch_config(*[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def version() -> str:

@@ -83,15 +83,16 @@ __device__ __forceinline__ void day_fields(uint4 w, uint32_t f[6])
 // v_sqrt_f32, v_rcp_f32, v_sin/v_cos_f32 which take revolutions).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void normals_f32(uint4 w, float z[5])
+// Standard normals scaled by the noise scale s: the factor enters under the
+// Box-Muller square root, c = -2 ln(2) s^2, so it costs nothing per draw.
+__device__ __forceinline__ void normals_f32(uint4 w, float c, float z[5])
 {
     uint32_t f[6];
     day_fields(w, f);
     float u[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u[k] = ((float)f[k] + 0.5f) * 0x1p-21f;
-    // -2 ln u = -2 ln(2) log2(u)
-    const float c = -1.38629436111989061883f;
+    for (int k = 0; k < 6; ++k) u[k] = fmaf((float)f[k], 0x1p-21f, 0x1p-22f);  // exact
+    // -2 s^2 ln u = c log2(u)
     const float r0 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[0]));
     const float r1 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[2]));
     const float r2 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[4]));
@@ -102,17 +103,24 @@ __device__ __forceinline__ void normals_f32(uint4 w, float z[5])
     z[4] = r2 * __builtin_amdgcn_cosf(u[5]);
 }
 
-// floor(h + sd z) limited to [0, avail]. The float is clamped below 2^31
-// before the conversion, then the integer is limited to avail, so a float
-// rounding of avail can never leak into the count.
+__device__ __forceinline__ float noise_c(float scale)
+{
+    return -1.38629436111989061883f * scale * scale;
+}
+
+// floor(h + sd z) limited to [0, avail] (z already carries the noise scale).
+// For x >= 0 the float->int conversion truncates, which is the floor, and
+// the clamp at 0 absorbs negative x, so no separate floor is needed. The
+// float is limited below 2^31 before the conversion and the integer is then
+// limited to avail, so a float rounding of avail cannot leak into the count.
+// Rates are non-negative, so h >= 0 and sd is finite.
 template <int NOISE>
-__device__ __forceinline__ int32_t draw_f32(float h, float z, int32_t avail, float scale)
+__device__ __forceinline__ int32_t draw_f32(float h, float z, int32_t avail)
 {
     float sd = __builtin_amdgcn_sqrtf(h);
     if (NOISE == 1) sd = __builtin_amdgcn_sqrtf(sd);
-    const float x = fmaf(scale * sd, z, h);
-    float f = floorf(x);
-    f = fminf(fmaxf(f, 0.0f), 2147483520.0f);
+    const float x = fmaf(sd, z, h);
+    const float f = __builtin_amdgcn_fmed3f(x, 0.0f, 2147483520.0f);
     return min((int32_t)f, avail);
 }
 
@@ -126,7 +134,7 @@ __device__ __forceinline__ RatesF rates_f32(const Theta& t)
 }
 
 template <int NOISE>
-__device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float invP, float scale,
+__device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float invP,
                                              const float z[5])
 {
     const float M = (float)(s.A + s.R + s.D);
@@ -134,16 +142,16 @@ __device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float in
     const float g = fmaf(r.al, __builtin_amdgcn_rcpf(1.0f + pw), r.a0);
     const float If = (float)s.I;
     const float Af = (float)s.A;
-    const float h1 = g * (float)s.S * (If * invP);
+    const float h1 = (g * invP) * (float)s.S * If;
     const float h2 = r.ga * If;
     const float h3 = r.be * Af;
     const float h4 = r.de * Af;
     const float h5 = r.bh * If;
-    const int32_t n1 = draw_f32<NOISE>(h1, z[0], s.S, scale);
-    const int32_t n2 = draw_f32<NOISE>(h2, z[1], s.I, scale);
-    const int32_t n3 = draw_f32<NOISE>(h3, z[2], s.A, scale);
-    const int32_t n4 = draw_f32<NOISE>(h4, z[3], s.A - n3, scale);
-    const int32_t n5 = draw_f32<NOISE>(h5, z[4], s.I - n2, scale);
+    const int32_t n1 = draw_f32<NOISE>(h1, z[0], s.S);
+    const int32_t n2 = draw_f32<NOISE>(h2, z[1], s.I);
+    const int32_t n3 = draw_f32<NOISE>(h3, z[2], s.A);
+    const int32_t n4 = draw_f32<NOISE>(h4, z[3], s.A - n3);
+    const int32_t n5 = draw_f32<NOISE>(h5, z[4], s.I - n2);
     s.S -= n1;
     s.I += n1 - n2 - n5;
     s.A += n2 - n3 - n4;
@@ -152,10 +160,11 @@ __device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float in
     s.Ru += n5;
 }
 
-// log1p of a non-negative count: ln(X + 1) = log2(X + 1) ln 2.
-__device__ __forceinline__ float log1p_count_f32(int32_t X)
+// log2(1 + X) of a non-negative count; the float32 distance is accumulated
+// in log2 units and scaled by ln 2 once at the end.
+__device__ __forceinline__ float log2p1_count_f32(int32_t X)
 {
-    return __builtin_amdgcn_logf((float)(X + 1)) * 0.693147180559945309417f;
+    return __builtin_amdgcn_logf((float)(X + 1));
 }
 
 // ---------------------------------------------------------------------------

@@ -35,6 +35,7 @@ struct SimArgs {
     double exit_f64;     // same, double path
     float* dist;
     double* dist64;
+    unsigned long long* days;  // nullable: += sample-days executed
     int32_t* traj;       // record mode: [n][T+1][6]
 };
 
@@ -52,118 +53,349 @@ __device__ __forceinline__ void load_or_draw_theta(const SimArgs& a, bool prior,
 }
 
 // ---------------------------------------------------------------------------
-// float32 simulate + distance
+// float32 simulate + distance with per-wave lane refill
+//
+// Each wavefront owns a fixed set of 64-sample chunks (chunk c = wave id +
+// j * number of waves) and walks through them as a queue. A lane whose
+// sample is finished -- early exit or day T reached -- writes its distance
+// and takes the next queue position at once, so lanes never idle behind the
+// slowest trajectory of the wave. Per-sample constants (rates, I0) are
+// produced 64 at a time by the whole wave into a small per-wave LDS ring,
+// which keeps the prior draw (two Philox calls) out of the divergent refill
+// branch. SPL independent sample slots per lane add instruction-level
+// parallelism. The result of each sample depends only on its index and
+// theta, never on the launch shape or on which lane ran it.
 // ---------------------------------------------------------------------------
-template <int NOISE, int DIST, bool KAHAN, bool PRIOR>
-__global__ __launch_bounds__(SIM_BLOCK) void k_simulate_f32(SimArgs a)
+struct alignas(16) Slot {
+    float a0, al, n, be, ga, de, bh;
+    int32_t i0;
+};
+
+template <bool PRIOR>
+__device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, Slot& out)
 {
-    extern __shared__ float lds_f[];  // [3][T]: log1p(O), or O bits for DIST=1
+    float thv[8];
+    load_or_draw_theta(a, PRIOR, k, a.first + (uint64_t)k, thv);
+    const Theta th = theta_from(thv);
+    const RatesF r = rates_f32(th);
+    const State s0 = init_state(th.ka, a.P, a.A0, a.R0, a.D0);
+    out.a0 = r.a0; out.al = r.al; out.n = r.n; out.be = r.be;
+    out.ga = r.ga; out.de = r.de; out.bh = r.bh; out.i0 = s0.I;
+}
+
+struct Lane {
+    State s;
+    RatesF r;
+    PhiloxDays ph;
+    int64_t k;     // sample offset within the launch
+    int32_t t;     // next day to simulate
+    float acc, comp;
+    bool active;
+};
+
+template <int NOISE, int DIST, bool KAHAN, bool PRIOR, int SPL>
+__global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
+{
+    // 128 entries suffice for any SPL: every slot refill consumes at most 64
+    // positions and is followed by a top-up to 64 ready positions.
+    constexpr int RING = 128;
+    extern __shared__ float lds_f[];
     const int T = a.T;
+    const int obs_words = (3 * T + 3) & ~3;
+    Slot* ring_all = reinterpret_cast<Slot*>(lds_f + obs_words);
+
+    // observed series: log2(1 + O) for the log1p distance (accumulated in
+    // log2 units), or the count itself for the raw distance
     for (int q = threadIdx.x; q < 3 * T; q += blockDim.x) {
         const int32_t O = a.obs[q];
         if (DIST == 0)
-            lds_f[q] = (float)log1p((double)O);
+            lds_f[q] = (float)(log1p((double)O) * 1.44269504088896340736);
         else
             lds_f[q] = __int_as_float(O);
     }
     __syncthreads();
 
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    const uint64_t i = a.first + (uint64_t)k;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    Slot* ring = ring_all + wv * RING;
+    const int64_t wg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t nchunks = (a.n + 63) >> 6;
+    if (wg >= nchunks) return;
+    const int64_t Q = ((nchunks - 1 - wg) / nw + 1) << 6;  // queue positions of this wave
+    auto sample_of = [&](int64_t q) -> int64_t { return ((wg + (q >> 6) * nw) << 6) + (q & 63); };
 
-    float thv[8];
-    load_or_draw_theta(a, PRIOR, k, i, thv);
-    const Theta th = theta_from(thv);
-    const RatesF r = rates_f32(th);
-    State s = init_state(th.ka, a.P, a.A0, a.R0, a.D0);
+    const PhiloxSeries ps = philox_series(a.series, a.key);
     const float invP = 1.0f / (float)a.P;
+    const float nc = noise_c(a.scale);
+    const float dscale = DIST == 0 ? 0.693147180559945309417f : 1.0f;
+    const uint32_t wdom = a.domain << 4;
 
-    float acc = 0.0f, comp = 0.0f;
-    bool exited = false;
-    for (int t = 1; t <= T; ++t) {
-        const uint4 w = stream_words(a.key, i, a.series, ctr_word3((uint32_t)t, a.domain, 0));
-        float z[5];
-        normals_f32(w, z);
-        day_step_f32<NOISE>(s, r, invP, a.scale, z);
-        const int32_t X[3] = {s.A, s.R, s.D};
+    int64_t q_base = 0, p_fill = 0;
+    auto top_up = [&]() {
+        while (p_fill < Q && p_fill - q_base < 64) {
+            const int64_t k = sample_of(p_fill + lane);
+            if (k < a.n) fill_slot<PRIOR>(a, k, ring[(p_fill + lane) & (RING - 1)]);
+            p_fill += 64;
+        }
+    };
+    top_up();
+
+    Lane L[SPL];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float d;
-            if (DIST == 0)
-                d = log1p_count_f32(X[c]) - lds_f[c * T + t - 1];
-            else
-                d = (float)(X[c] - __float_as_int(lds_f[c * T + t - 1]));
-            if (KAHAN) {
-                const float y = d * d - comp;
-                const float tt = acc + y;
-                comp = (tt - acc) - y;
-                acc = tt;
+    for (int j = 0; j < SPL; ++j) L[j].active = false;
+    uint32_t days_done = 0;
+
+    while (true) {
+        // refill every idle slot from the wave queue, in queue order
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+            const bool need = !L[j].active;
+            const uint64_t m = __ballot(need);
+            if (m == 0ull) continue;
+            if (need && q_base < Q) {
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const int64_t q = q_base + rank;
+                const int64_t k = q < Q ? sample_of(q) : a.n;
+                if (k < a.n) {
+                    const Slot sl = ring[q & (RING - 1)];
+                    Lane& l = L[j];
+                    l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
+                    l.s.A = a.A0; l.s.R = a.R0; l.s.D = a.D0; l.s.Ru = 0;
+                    l.s.I = sl.i0;
+                    l.s.S = a.P - (a.A0 + a.R0 + a.D0) - sl.i0;
+                    l.ph.begin(a.first + (uint64_t)k, ps.u0, a.key);
+                    l.k = k;
+                    l.t = 1;
+                    l.acc = 0.0f;
+                    l.comp = 0.0f;
+                    l.active = true;
+                }
+            }
+            q_base += __popcll(m);
+            top_up();
+        }
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) any |= L[j].active;
+        if (__ballot(any) == 0ull) break;
+
+        // one day of every active slot
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+            Lane& l = L[j];
+            if (!l.active) continue;
+            const int t = l.t;
+            const uint4 w = l.ph.day(((uint32_t)t << 8) | wdom, ps.b1, a.key);
+            float z[5];
+            normals_f32(w, nc, z);
+            day_step_f32<NOISE>(l.s, l.r, invP, z);
+            const int32_t X[3] = {l.s.A, l.s.R, l.s.D};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float d;
+                if (DIST == 0)
+                    d = log2p1_count_f32(X[c]) - lds_f[c * T + t - 1];
+                else
+                    d = (float)(X[c] - __float_as_int(lds_f[c * T + t - 1]));
+                if (KAHAN) {
+                    const float y = fmaf(d, d, -l.comp);
+                    const float tt = l.acc + y;
+                    l.comp = (tt - l.acc) - y;
+                    l.acc = tt;
+                } else {
+                    l.acc = fmaf(d, d, l.acc);
+                }
+            }
+            ++days_done;
+            const bool exited = l.acc > a.exit_f32;
+            if (exited || t == T) {
+                const float dd = exited ? INFINITY : sqrtf(l.acc) * dscale;
+                a.dist[l.k] = dd;
+                if (a.dist64) a.dist64[l.k] = (double)dd;
+                l.active = false;
             } else {
-                acc = fmaf(d, d, acc);
+                l.t = t + 1;
             }
         }
-        if (acc > a.exit_f32) {
-            exited = true;
-            break;
-        }
     }
-    const float dd = exited ? INFINITY : sqrtf(acc);
-    a.dist[k] = dd;
-    if (a.dist64) a.dist64[k] = (double)dd;
+    if (a.days) {
+        uint64_t v = days_done;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) atomicAdd(a.days, (unsigned long long)v);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // float64 simulate + distance (precision study, recheck of borderline samples)
 // ---------------------------------------------------------------------------
-template <int NOISE, int DIST, bool PRIOR>
-__global__ __launch_bounds__(SIM_BLOCK) void k_simulate_f64(SimArgs a)
+
+// Observed series for the float64 distance: log1p(O), or O for the raw distance.
+template <int DIST>
+__device__ __forceinline__ void stage_obs_f64(const int32_t* obs, int T, double* lds)
+{
+    for (int q = threadIdx.x; q < 3 * T; q += blockDim.x) {
+        const int32_t O = obs[q];
+        lds[q] = DIST == 0 ? log1p((double)O) : (double)O;
+    }
+}
+
+// One trajectory in float64; returns +INF once the squared distance passes
+// exit_sq.
+template <int NOISE, int DIST>
+__device__ double simulate_one_f64(const float thv[8], uint64_t i, Key key, uint32_t series,
+                                   uint32_t domain, int32_t P, int32_t A0, int32_t R0, int32_t D0,
+                                   int T, double scale, const double* lds, double exit_sq)
 {
 #pragma clang fp contract(off)
-    extern __shared__ double lds_d[];  // [3][T]: log1p(O) or O
-    const int T = a.T;
-    for (int q = threadIdx.x; q < 3 * T; q += blockDim.x) {
-        const int32_t O = a.obs[q];
-        lds_d[q] = DIST == 0 ? log1p((double)O) : (double)O;
-    }
-    __syncthreads();
-
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    const uint64_t i = a.first + (uint64_t)k;
-
-    float thv[8];
-    load_or_draw_theta(a, PRIOR, k, i, thv);
     const Theta th = theta_from(thv);
-    State s = init_state(th.ka, a.P, a.A0, a.R0, a.D0);
-    const double P = (double)a.P;
-    const double scale = (double)a.scale;
-
+    State s = init_state(th.ka, P, A0, R0, D0);
+    const double Pd = (double)P;
     double acc = 0.0;
-    bool exited = false;
     for (int t = 1; t <= T; ++t) {
-        const uint4 w = stream_words(a.key, i, a.series, ctr_word3((uint32_t)t, a.domain, 0));
+        const uint4 w = stream_words(key, i, series, ctr_word3((uint32_t)t, domain, 0));
         double z[5];
         normals_f64(w, z);
-        day_step_f64<NOISE>(s, th, P, scale, z);
+        day_step_f64<NOISE>(s, th, Pd, scale, z);
         const int32_t X[3] = {s.A, s.R, s.D};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double d;
             if (DIST == 0)
-                d = log1p((double)X[c]) - lds_d[c * T + t - 1];
+                d = log1p((double)X[c]) - lds[c * T + t - 1];
             else
-                d = (double)X[c] - lds_d[c * T + t - 1];
+                d = (double)X[c] - lds[c * T + t - 1];
             acc += d * d;
         }
-        if (acc > a.exit_f64) {
-            exited = true;
-            break;
-        }
+        if (acc > exit_sq) return (double)INFINITY;
     }
-    const double dd = exited ? (double)INFINITY : sqrt(acc);
+    return sqrt(acc);
+}
+
+template <int NOISE, int DIST, bool PRIOR>
+__global__ __launch_bounds__(SIM_BLOCK) void k_simulate_f64(SimArgs a)
+{
+    extern __shared__ double lds_d[];  // [3][T]
+    stage_obs_f64<DIST>(a.obs, a.T, lds_d);
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const uint64_t i = a.first + (uint64_t)k;
+    float thv[8];
+    load_or_draw_theta(a, PRIOR, k, i, thv);
+    const double dd = simulate_one_f64<NOISE, DIST>(thv, i, a.key, a.series, a.domain, a.P, a.A0,
+                                                    a.R0, a.D0, a.T, (double)a.scale, lds_d,
+                                                    a.exit_f64);
     a.dist[k] = (float)dd;
     if (a.dist64) a.dist64[k] = dd;
+}
+
+// Float64 decision for the candidates of a float32 pass (compacted at
+// eps (1 + w)): rows whose float32 distance lies above eps (1 - w) are
+// simulated again in float64 and decided by that distance; then the kept
+// rows are compacted in place, in their original order. One workgroup.
+struct RecheckArgs {
+    SimArgs sim;
+    float eps;
+    float band_lo;   // eps (1 - w)
+    float band_hi;   // eps (1 + w)
+    int64_t capacity;
+    int64_t* idx;
+    float* theta;
+    float* dist;
+    float* weight;
+    int64_t* count;
+    uint8_t* keep;   // scratch [capacity]
+    int32_t* rechecked;  // nullable: number of rows simulated in float64
+};
+
+// Pass 1: one lane per candidate row. Workgroups without in-band rows skip
+// the staging of the observed series and only write their keep flags.
+template <int NOISE, int DIST>
+__global__ __launch_bounds__(64) void k_recheck_flags(RecheckArgs r)
+{
+    extern __shared__ double lds_r[];
+    const SimArgs& a = r.sim;
+    const int64_t count = *r.count;
+    if (count > r.capacity) return;  // overflowed candidate set: left for the caller to rerun
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)blockIdx.x * blockDim.x >= count) return;
+    const float d = q < count ? r.dist[q] : INFINITY;
+    const bool band = q < count && d > r.band_lo && d <= r.band_hi;
+    if (__ballot(band) == 0ull) {
+        if (q < count) r.keep[q] = d <= r.eps ? 1 : 0;
+        return;
+    }
+    stage_obs_f64<DIST>(a.obs, a.T, lds_r);
+    __syncthreads();
+    if (q >= count) return;
+    bool keep = d <= r.eps;
+    if (band) {
+        float thv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) thv[j] = r.theta[8 * q + j];
+        const double d64 = simulate_one_f64<NOISE, DIST>(
+            thv, (uint64_t)r.idx[q], a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, a.T,
+            (double)a.scale, lds_r, (double)INFINITY);
+        keep = d64 <= (double)r.eps;
+        r.dist[q] = (float)d64;
+        if (r.rechecked) atomicAdd(r.rechecked, 1);
+    }
+    r.keep[q] = keep ? 1 : 0;
+}
+
+// Pass 2: stable in-place compaction of the kept rows, 256 rows at a time.
+__global__ __launch_bounds__(256) void k_recheck_compact(RecheckArgs r)
+{
+    __shared__ int64_t base_sh;
+    __shared__ int wave_tot[4];
+    const int64_t count = *r.count;
+    if (count > r.capacity) return;
+    if (threadIdx.x == 0) base_sh = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t c0 = 0; c0 < count; c0 += blockDim.x) {
+        const int64_t q = c0 + threadIdx.x;
+        const bool kp = q < count && r.keep[q];
+        int64_t id = 0;
+        float th[8], d = 0.0f, w = 0.0f;
+        if (kp) {
+            id = r.idx[q];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) th[j] = r.theta[8 * q + j];
+            d = r.dist[q];
+            if (r.weight) w = r.weight[q];
+        }
+        const uint64_t m = __ballot(kp);
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_tot[wave] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
+            if (v < wave) off += wave_tot[v];
+            tot += wave_tot[v];
+        }
+        const int64_t dst = base_sh + off + rank;
+        __syncthreads();  // every row of this chunk is in registers before any write
+        if (kp) {
+            r.idx[dst] = id;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r.theta[8 * dst + j] = th[j];
+            r.dist[dst] = d;
+            if (r.weight) r.weight[dst] = w;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) base_sh += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *r.count = base_sh;
+}
+
+__global__ void k_zero_i32(int32_t* p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -188,6 +420,7 @@ __global__ __launch_bounds__(SIM_BLOCK) void k_record(SimArgs a)
     store_state(out, s);
     const RatesF r = rates_f32(th);
     const float invP = 1.0f / (float)a.P;
+    const float nc = noise_c(a.scale);
     for (int t = 1; t <= a.T; ++t) {
         const uint4 w = stream_words(a.key, i, a.series, ctr_word3((uint32_t)t, a.domain, 0));
         if (F64) {
@@ -196,8 +429,8 @@ __global__ __launch_bounds__(SIM_BLOCK) void k_record(SimArgs a)
             day_step_f64<NOISE>(s, th, (double)a.P, (double)a.scale, z);
         } else {
             float z[5];
-            normals_f32(w, z);
-            day_step_f32<NOISE>(s, r, invP, a.scale, z);
+            normals_f32(w, nc, z);
+            day_step_f32<NOISE>(s, r, invP, z);
         }
         store_state(out + 6 * t, s);
     }
@@ -242,15 +475,78 @@ static inline unsigned grid_for(int64_t n) { return (unsigned)((n + SIM_BLOCK - 
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-template <int NOISE, int DIST, bool KAHAN>
-static void launch_f32(const SimArgs& a, bool prior, size_t lds, hipStream_t s)
+// Launch shape of the float32 refill kernel for the calling thread: samples
+// per lane, workgroup size and resident workgroups per CU (0 = default).
+struct LaunchConfig {
+    int spl = 1;
+    int block = 512;
+    int blocks_per_cu = 4;
+};
+static thread_local LaunchConfig g_launch;
+
+// Resident-grid size for the refill kernel: enough workgroups to fill every
+// CU several times over, never more than there are 64-sample chunks.
+static unsigned refill_grid(int64_t n, int block, int blocks_per_cu)
 {
+    static int num_cu = 0;
+    if (num_cu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            num_cu <= 0)
+            num_cu = 256;
+    }
+    const int64_t waves_needed = (n + 63) / 64;
+    const int64_t per_block = block / 64;
+    int64_t g = (int64_t)num_cu * blocks_per_cu;
+    const int64_t need = (waves_needed + per_block - 1) / per_block;
+    if (g > need) g = need;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+static size_t refill_lds_bytes(int T, int block)
+{
+    return sizeof(float) * (size_t)((3 * T + 3) & ~3) + sizeof(Slot) * 128 * (size_t)(block / 64);
+}
+
+static size_t max_lds_per_block()
+{
+    static int bytes = 0;
+    if (bytes == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            bytes <= 0)
+            bytes = 65536;
+    }
+    return (size_t)bytes;
+}
+
+template <int NOISE, int DIST, bool KAHAN, int SPL>
+static void launch_f32_spl(const SimArgs& a, bool prior, hipStream_t s)
+{
+    const int block = g_launch.block;
+    const size_t lds = refill_lds_bytes(a.T, block);
+    const dim3 g(refill_grid(a.n, block, g_launch.blocks_per_cu)), b(block);
     if (prior)
-        hipLaunchKernelGGL((k_simulate_f32<NOISE, DIST, KAHAN, true>), dim3(grid_for(a.n)),
-                           dim3(SIM_BLOCK), lds, s, a);
+        hipLaunchKernelGGL((k_simulate_f32<NOISE, DIST, KAHAN, true, SPL>), g, b, lds, s, a);
     else
-        hipLaunchKernelGGL((k_simulate_f32<NOISE, DIST, KAHAN, false>), dim3(grid_for(a.n)),
-                           dim3(SIM_BLOCK), lds, s, a);
+        hipLaunchKernelGGL((k_simulate_f32<NOISE, DIST, KAHAN, false, SPL>), g, b, lds, s, a);
+}
+
+template <int NOISE, int DIST, bool KAHAN>
+static void launch_f32(const SimArgs& a, bool prior, size_t /*unused*/, hipStream_t s)
+{
+    // several samples per lane only for the paper's model and distance
+    if constexpr (NOISE == 0 && DIST == 0) {
+        switch (g_launch.spl) {
+        case 2: launch_f32_spl<NOISE, DIST, KAHAN, 2>(a, prior, s); return;
+        case 4: launch_f32_spl<NOISE, DIST, KAHAN, 4>(a, prior, s); return;
+        case 8: launch_f32_spl<NOISE, DIST, KAHAN, 8>(a, prior, s); return;
+        default: break;
+        }
+    }
+    launch_f32_spl<NOISE, DIST, KAHAN, 1>(a, prior, s);
 }
 
 template <int NOISE, int DIST>
@@ -292,7 +588,7 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
                                             const abc_stream* st, const float* theta,
                                             const abc_prior* prior, uint64_t first, int64_t n,
                                             float eps_exit, float* dist, double* dist64,
-                                            void* stream)
+                                            unsigned long long* days, void* stream)
 {
     abc_status rc;
     if ((rc = check_series(ser, true))) return rc;
@@ -306,6 +602,8 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
     const bool use_prior = theta == nullptr;
     if (use_prior) {
         if ((rc = prior_lo_width(prior, a.lo, a.width))) return rc;
+        for (int k = 0; k < 8; ++k)
+            ABC_REQUIRE(prior->lo[k] >= 0.0f, "model rates must be non-negative: prior lo[%d] < 0", k);
     } else {
         ABC_REQUIRE(aligned16(theta), "theta must be 16-byte aligned");
     }
@@ -313,10 +611,13 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
     a.theta = theta;
     a.dist = dist;
     a.dist64 = dist64;
+    a.days = days;
     // Early-exit bounds with a relative margin that keeps every exited sample
     // strictly above eps_exit after the final square root and rounding.
     const double e2 = (double)eps_exit * (double)eps_exit;
-    a.exit_f32 = isinf(eps_exit) ? INFINITY : (float)(e2 * (1.0 + 0x1p-18));
+    // the float32 log1p distance accumulates in log2 units: bound / ln(2)^2
+    const double unit = (model->flags & ABC_DIST_RAW) ? 1.0 : 2.08136898100560809980;
+    a.exit_f32 = isinf(eps_exit) ? INFINITY : (float)(e2 * unit * (1.0 + 0x1p-18));
     a.exit_f64 = isinf(eps_exit) ? (double)INFINITY : e2 * (1.0 + 1e-12);
 
     const hipStream_t s = as_stream(stream);
@@ -330,7 +631,10 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
         else launch_f64<1, 1>(a, use_prior, lds, s);
         return check_launch("k_simulate_f64");
     }
-    const size_t lds = sizeof(float) * 3 * (size_t)a.T;
+    const size_t lds = refill_lds_bytes(a.T, g_launch.block);
+    if (lds > max_lds_per_block())
+        return set_error(ABC_EUNSUPPORTED, "T = %d with workgroup size %d needs %zu B of LDS (> %zu)",
+                         a.T, g_launch.block, lds, max_lds_per_block());
     const bool kahan = (model->flags & ABC_KAHAN) != 0;
     if (kahan) {
         if (noise == 0 && distm == 0) launch_f32<0, 0, true>(a, use_prior, lds, s);
@@ -374,4 +678,80 @@ extern "C" abc_status abc_simulate_record(const abc_series* ser, const abc_model
         else hipLaunchKernelGGL((k_record<0, false>), g, b, 0, s, a);
     }
     return check_launch("k_record");
+}
+
+extern "C" abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu)
+{
+    if (spl == 0) spl = 1;
+    if (block == 0) block = 512;
+    if (blocks_per_cu == 0) blocks_per_cu = 4;
+    ABC_REQUIRE(spl == 1 || spl == 2 || spl == 4 || spl == 8, "spl must be 1, 2, 4 or 8");
+    ABC_REQUIRE(block >= 64 && block <= 1024 / spl && block % 64 == 0,
+                "block must be a multiple of 64 in [64, 1024/spl]");
+    ABC_REQUIRE(blocks_per_cu >= 1 && blocks_per_cu <= 64, "blocks_per_cu must be in [1, 64]");
+    g_launch.spl = spl;
+    g_launch.block = block;
+    g_launch.blocks_per_cu = blocks_per_cu;
+    return ABC_OK;
+}
+
+extern "C" abc_status abc_get_launch_config(int32_t* spl, int32_t* block, int32_t* blocks_per_cu)
+{
+    ABC_REQUIRE(spl && block && blocks_per_cu, "NULL output pointer");
+    *spl = g_launch.spl;
+    *block = g_launch.block;
+    *blocks_per_cu = g_launch.blocks_per_cu;
+    return ABC_OK;
+}
+
+extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* model,
+                                       const abc_stream* st, float eps, float band_w,
+                                       int64_t capacity, int64_t* idx, float* theta, float* dist,
+                                       float* weight, int64_t* count, int32_t* rechecked,
+                                       void* stream)
+{
+    abc_status rc;
+    if ((rc = check_series(ser, true))) return rc;
+    if ((rc = check_model(model))) return rc;
+    if ((rc = check_stream_sel(st))) return rc;
+    ABC_REQUIRE(isfinite(eps) && eps >= 0.0f, "eps must be finite and >= 0");
+    ABC_REQUIRE(isfinite(band_w) && band_w >= 0.0f && band_w < 1.0f, "band_w must be in [0, 1)");
+    ABC_REQUIRE(capacity >= 0, "capacity < 0");
+    ABC_REQUIRE(count != nullptr, "count is NULL");
+    if (capacity == 0) return ABC_OK;
+    ABC_REQUIRE(idx && theta && dist, "idx/theta/dist NULL");
+    const size_t lds = sizeof(double) * 3 * (size_t)ser->T;
+    ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 recheck");
+    const hipStream_t s = as_stream(stream);
+    RecheckArgs r{};
+    fill_series(r.sim, ser, model, st, 0, 0);
+    r.eps = eps;
+    r.band_lo = (float)((double)eps * (1.0 - (double)band_w));
+    r.band_hi = (float)((double)eps * (1.0 + (double)band_w));
+    r.capacity = capacity;
+    r.idx = idx;
+    r.theta = theta;
+    r.dist = dist;
+    r.weight = weight;
+    r.count = count;
+    r.rechecked = rechecked;
+    void* scratch = nullptr;
+    ABC_HIP(hipMallocAsync(&scratch, (size_t)capacity, s));
+    r.keep = reinterpret_cast<uint8_t*>(scratch);
+    const int noise = (model->flags & ABC_NOISE_LITERAL) ? 1 : 0;
+    const int distm = (model->flags & ABC_DIST_RAW) ? 1 : 0;
+    if (rechecked) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, rechecked);
+    const dim3 g((unsigned)((capacity + 63) / 64)), b(64);
+    if (noise == 0 && distm == 0) hipLaunchKernelGGL((k_recheck_flags<0, 0>), g, b, lds, s, r);
+    else if (noise == 0) hipLaunchKernelGGL((k_recheck_flags<0, 1>), g, b, lds, s, r);
+    else if (distm == 0) hipLaunchKernelGGL((k_recheck_flags<1, 0>), g, b, lds, s, r);
+    else hipLaunchKernelGGL((k_recheck_flags<1, 1>), g, b, lds, s, r);
+    rc = check_launch("k_recheck_flags");
+    if (rc == ABC_OK) {
+        hipLaunchKernelGGL(k_recheck_compact, dim3(1), dim3(256), 0, s, r);
+    }
+    if (rc == ABC_OK) rc = check_launch("k_recheck_compact");
+    hipError_t e = hipFreeAsync(scratch, s);
+    if (rc == ABC_OK && e != hipSuccess) return set_error(ABC_EHIP, "hipFreeAsync: %s", hipGetErrorString(e));
+    return rc;
 }

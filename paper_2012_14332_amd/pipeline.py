@@ -1,0 +1,94 @@
+"""Host orchestration of the plain rejection-ABC path (Sec. 3.1 / 3.2).
+
+Only control flow lives here -- which entry point of libabc.so runs next,
+on which stream, with which index range. Every step of the computation is a
+HIP kernel behind the C ABI.
+
+One pass over a batch of N prior samples of one series is:
+  1. simulate + distance in float32, theta drawn in-kernel from the prior,
+     early exit at eps (1 + w);
+  2. wavefront-ballot compaction of the candidates d <= eps (1 + w);
+  3. float64 decision of the candidates inside the band (eps (1 - w), eps (1 + w)];
+  4. float64 posterior mean and covariance of the accepted theta.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import abc
+from . import workloads as W
+
+DEFAULT_BAND = 0.02
+
+
+def observed_series(s: W.Series, device="cuda") -> abc.DeviceSeries:
+    """Synthesise the observed A, R, D series of `s`: one float64 model run at
+    theta_true on the observation stream (domain 0, seed s.obs_seed)."""
+    th = torch.tensor(np.asarray(s.theta_true, np.float32)[None], device=device)
+    ser0 = abc.DeviceSeries(s.P, s.T, A0=s.A0, R0=s.R0, D0=s.D0, device=device)
+    traj = abc.simulate_record(ser0, th, s.obs_seed, domain=W.DOMAIN_OBS, series=s.series_id,
+                               flags=abc.ABC_FP64, device=device)
+    obs = traj[0, 1:, 2:5].T.contiguous()
+    return abc.DeviceSeries(s.P, s.T, obs, A0=s.A0, R0=s.R0, D0=s.D0, device=device)
+
+
+def pilot_distances(ser: abc.DeviceSeries, seed: int, n: int, series: int = 0,
+                    first: int = 0) -> np.ndarray:
+    """Float32 distances of a pilot prefix without early exit (host copy)."""
+    return abc.simulate_distance(ser, n, seed, first=first, series=series).cpu().numpy()
+
+
+def pilot_eps(ser: abc.DeviceSeries, seed: int, n: int = 100_000, q: float = 1e-4,
+              series: int = 0) -> float:
+    """Tolerance that a fraction q of a pilot run falls under: the ceil(q n)-th
+    smallest pilot distance."""
+    d = np.sort(pilot_distances(ser, seed, n, series))
+    k = max(1, int(math.ceil(q * n)))
+    return float(d[k - 1])
+
+
+@dataclasses.dataclass
+class PlainResult:
+    idx: torch.Tensor      # [cap] int64, first `count` valid
+    theta: torch.Tensor    # [cap, 8]
+    dist: torch.Tensor     # [cap]
+    count: torch.Tensor    # [1] int64 (device)
+    mean: torch.Tensor     # [8] float64
+    cov: torch.Tensor      # [8, 8] float64
+    rechecked: Optional[torch.Tensor] = None
+
+    def n(self) -> int:
+        return int(self.count.item())
+
+
+class PlainABC:
+    """Reusable buffers for repeated plain-ABC passes over one series."""
+
+    def __init__(self, ser: abc.DeviceSeries, seed: int, eps: float, n: int, *, series: int = 0,
+                 band_w: float = DEFAULT_BAND, capacity: int = 1 << 16, flags: int = 0,
+                 device="cuda"):
+        self.ser, self.seed, self.eps, self.n = ser, int(seed), float(eps), int(n)
+        self.series, self.band_w, self.cap, self.flags = int(series), float(band_w), int(capacity), flags
+        self.dist = torch.empty(self.n, dtype=torch.float32, device=device)
+        self.device = device
+
+    def run(self, first: int, want_rechecked: bool = False) -> PlainResult:
+        eps_hi = self.eps * (1.0 + self.band_w) if self.band_w > 0 else self.eps
+        abc.simulate_distance(self.ser, self.n, self.seed, first=first, series=self.series,
+                              eps_exit=eps_hi, flags=self.flags, out=self.dist,
+                              device=self.device)
+        idx, th, d, _, cnt = abc.accept_compact(self.dist, eps_hi, self.cap, first=first,
+                                                seed=self.seed, series=self.series,
+                                                device=self.device)
+        nre = None
+        if self.band_w > 0:
+            nre = abc.recheck_band(self.ser, self.seed, self.eps, self.band_w, idx, th, d, cnt,
+                                   series=self.series, flags=self.flags,
+                                   want_rechecked=want_rechecked)
+        mean, cov = abc.posterior_moments(th, n_dev=cnt, device=self.device)
+        return PlainResult(idx, th, d, cnt, mean, cov, nre)

@@ -66,7 +66,7 @@ def test_host_validation_rejects_bad_arguments(built):
     ser = abc._Series(1000, 100, 0, 0, 0, None)  # T = 0
     md = abc._Model(1.0, 0)
     rc = L.abc_simulate_distance(ctypes.byref(ser), ctypes.byref(md), ctypes.byref(st), None,
-                                 ctypes.byref(pr), 0, 10, float("inf"), None, None, None)
+                                 ctypes.byref(pr), 0, 10, float("inf"), None, None, None, None)
     assert rc == -1 and b"T = 0" in L.abc_last_error()
     ser = abc._Series(50, 100, 0, 0, 10, None)  # A0 > P
     rc = L.abc_simulate_record(ctypes.byref(ser), ctypes.byref(md), ctypes.byref(st), None, 0,
