@@ -53,6 +53,7 @@ typedef int32_t abc_status;
 #define ABC_EHIP (-2)         /* a HIP runtime call failed */
 #define ABC_ENOMEM (-3)       /* library scratch could not be allocated */
 #define ABC_EUNSUPPORTED (-4) /* option combination not built */
+#define ABC_EOVERFLOW (-5)    /* a result did not fit its buffer, or a quota was not met */
 
 /* Model options (flags of abc_model.flags). */
 #define ABC_FP64 0x1u          /* simulate in double precision (default float32) */
@@ -219,6 +220,62 @@ ABC_API abc_status abc_posterior_moments(const float* theta, const float* weight
  */
 ABC_API abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu);
 ABC_API abc_status abc_get_launch_config(int32_t* spl, int32_t* block, int32_t* blocks_per_cu);
+
+/* One observed series of a batch: as abc_series, plus its tolerance and its
+ * stream series id (counter word 2; give every series of a batch its own). */
+typedef struct {
+    int64_t P;
+    int32_t A0, R0, D0;
+    int32_t T;
+    const int32_t* obs;  /* device [3][T] */
+    float eps;
+    uint32_t series;
+} abc_batch_series;
+
+typedef struct {
+    int64_t rounds;        /* rounds run (graph replays x rounds_per_graph) */
+    int64_t graph_replays;
+    int64_t sample_days;   /* sample-days simulated (after early exits) */
+    int64_t rechecked;     /* candidates decided in float64 */
+    int32_t grid, block, spl, lds_bytes;
+} abc_batch_stats;
+
+/*
+ * Rejection ABC over m observed series of uneven T and P in one persistent
+ * launch per round (Sec. 3.1: repeat until the target number of accepted
+ * samples; Sec. 3.2: accept-reject on the device), until every series has
+ * `quota` accepted samples. Each round hands round_size samples, split evenly,
+ * to the series still below quota; series j consumes its stream indices
+ * 0, 1, 2, ... as a prefix (theta drawn from `prior` on stream (seed, domain,
+ * series[j].series)). The rounds are captured once as a hipGraph
+ * (rounds_per_graph rounds per replay) and replayed; the host checks a
+ * completion flag after each replay. At the end the candidates inside the
+ * band (eps (1 - band_w), eps (1 + band_w)] are decided in float64, and the
+ * first `quota` accepted samples by index are written per series:
+ *   out_idx   device int64 [m][quota]        out_theta device float32 [m][quota][8]
+ *   out_dist  device float32 [m][quota]      out_count device int64 [m] (rows written)
+ *   out_used  device int64 [m] (samples simulated per series)
+ *   out_mean  device float64 [m][8]          out_cov   device float64 [m][8][8]
+ * The result equals the first `quota` indices i with dist_i <= eps of the
+ * plain path. Only the default model (flags = 0, any noise_scale) runs here.
+ * m <= 256; quota <= 4096; the observed series of the batch must fit in LDS
+ * (about 12 B per day of all series together plus the launch shape's ring),
+ * otherwise ABC_EUNSUPPORTED asks to split the batch. max_samples bounds the
+ * samples per series; ABC_EOVERFLOW if some series then still lacks its quota
+ * or produced more candidates (d <= eps (1 + band_w)) than cand_capacity rows
+ * (0 = 4 quota, at most 16384); each round caps a series' share by its
+ * candidate rate so far to stay within half the free capacity. Launch shape: abc_set_launch_config
+ * (spl 1, 2 or 4). Blocks the calling host thread until done; the caller's
+ * stream is ordered before and after the work. stats may be NULL.
+ */
+ABC_API abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
+                                 const abc_prior* prior, const abc_model* model, uint64_t seed,
+                                 uint32_t domain, int32_t quota, int64_t round_size,
+                                 int64_t max_samples, float band_w, int32_t rounds_per_graph,
+                                 int32_t cand_capacity, int64_t* out_idx, float* out_theta,
+                                 float* out_dist,
+                                 int64_t* out_count, int64_t* out_used, double* out_mean,
+                                 double* out_cov, abc_batch_stats* stats, void* stream);
 
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);

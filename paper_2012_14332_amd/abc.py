@@ -48,6 +48,19 @@ class _Model(ctypes.Structure):
     _fields_ = [("noise_scale", ctypes.c_float), ("flags", ctypes.c_uint32)]
 
 
+class _BatchSeries(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("A0", ctypes.c_int32), ("R0", ctypes.c_int32),
+                ("D0", ctypes.c_int32), ("T", ctypes.c_int32), ("obs", ctypes.c_void_p),
+                ("eps", ctypes.c_float), ("series", ctypes.c_uint32)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
+                ("sample_days", ctypes.c_int64), ("rechecked", ctypes.c_int64),
+                ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("spl", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -74,6 +87,11 @@ def lib():
         L.abc_recheck_band.argtypes = [P(_Series), P(_Model), P(_Stream), f32, f32, i64, vp, vp,
                                        vp, vp, vp, vp, vp]
         L.abc_recheck_band.restype = ctypes.c_int32
+        L.abc_batch_run.argtypes = [P(_BatchSeries), ctypes.c_int32, P(_Prior), P(_Model), u64,
+                                    ctypes.c_uint32, ctypes.c_int32, i64, i64, f32,
+                                    ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                    P(_BatchStats), vp]
+        L.abc_batch_run.restype = ctypes.c_int32
         L.abc_set_launch_config.argtypes = [ctypes.c_int32] * 3
         L.abc_set_launch_config.restype = ctypes.c_int32
         L.abc_get_launch_config.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
@@ -231,6 +249,44 @@ def get_launch_config():
     v = [ctypes.c_int32() for _ in range(3)]
     _check(lib().abc_get_launch_config(*[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
+
+
+def batch_run(sers, eps, seed: int, quota: int, *, series_ids=None, round_size: int = 1 << 22,
+              max_samples: int = 1 << 40, band_w: float = 0.02, rounds_per_graph: int = 4,
+              domain: int = 1, noise_scale: float = 1.0, prior: Optional[_Prior] = None,
+              cand_capacity: int = 0, device="cuda", check: bool = True):
+    """Batched persistent ABC over DeviceSeries `sers` with tolerances `eps` until each has
+    `quota` accepted samples. Returns a dict of device tensors and the run statistics."""
+    m = len(sers)
+    ids = list(range(m)) if series_ids is None else list(series_ids)
+    arr = (_BatchSeries * m)()
+    for j, (ser, e) in enumerate(zip(sers, eps)):
+        arr[j] = _BatchSeries(ser.P, ser.A0, ser.R0, ser.D0, ser.T, ser.obs.data_ptr(), float(e),
+                              int(ids[j]))
+    out = {
+        "idx": torch.full((m, quota), -1, dtype=torch.int64, device=device),
+        "theta": torch.zeros((m, quota, 8), dtype=torch.float32, device=device),
+        "dist": torch.zeros((m, quota), dtype=torch.float32, device=device),
+        "count": torch.zeros(m, dtype=torch.int64, device=device),
+        "used": torch.zeros(m, dtype=torch.int64, device=device),
+        "mean": torch.zeros((m, 8), dtype=torch.float64, device=device),
+        "cov": torch.zeros((m, 8, 8), dtype=torch.float64, device=device),
+    }
+    st = _BatchStats()
+    pr = prior or make_prior()
+    md = _Model(float(noise_scale), 0)
+    rc = lib().abc_batch_run(arr, m, ctypes.byref(pr), ctypes.byref(md), int(seed), int(domain),
+                             int(quota), int(round_size), int(max_samples), float(band_w),
+                             int(rounds_per_graph), int(cand_capacity), _dptr(out["idx"]),
+                             _dptr(out["theta"]),
+                             _dptr(out["dist"]), _dptr(out["count"]), _dptr(out["used"]),
+                             _dptr(out["mean"]), _dptr(out["cov"]), ctypes.byref(st),
+                             _stream_handle())
+    out["status"] = rc
+    out["stats"] = {k: getattr(st, k) for k, _ in _BatchStats._fields_}
+    if check:
+        _check(rc)
+    return out
 
 
 def version() -> str:

@@ -1,0 +1,785 @@
+// Batched persistent rejection ABC over many observed series of uneven
+// length and population (Sec. 3.1 "iterate until the required number of
+// accepted samples"), run as hipGraph-captured rounds, and its C-ABI entry
+// point abc_batch_run.
+//
+// Round structure (all on the device, captured once, replayed):
+//   k_batch_plan   one workgroup: series whose certain-accept count is below
+//                  the quota share the round's samples evenly; each gets the
+//                  next contiguous index range of its own stream.
+//   k_batch_round  persistent grid: every wavefront walks a fixed share of
+//                  the round's 64-sample chunks with lane refill. Lanes carry
+//                  their own series (T, P, tolerance, stream words), and the
+//                  observed series of the whole batch sit in LDS, so a lane
+//                  never waits for the rest of its wave to change series.
+//                  A finished sample with d <= eps (1 + w) is appended to its
+//                  series' candidate list; d <= eps (1 - w) also counts as a
+//                  certain accept.
+// Because each series consumes its indices as a prefix, the first Q
+// accepted samples by index are exact once Q certain accepts exist: the
+// finalisation decides the band candidates in float64, sorts by index and
+// keeps the first Q. The outcome does not depend on the launch shape.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "common.hpp"
+#include "model.hpp"
+
+namespace abc {
+
+constexpr int BT_MAX_SERIES = 256;
+constexpr int BT_RING = 64;  // ring slots per wave (one chunk)
+
+struct SeriesDesc {         // device, per series, constant over the run
+    int32_t T, P, A0, R0, D0;
+    int32_t obs_off;        // offset of [3][T] log2(1 + O) floats in the obs table
+    int32_t room;           // P - A0 - R0 - D0
+    uint32_t series_id;     // stream series (counter word 2)
+    float invP;
+    float exit2;            // early-exit bound on the log2-unit sum
+    float eps_hi, eps_lo, eps;
+    uint32_t u0, b1;        // wave-uniform Philox words of this series
+    uint32_t pad;
+};
+
+struct SeriesState {        // device, per series, updated every round
+    int64_t next;           // next sample index of the stream
+    int32_t certain;        // accepts with d <= eps (1 - w) so far
+    int32_t cand;           // candidates with d <= eps (1 + w) so far (may exceed capacity)
+};
+
+struct RoundTable {
+    int32_t n_active;
+    int32_t total_chunks;
+    int32_t done;
+    int32_t pad;
+    int32_t s[BT_MAX_SERIES];
+    int32_t n[BT_MAX_SERIES];
+    int32_t chunk0[BT_MAX_SERIES + 1];
+    int64_t first[BT_MAX_SERIES];
+};
+
+struct BatchArgs {
+    int32_t m;
+    int32_t quota;
+    int64_t round_size;
+    int64_t max_samples;    // per series
+    int32_t cand_cap;       // candidate rows per series
+    int32_t obs_words;      // floats in the obs table
+    Key key;
+    uint32_t domain;
+    float lo[8], width[8];
+    const SeriesDesc* desc;
+    SeriesState* state;
+    RoundTable* table;
+    const float* obs_table; // [obs_words]
+    int64_t* cand_idx;      // [m][cand_cap]
+    float* cand_dist;       // [m][cand_cap]
+    int32_t* flag_dev;      // 1 once no series needs more samples
+    unsigned long long* days;
+    float nc;               // -2 ln(2) s^2 of the Box-Muller radius
+    float scale;
+};
+
+// ----------------------------------------------------------------------------
+// setup: log2(1 + O) table of all series
+// ----------------------------------------------------------------------------
+__global__ void k_batch_obs(const int32_t* const* obs, const SeriesDesc* desc, int m, float* table)
+{
+    const int s = blockIdx.x;
+    if (s >= m) return;
+    const SeriesDesc d = desc[s];
+    for (int q = threadIdx.x; q < 3 * d.T; q += blockDim.x)
+        table[d.obs_off + q] = (float)(log1p((double)obs[s][q]) * 1.44269504088896340736);
+}
+
+__global__ void k_batch_init(BatchArgs a)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < a.m) {
+        a.state[s].next = 0;
+        a.state[s].certain = 0;
+        a.state[s].cand = 0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// plan of one round (one workgroup of 256 threads, one series per thread)
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
+{
+    __shared__ int wave_cnt[BT_MAX_SERIES / 64];
+    __shared__ int chunk_wave[BT_MAX_SERIES / 64];
+    const int s = threadIdx.x;
+    const int lane = s & 63, wave = s >> 6;
+    bool active = false;
+    int64_t next = 0;
+    if (s < a.m) {
+        next = a.state[s].next;
+        active = a.state[s].certain < a.quota && next < a.max_samples;
+    }
+    const uint64_t bal = __ballot(active);
+    const int rank_w = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0, n_active = 0;
+    for (int w = 0; w < BT_MAX_SERIES / 64; ++w) {
+        if (w < wave) before += wave_cnt[w];
+        n_active += wave_cnt[w];
+    }
+    const int rank = before + rank_w;
+    int64_t n_s = 0;
+    if (active) {
+        const int64_t per = a.round_size / n_active;
+        const int64_t rem = a.round_size % n_active;
+        n_s = per + (rank < rem ? 1 : 0);
+        if (n_s > a.max_samples - next) n_s = a.max_samples - next;
+        // keep the expected new candidates within half the free capacity,
+        // from the candidate rate seen so far (the schedule never changes
+        // which samples are accepted, only how many rounds it takes)
+        const int64_t cand = a.state[s].cand;
+        if (next > 0) {
+            const int64_t room = (int64_t)a.cand_cap - cand;
+            int64_t lim = room > 0 ? room * next / (2 * (cand + 1)) : 0;
+            if (lim < 64) lim = 64;
+            if (n_s > lim) n_s = lim;
+        }
+    }
+    const int chunks = (int)((n_s + 63) / 64);
+    // exclusive scan of chunk counts in series order
+    int incl = chunks;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) chunk_wave[wave] = incl;
+    __syncthreads();
+    int cbase = 0, ctot = 0;
+    for (int w = 0; w < BT_MAX_SERIES / 64; ++w) {
+        if (w < wave) cbase += chunk_wave[w];
+        ctot += chunk_wave[w];
+    }
+    const int c0 = cbase + incl - chunks;
+    RoundTable* t = a.table;
+    if (active) {
+        t->s[rank] = s;
+        t->n[rank] = (int32_t)n_s;
+        t->first[rank] = next;
+        t->chunk0[rank] = c0;
+        a.state[s].next = next + n_s;
+    }
+    if (s == 0) {
+        t->n_active = n_active;
+        t->total_chunks = ctot;
+        t->chunk0[n_active] = ctot;
+        t->done = n_active == 0 ? 1 : 0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// one round: persistent grid with lane refill and per-lane series
+// ----------------------------------------------------------------------------
+struct alignas(16) BSlot {
+    float a0, al, n, be, ga, de, bh;
+    int32_t i0;
+    int32_t series;         // index into desc, -1 = no sample
+    int32_t pad;
+    int64_t i;              // sample index
+};
+
+struct BLane {
+    State s;
+    RatesF r;
+    PhiloxDays ph;
+    int64_t i;
+    int32_t t, T, obs_off, series;
+    float invP, exit2;
+    uint32_t b1;
+    float acc;
+    bool active;
+};
+
+template <int SPL>
+__global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
+{
+    extern __shared__ float lds_b[];
+    __shared__ RoundTable tab_sh;  // copied once per workgroup
+    const int nwaves_blk = blockDim.x >> 6;
+    SeriesDesc* desc_sh = reinterpret_cast<SeriesDesc*>(lds_b);
+    float* obs_sh = reinterpret_cast<float*>(desc_sh + a.m);
+    BSlot* ring_all = reinterpret_cast<BSlot*>(obs_sh + ((a.obs_words + 3) & ~3));
+
+    // stage the round table, series descriptors and observed series
+    {
+        const int32_t* src = reinterpret_cast<const int32_t*>(a.table);
+        int32_t* dst = reinterpret_cast<int32_t*>(&tab_sh);
+        for (int q = threadIdx.x; q < (int)(sizeof(RoundTable) / 4); q += blockDim.x) dst[q] = src[q];
+        const int32_t* dsrc = reinterpret_cast<const int32_t*>(a.desc);
+        int32_t* ddst = reinterpret_cast<int32_t*>(desc_sh);
+        for (int q = threadIdx.x; q < a.m * (int)(sizeof(SeriesDesc) / 4); q += blockDim.x)
+            ddst[q] = dsrc[q];
+        for (int q = threadIdx.x; q < a.obs_words; q += blockDim.x) obs_sh[q] = a.obs_table[q];
+    }
+    __syncthreads();
+    const int C = tab_sh.total_chunks;
+    const int na = tab_sh.n_active;
+    if (C == 0) return;
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    BSlot* ring = ring_all + wv * BT_RING;
+    const int64_t wg = (int64_t)blockIdx.x * nwaves_blk + wv;
+    const int64_t nw = (int64_t)gridDim.x * nwaves_blk;
+    if (wg >= C) return;
+    const int64_t J = (C - 1 - wg) / nw + 1;  // chunks of this wave
+    const int64_t Q = J << 6;
+
+    // fill the ring with chunk j of this wave (all 64 lanes, one sample each)
+    auto fill = [&](int64_t j) {
+        const int c = (int)(wg + j * nw);
+        int lo = 0, hi = na - 1;  // the active slot r with chunk0[r] <= c < chunk0[r+1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab_sh.chunk0[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        const int r = lo;
+        const int s = tab_sh.s[r];
+        const int64_t local = (int64_t)(c - tab_sh.chunk0[r]) * 64 + lane;
+        BSlot sl;
+        if (local < tab_sh.n[r]) {
+            const SeriesDesc& d = desc_sh[s];
+            const int64_t i = tab_sh.first[r] + local;
+            float th[8];
+            prior_draw(a.key, (uint64_t)i, d.series_id, a.domain, a.lo, a.width, th);
+            const Theta tt = theta_from(th);
+            const RatesF rr = rates_f32(tt);
+            const State s0 = init_state(tt.ka, d.P, d.A0, d.R0, d.D0);
+            sl.a0 = rr.a0; sl.al = rr.al; sl.n = rr.n; sl.be = rr.be;
+            sl.ga = rr.ga; sl.de = rr.de; sl.bh = rr.bh; sl.i0 = s0.I;
+            sl.series = s;
+            sl.i = i;
+        } else {
+            sl.series = -1;
+            sl.i = 0;
+        }
+        sl.pad = 0;
+        ring[lane] = sl;
+    };
+
+    int64_t q_base = 0;      // next queue position
+    int64_t filled_j = -1;   // chunk currently in the ring
+    BLane L[SPL];
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) L[k].active = false;
+    uint32_t days_done = 0;
+
+    while (true) {
+        // refill every idle slot from the wave queue, in queue order; the ring
+        // holds one chunk, so a refill may span the end of one chunk and the
+        // start of the next
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            uint64_t m = __ballot(!L[k].active);
+            while (m != 0ull && q_base < Q) {
+                const int64_t j = q_base >> 6;
+                if (j != filled_j) {
+                    fill(j);
+                    filled_j = j;
+                }
+                const int avail = 64 - (int)(q_base & 63);
+                const bool inm = (m >> lane) & 1ull;
+                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                const bool take = inm && rank < avail;
+                if (take) {
+                    const BSlot sl = ring[(q_base & 63) + rank];
+                    if (sl.series >= 0) {
+                        const SeriesDesc& d = desc_sh[sl.series];
+                        BLane& l = L[k];
+                        l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
+                        l.s.A = d.A0; l.s.R = d.R0; l.s.D = d.D0; l.s.Ru = 0;
+                        l.s.I = sl.i0;
+                        l.s.S = d.room - sl.i0;
+                        l.ph.begin((uint64_t)sl.i, d.u0, a.key);
+                        l.i = sl.i;
+                        l.t = 1;
+                        l.T = d.T;
+                        l.obs_off = d.obs_off;
+                        l.series = sl.series;
+                        l.invP = d.invP;
+                        l.exit2 = d.exit2;
+                        l.b1 = d.b1;
+                        l.acc = 0.0f;
+                        l.active = true;
+                    }
+                }
+                const int cnt = __popcll(m);
+                q_base += cnt < avail ? cnt : avail;
+                m = __ballot(inm && !take);  // lanes still without a position
+            }
+        }
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) any |= L[k].active;
+        // a refill can land every idle lane on the unused tail of a series'
+        // last chunk; the wave ends only when the queue is exhausted too
+        if (__ballot(any) == 0ull && q_base >= Q) break;
+
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            BLane& l = L[k];
+            if (!l.active) continue;
+            const int t = l.t;
+            const uint4 w = l.ph.day(((uint32_t)t << 8) | (a.domain << 4), l.b1, a.key);
+            float z[5];
+            normals_f32(w, a.nc, z);
+            day_step_f32<0>(l.s, l.r, l.invP, z);
+            const int32_t X[3] = {l.s.A, l.s.R, l.s.D};
+            const float* ob = obs_sh + l.obs_off + t - 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float d = log2p1_count_f32(X[c]) - ob[c * l.T];
+                l.acc = fmaf(d, d, l.acc);
+            }
+            ++days_done;
+            const bool exited = l.acc > l.exit2;
+            if (exited || t == l.T) {
+                if (!exited) {
+                    const float dd = sqrtf(l.acc) * 0.693147180559945309417f;
+                    const SeriesDesc& ds = desc_sh[l.series];
+                    if (dd <= ds.eps_hi) {
+                        const int pos = atomicAdd(&a.state[l.series].cand, 1);
+                        if (pos < a.cand_cap) {
+                            a.cand_idx[(int64_t)l.series * a.cand_cap + pos] = l.i;
+                            a.cand_dist[(int64_t)l.series * a.cand_cap + pos] = dd;
+                        }
+                        if (dd <= ds.eps_lo) atomicAdd(&a.state[l.series].certain, 1);
+                    }
+                }
+                l.active = false;
+            } else {
+                l.t = t + 1;
+            }
+        }
+    }
+    if (a.days) {
+        uint64_t v = days_done;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) atomicAdd(a.days, (unsigned long long)v);
+    }
+}
+
+// 1 once every series has its quota of certain accepts or used its maximum
+__global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_flag(BatchArgs a)
+{
+    __shared__ int open;
+    if (threadIdx.x == 0) open = 0;
+    __syncthreads();
+    const int s = threadIdx.x;
+    if (s < a.m && a.state[s].certain < a.quota && a.state[s].next < a.max_samples)
+        atomicAdd(&open, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) *a.flag_dev = open == 0 ? 1 : 0;
+}
+
+// ----------------------------------------------------------------------------
+// finalisation: one workgroup per series
+// ----------------------------------------------------------------------------
+struct FinalArgs {
+    BatchArgs b;
+    const int32_t* const* obs;  // raw observed counts per series (float64 decision)
+    float band_w;
+    int64_t* out_idx;    // [m][quota]
+    float* out_theta;    // [m][quota][8]
+    float* out_dist;     // [m][quota]
+    int64_t* out_count;  // [m]
+    int64_t* out_used;   // [m] samples consumed
+    int32_t* out_rechecked;
+};
+
+// bitonic sort of (idx, dist) pairs in LDS, ascending by idx
+__device__ void bitonic_sort(int64_t* key, float* val, int n_pow2)
+{
+    for (int k = 2; k <= n_pow2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n_pow2; t += blockDim.x) {
+                const int p = t ^ j;
+                if (p > t) {
+                    const bool up = (t & k) == 0;
+                    const int64_t a = key[t], b = key[p];
+                    if ((a > b) == up) {
+                        key[t] = b; key[p] = a;
+                        const float v = val[t]; val[t] = val[p]; val[p] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
+{
+    extern __shared__ unsigned char lds_f8[];
+    const BatchArgs& a = f.b;
+    const int s = blockIdx.x;
+    const SeriesDesc d = a.desc[s];
+    const int cand = a.state[s].cand;
+    int n = cand < a.cand_cap ? cand : a.cand_cap;
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    int64_t* key = reinterpret_cast<int64_t*>(lds_f8);
+    float* val = reinterpret_cast<float*>(key + npow);
+    double* obs64 = reinterpret_cast<double*>(val + npow + (npow & 1));
+    __shared__ int nkeep;
+    __shared__ int nre;
+    if (threadIdx.x == 0) { nkeep = 0; nre = 0; }
+    for (int q = threadIdx.x; q < 3 * d.T; q += blockDim.x) obs64[q] = log1p((double)f.obs[s][q]);
+    __syncthreads();
+    // float64 decision inside the band; rejected rows get idx = INT64_MAX
+    for (int q = threadIdx.x; q < npow; q += blockDim.x) {
+        int64_t k = INT64_MAX;
+        float v = INFINITY;
+        if (q < n) {
+            k = a.cand_idx[(int64_t)s * a.cand_cap + q];
+            v = a.cand_dist[(int64_t)s * a.cand_cap + q];
+            if (v > d.eps_lo) {
+                float th[8];
+                prior_draw(a.key, (uint64_t)k, d.series_id, a.domain, a.lo, a.width, th);
+                const double d64 = simulate_one_f64<0, 0>(th, (uint64_t)k, a.key, d.series_id,
+                                                          a.domain, d.P, d.A0, d.R0, d.D0, d.T,
+                                                          (double)a.scale, obs64,
+                                                          (double)INFINITY);
+                v = (float)d64;
+                if (!(d64 <= (double)d.eps)) k = INT64_MAX;
+                atomicAdd(&nre, 1);
+            }
+        }
+        key[q] = k;
+        val[q] = v;
+    }
+    __syncthreads();
+    bitonic_sort(key, val, npow);
+    for (int q = threadIdx.x; q < npow && q < a.quota; q += blockDim.x) {
+        if (key[q] != INT64_MAX) {
+            f.out_idx[(int64_t)s * a.quota + q] = key[q];
+            f.out_dist[(int64_t)s * a.quota + q] = val[q];
+            float th[8];
+            prior_draw(a.key, (uint64_t)key[q], d.series_id, a.domain, a.lo, a.width, th);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) f.out_theta[((int64_t)s * a.quota + q) * 8 + j] = th[j];
+            atomicAdd(&nkeep, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        f.out_count[s] = cand > a.cand_cap ? -(int64_t)cand : (int64_t)nkeep;
+        f.out_used[s] = a.state[s].next;
+        if (f.out_rechecked) f.out_rechecked[s] = nre;
+    }
+}
+
+// Float64 mean and covariance of each series' accepted theta: one workgroup
+// per series, two passes (mean, then centred products), fixed reduction order.
+__device__ double block_sum_f64(double v, double* red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_batch_moments(const float* theta, const int64_t* count,
+                                                       int quota, double* mean, double* cov)
+{
+    __shared__ double red[4];
+    const int s = blockIdx.x;
+    const int64_t n = count[s] > 0 ? (count[s] < quota ? count[s] : quota) : 0;
+    const float* th = theta + (int64_t)s * quota * 8;
+    double mu[8];
+    for (int j = 0; j < 8; ++j) {
+        double v = 0.0;
+        for (int64_t r = threadIdx.x; r < n; r += blockDim.x) v += (double)th[8 * r + j];
+        mu[j] = block_sum_f64(v, red) / (double)n;
+    }
+    for (int j = 0; j < 8; ++j)
+        for (int l = j; l < 8; ++l) {
+            double v = 0.0;
+            for (int64_t r = threadIdx.x; r < n; r += blockDim.x)
+                v += ((double)th[8 * r + j] - mu[j]) * ((double)th[8 * r + l] - mu[l]);
+            const double c = block_sum_f64(v, red) / (double)(n - 1);
+            if (threadIdx.x == 0) {
+                cov[(int64_t)s * 64 + 8 * j + l] = c;
+                cov[(int64_t)s * 64 + 8 * l + j] = c;
+            }
+        }
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 8; ++j) mean[(int64_t)s * 8 + j] = n > 0 ? mu[j] : NAN;
+}
+
+static size_t batch_lds_bytes(int m, int obs_words, int block)
+{
+    return sizeof(SeriesDesc) * (size_t)m + sizeof(float) * (size_t)((obs_words + 3) & ~3) +
+           sizeof(BSlot) * BT_RING * (size_t)(block / 64);
+}
+
+}  // namespace abc
+
+using namespace abc;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+template <int SPL>
+void launch_round(const BatchArgs& a, unsigned grid, int block, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch_round<SPL>), dim3(grid), dim3(block), lds, s, a);
+}
+
+}  // namespace
+
+extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
+                                    const abc_prior* prior, const abc_model* model,
+                                    uint64_t seed, uint32_t domain, int32_t quota,
+                                    int64_t round_size, int64_t max_samples, float band_w,
+                                    int32_t rounds_per_graph, int32_t cand_capacity,
+                                    int64_t* out_idx,
+                                    float* out_theta, float* out_dist, int64_t* out_count,
+                                    int64_t* out_used, double* out_mean, double* out_cov,
+                                    abc_batch_stats* stats, void* stream)
+{
+    abc_status rc;
+    ABC_REQUIRE(series != nullptr && m >= 1 && m <= BT_MAX_SERIES, "need 1 <= m <= %d series", BT_MAX_SERIES);
+    if ((rc = check_model(model))) return rc;
+    ABC_REQUIRE((model->flags & (ABC_FP64 | ABC_KAHAN | ABC_NOISE_LITERAL | ABC_DIST_RAW)) == 0,
+                "the batched path runs the default model in float32 (flags must be 0)");
+    ABC_REQUIRE(domain <= 15u, "domain > 15");
+    ABC_REQUIRE(quota >= 1 && quota <= 4096, "quota must be in [1, 4096]");
+    ABC_REQUIRE(round_size >= 64, "round_size < 64");
+    ABC_REQUIRE(max_samples >= 1, "max_samples < 1");
+    ABC_REQUIRE(isfinite(band_w) && band_w >= 0.0f && band_w < 1.0f, "band_w must be in [0, 1)");
+    ABC_REQUIRE(rounds_per_graph >= 1 && rounds_per_graph <= 64, "rounds_per_graph in [1, 64]");
+    ABC_REQUIRE(out_idx && out_theta && out_dist && out_count && out_used && out_mean && out_cov,
+                "NULL output pointer");
+    float lo[8], width[8];
+    if ((rc = prior_lo_width(prior, lo, width))) return rc;
+    for (int k = 0; k < 8; ++k) ABC_REQUIRE(prior->lo[k] >= 0.0f, "prior lo[%d] < 0", k);
+
+    // host-side series descriptors
+    std::vector<SeriesDesc> desc(m);
+    std::vector<const int32_t*> obs_ptr(m);
+    int obs_words = 0, maxT = 0;
+    const Key key = make_key(seed);
+    for (int s = 0; s < m; ++s) {
+        const abc_batch_series& b = series[s];
+        abc_series ser{b.P, b.A0, b.R0, b.D0, b.T, b.obs};
+        if ((rc = check_series(&ser, true))) return set_error(rc, "series %d: %s", s, abc_last_error());
+        ABC_REQUIRE(isfinite(b.eps) && b.eps >= 0.0f, "series %d: eps must be finite and >= 0", s);
+        SeriesDesc& d = desc[s];
+        d.T = b.T; d.P = (int32_t)b.P; d.A0 = b.A0; d.R0 = b.R0; d.D0 = b.D0;
+        d.obs_off = obs_words;
+        d.room = (int32_t)b.P - (b.A0 + b.R0 + b.D0);
+        d.series_id = b.series;
+        d.invP = 1.0f / (float)b.P;
+        const double hi = (double)b.eps * (1.0 + (double)band_w);
+        d.eps_hi = (float)hi;
+        d.eps_lo = (float)((double)b.eps * (1.0 - (double)band_w));
+        d.eps = b.eps;
+        d.exit2 = (float)(hi * hi * 2.08136898100560809980 * (1.0 + 0x1p-18));
+        const uint64_t p1 = (uint64_t)PH_M1 * (uint64_t)b.series;
+        d.u0 = (uint32_t)(p1 >> 32) ^ key.k0;
+        d.b1 = (uint32_t)p1 ^ (key.k0 + PH_W0);
+        d.pad = 0;
+        obs_words += 3 * b.T;
+        obs_ptr[s] = b.obs;
+        if (b.T > maxT) maxT = b.T;
+    }
+    int32_t spl = 1, block = 512, bpc = 4;
+    abc_get_launch_config(&spl, &block, &bpc);
+    const size_t lds = batch_lds_bytes(m, obs_words, block);
+    int dev = 0, num_cu = 0, max_lds = 0;
+    ABC_HIP(hipGetDevice(&dev));
+    ABC_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    ABC_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t static_lds = sizeof(RoundTable);
+    if (lds + static_lds > (size_t)max_lds)
+        return set_error(ABC_EUNSUPPORTED,
+                         "batch needs %zu B of LDS per workgroup (> %d): split the series into groups",
+                         lds + static_lds, max_lds);
+    const int per_cu = (int)(163840 / (lds + static_lds));
+    const unsigned grid = (unsigned)num_cu * (unsigned)(per_cu < bpc ? (per_cu > 0 ? per_cu : 1) : bpc);
+    ABC_REQUIRE(cand_capacity == 0 || (cand_capacity >= quota && cand_capacity <= 16384),
+                "cand_capacity must be 0 (4 quota) or in [quota, 16384]");
+    const int cand_cap = cand_capacity ? cand_capacity : 4 * quota;
+
+    // device buffers (freed on return)
+    DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days;
+    ABC_HIP(hipMalloc(&b_desc.p, sizeof(SeriesDesc) * m));
+    ABC_HIP(hipMalloc(&b_state.p, sizeof(SeriesState) * m));
+    ABC_HIP(hipMalloc(&b_table.p, sizeof(RoundTable)));
+    ABC_HIP(hipMalloc(&b_obs.p, sizeof(float) * (size_t)obs_words));
+    ABC_HIP(hipMalloc(&b_ptrs.p, sizeof(const int32_t*) * m));
+    ABC_HIP(hipMalloc(&b_cidx.p, sizeof(int64_t) * (size_t)m * cand_cap));
+    ABC_HIP(hipMalloc(&b_cdist.p, sizeof(float) * (size_t)m * cand_cap));
+    ABC_HIP(hipMalloc(&b_flag.p, sizeof(int32_t)));
+    ABC_HIP(hipMalloc(&b_days.p, sizeof(unsigned long long)));
+    int32_t* flag_host = nullptr;
+    ABC_HIP(hipHostMalloc((void**)&flag_host, sizeof(int32_t), hipHostMallocDefault));
+    struct HostFree {
+        int32_t* p;
+        ~HostFree() { if (p) (void)hipHostFree(p); }
+    } host_free{flag_host};
+
+    hipStream_t user = as_stream(stream);
+    hipStream_t s;
+    ABC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct StreamFree {
+        hipStream_t s;
+        ~StreamFree() { (void)hipStreamDestroy(s); }
+    } stream_free{s};
+    hipEvent_t ev;
+    ABC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    struct EventFree {
+        hipEvent_t e;
+        ~EventFree() { (void)hipEventDestroy(e); }
+    } event_free{ev};
+    ABC_HIP(hipEventRecord(ev, user));
+    ABC_HIP(hipStreamWaitEvent(s, ev, 0));
+
+    ABC_HIP(hipMemcpyAsync(b_desc.p, desc.data(), sizeof(SeriesDesc) * m, hipMemcpyHostToDevice, s));
+    ABC_HIP(hipMemcpyAsync(b_ptrs.p, obs_ptr.data(), sizeof(const int32_t*) * m, hipMemcpyHostToDevice, s));
+    ABC_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope with this call
+
+    BatchArgs a{};
+    a.m = m;
+    a.quota = quota;
+    a.round_size = round_size;
+    a.max_samples = max_samples;
+    a.cand_cap = cand_cap;
+    a.obs_words = obs_words;
+    a.key = key;
+    a.domain = domain;
+    for (int k = 0; k < 8; ++k) { a.lo[k] = lo[k]; a.width[k] = width[k]; }
+    a.desc = reinterpret_cast<const SeriesDesc*>(b_desc.p);
+    a.state = reinterpret_cast<SeriesState*>(b_state.p);
+    a.table = reinterpret_cast<RoundTable*>(b_table.p);
+    a.obs_table = reinterpret_cast<const float*>(b_obs.p);
+    a.cand_idx = reinterpret_cast<int64_t*>(b_cidx.p);
+    a.cand_dist = reinterpret_cast<float*>(b_cdist.p);
+    a.flag_dev = reinterpret_cast<int32_t*>(b_flag.p);
+    a.days = reinterpret_cast<unsigned long long*>(b_days.p);
+    a.nc = -1.38629436111989061883f * model->noise_scale * model->noise_scale;
+    a.scale = model->noise_scale;
+
+    hipLaunchKernelGGL(k_batch_obs, dim3(m), dim3(256), 0, s,
+                       reinterpret_cast<const int32_t* const*>(b_ptrs.p), a.desc, m,
+                       reinterpret_cast<float*>(b_obs.p));
+    hipLaunchKernelGGL(k_batch_init, dim3((m + 255) / 256), dim3(256), 0, s, a);
+    if ((rc = check_launch("k_batch setup"))) return rc;
+    ABC_HIP(hipMemsetAsync(b_days.p, 0, sizeof(unsigned long long), s));
+
+    // capture rounds_per_graph rounds + the completion flag copy
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ABC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < rounds_per_graph; ++r) {
+        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(BT_MAX_SERIES), 0, s, a);
+        switch (spl) {
+        case 2: launch_round<2>(a, grid, block, lds, s); break;
+        case 4: launch_round<4>(a, grid, block, lds, s); break;
+        default: launch_round<1>(a, grid, block, lds, s); break;
+        }
+    }
+    hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(BT_MAX_SERIES), 0, s, a);
+    (void)hipMemcpyAsync(flag_host, a.flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (ce != hipSuccess) return set_error(ABC_EHIP, "graph capture: %s", hipGetErrorString(ce));
+    struct GraphFree {
+        hipGraph_t g;
+        hipGraphExec_t e;
+        ~GraphFree() {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } graph_free{graph, nullptr};
+    ABC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    graph_free.e = exec;
+
+    const int64_t max_replays =
+        (max_samples * (int64_t)m + round_size - 1) / round_size / rounds_per_graph + 2;
+    int64_t replays = 0;
+    *flag_host = 0;
+    while (replays < max_replays) {
+        ABC_HIP(hipGraphLaunch(exec, s));
+        ABC_HIP(hipStreamSynchronize(s));
+        ++replays;
+        if (*flag_host) break;
+    }
+
+    FinalArgs f{};
+    f.b = a;
+    f.obs = reinterpret_cast<const int32_t* const*>(b_ptrs.p);
+    f.band_w = band_w;
+    f.out_idx = out_idx;
+    f.out_theta = out_theta;
+    f.out_dist = out_dist;
+    f.out_count = out_count;
+    f.out_used = out_used;
+    DevBuf b_re;
+    ABC_HIP(hipMalloc(&b_re.p, sizeof(int32_t) * m));
+    f.out_rechecked = reinterpret_cast<int32_t*>(b_re.p);
+    int npow = 1;
+    while (npow < cand_cap) npow <<= 1;
+    const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + sizeof(double) * 3 * maxT + 16;
+    ABC_REQUIRE(lds_f <= (size_t)max_lds, "quota too large for the finalisation");
+    hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(256), lds_f, s, f);
+    hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, out_count, quota,
+                       out_mean, out_cov);
+    if ((rc = check_launch("k_batch finalisation"))) return rc;
+    std::vector<int32_t> rech(m);
+    unsigned long long days = 0;
+    ABC_HIP(hipMemcpyAsync(rech.data(), b_re.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    ABC_HIP(hipMemcpyAsync(&days, b_days.p, sizeof(days), hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> cnt(m);
+    ABC_HIP(hipMemcpyAsync(cnt.data(), out_count, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+    ABC_HIP(hipStreamSynchronize(s));
+    ABC_HIP(hipEventRecord(ev, s));
+    ABC_HIP(hipStreamWaitEvent(user, ev, 0));
+    if (stats) {
+        stats->rounds = replays * rounds_per_graph;
+        stats->graph_replays = replays;
+        stats->sample_days = (int64_t)days;
+        int64_t re = 0;
+        for (int s2 = 0; s2 < m; ++s2) re += rech[s2];
+        stats->rechecked = re;
+        stats->grid = (int32_t)grid;
+        stats->block = block;
+        stats->spl = spl;
+        stats->lds_bytes = (int32_t)(lds + static_lds);
+    }
+    for (int s2 = 0; s2 < m; ++s2) {
+        if (cnt[s2] < 0)
+            return set_error(ABC_EOVERFLOW, "series %d: %lld candidates exceed the capacity %d",
+                             s2, (long long)-cnt[s2], cand_cap);
+        if (cnt[s2] < quota)
+            return set_error(ABC_EOVERFLOW, "series %d: %lld of %d accepted within max_samples",
+                             s2, (long long)cnt[s2], quota);
+    }
+    if (!*flag_host)
+        return set_error(ABC_EOVERFLOW, "stopped after %lld graph replays before every quota was met",
+                         (long long)replays);
+    return ABC_OK;
+}

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
         bool any = false;
 #pragma unroll
         for (int j = 0; j < SPL; ++j) any |= L[j].active;
-        if (__ballot(any) == 0ull) break;
+        if (__ballot(any) == 0ull && q_base >= Q) break;
 
         // one day of every active slot
 #pragma unroll
@@ -231,48 +231,6 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
 // ---------------------------------------------------------------------------
 // float64 simulate + distance (precision study, recheck of borderline samples)
 // ---------------------------------------------------------------------------
-
-// Observed series for the float64 distance: log1p(O), or O for the raw distance.
-template <int DIST>
-__device__ __forceinline__ void stage_obs_f64(const int32_t* obs, int T, double* lds)
-{
-    for (int q = threadIdx.x; q < 3 * T; q += blockDim.x) {
-        const int32_t O = obs[q];
-        lds[q] = DIST == 0 ? log1p((double)O) : (double)O;
-    }
-}
-
-// One trajectory in float64; returns +INF once the squared distance passes
-// exit_sq.
-template <int NOISE, int DIST>
-__device__ double simulate_one_f64(const float thv[8], uint64_t i, Key key, uint32_t series,
-                                   uint32_t domain, int32_t P, int32_t A0, int32_t R0, int32_t D0,
-                                   int T, double scale, const double* lds, double exit_sq)
-{
-#pragma clang fp contract(off)
-    const Theta th = theta_from(thv);
-    State s = init_state(th.ka, P, A0, R0, D0);
-    const double Pd = (double)P;
-    double acc = 0.0;
-    for (int t = 1; t <= T; ++t) {
-        const uint4 w = stream_words(key, i, series, ctr_word3((uint32_t)t, domain, 0));
-        double z[5];
-        normals_f64(w, z);
-        day_step_f64<NOISE>(s, th, Pd, scale, z);
-        const int32_t X[3] = {s.A, s.R, s.D};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double d;
-            if (DIST == 0)
-                d = log1p((double)X[c]) - lds[c * T + t - 1];
-            else
-                d = (double)X[c] - lds[c * T + t - 1];
-            acc += d * d;
-        }
-        if (acc > exit_sq) return (double)INFINITY;
-    }
-    return sqrt(acc);
-}
 
 template <int NOISE, int DIST, bool PRIOR>
 __global__ __launch_bounds__(SIM_BLOCK) void k_simulate_f64(SimArgs a)

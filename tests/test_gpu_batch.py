@@ -1,0 +1,113 @@
+"""Batched persistent path (many uneven series, hipGraph rounds, per-series
+quota) against the oracle's rule: for series j, the first Q sample indices i
+of its stream with dist_i <= eps_j, in index order.
+
+Also: the result does not depend on the round size, the rounds per graph
+replay or the launch shape, and equals the plain path on the same prefix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2012_14332_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TIE = 1e-5
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_14332_amd import abc, pipeline
+
+    abc.lib()
+    yield abc, pipeline
+    abc.set_launch_config(0, 0, 0)
+
+
+def _setup(env, m, q):
+    abc, P = env
+    ss = W.uneven_series(64, 5)[:m]
+    sers = [P.observed_series(s) for s in ss]
+    eps = [P.pilot_eps(ser, 9, n=20000, q=q, series=j) for j, ser in enumerate(sers)]
+    return ss, sers, eps
+
+
+def _oracle_first(s, j, eps, used, quota):
+    m = oracle.make_model(s.P, s.T)
+    obs = oracle.observe(m, s.theta_true, s.obs_seed, series=s.series_id)
+    d = oracle.distances(m, obs, seed=9, n=used, series=j)
+    return d, oracle.first_accepted(d, eps, quota)
+
+
+def test_batch_matches_oracle_first_quota(env):
+    abc, _ = env
+    ss, sers, eps = _setup(env, 16, 5e-3)
+    quota = 40
+    out = abc.batch_run(sers, eps, 9, quota, round_size=1 << 16)
+    cnt = out["count"].cpu().numpy()
+    used = out["used"].cpu().numpy()
+    idx = out["idx"].cpu().numpy()
+    assert np.all(cnt == quota), cnt
+    for j, s in enumerate(ss):
+        d, want = _oracle_first(s, j, eps[j], int(used[j]), quota)
+        got = idx[j]
+        if not np.array_equal(got, want):
+            diff = set(got.tolist()) ^ set(want.tolist())
+            assert all(abs(d[i] - eps[j]) < TIE * eps[j] for i in diff if i < len(d)), (j, diff)
+        th = oracle.prior(1, seed=9, series=j, first=int(got[0]))[0]
+        np.testing.assert_array_equal(out["theta"][j, 0].cpu().numpy(), th)
+    st = out["stats"]
+    assert st["rounds"] >= 1 and st["sample_days"] > 0
+
+
+def test_batch_independent_of_round_size_and_launch(env):
+    abc, _ = env
+    ss, sers, eps = _setup(env, 12, 1e-2)
+    ref = abc.batch_run(sers, eps, 9, 30, round_size=1 << 15, rounds_per_graph=1,
+                        cand_capacity=4096)
+    ref_idx = ref["idx"].cpu().numpy()
+    for rs, rpg, cfg in [(1 << 17, 4, (1, 512, 4)), (1 << 16, 8, (2, 256, 4)), (50_000, 2, (4, 128, 2)),
+                         (1 << 20, 1, (1, 1024, 1))]:
+        abc.set_launch_config(*cfg)
+        o = abc.batch_run(sers, eps, 9, 30, round_size=rs, rounds_per_graph=rpg,
+                          cand_capacity=4096)
+        np.testing.assert_array_equal(o["idx"].cpu().numpy(), ref_idx, err_msg=str((rs, rpg, cfg)))
+        np.testing.assert_array_equal(o["theta"].cpu().numpy(), ref["theta"].cpu().numpy())
+        np.testing.assert_array_equal(o["dist"].cpu().numpy(), ref["dist"].cpu().numpy())
+        np.testing.assert_allclose(o["mean"].cpu().numpy(), ref["mean"].cpu().numpy(), rtol=1e-13)
+    abc.set_launch_config(0, 0, 0)
+
+
+def test_batch_equals_plain_path(env):
+    abc, P = env
+    ss, sers, eps = _setup(env, 6, 1e-2)
+    quota = 25
+    o = abc.batch_run(sers, eps, 9, quota, round_size=1 << 15)
+    for j, ser in enumerate(sers):
+        used = int(o["used"][j].item())
+        run = P.PlainABC(ser, 9, eps[j], used, series=j, band_w=0.02, capacity=1 << 14)
+        r = run.run(0)
+        c = r.n()
+        assert c >= quota
+        np.testing.assert_array_equal(o["idx"][j].cpu().numpy(), r.idx[:quota].cpu().numpy())
+        rm, rc = oracle.moments(r.theta[:quota].cpu().numpy())
+        np.testing.assert_allclose(o["mean"][j].cpu().numpy(), rm, rtol=1e-12)
+        np.testing.assert_allclose(o["cov"][j].cpu().numpy(), rc, rtol=1e-9, atol=1e-12)
+
+
+def test_batch_limits(env):
+    abc, _ = env
+    ss, sers, eps = _setup(env, 4, 1e-3)
+    o = abc.batch_run(sers, eps, 9, 50, round_size=1 << 12, max_samples=5000, check=False)
+    assert o["status"] == -5  # quota not reachable within max_samples
+    assert np.all(o["used"].cpu().numpy() <= 5000)
+    assert np.all(o["count"].cpu().numpy() < 50)
+    with pytest.raises(abc.AbcError):
+        abc.batch_run(sers, eps, 9, 0)
+    # a capacity below what one round produces is reported, never overrun
+    o = abc.batch_run(sers, [e * 3 for e in eps], 9, 20, round_size=1 << 18, cand_capacity=20,
+                      check=False)
+    assert o["status"] == -5
