@@ -88,6 +88,58 @@ def cpu_baseline(countries, eps, first, n_sample):
     }
 
 
+def batched_leg(args):
+    """The 64-uneven-series workload: one persistent hipGraph-captured launch per
+    round of 2^22 samples until every series has 1000 accepted samples, launch
+    shape from the autotuner."""
+    import numpy as np
+    import torch
+
+    from paper_2012_14332_amd import abc, autotune
+    from paper_2012_14332_amd import pipeline as PL
+    from paper_2012_14332_amd import workloads as W
+
+    ss = W.uneven_series(64, 5)
+    sers = [PL.observed_series(s) for s in ss]
+    eps = [PL.pilot_eps(ser, 2, n=args.pilot, q=args.q, series=j) for j, ser in enumerate(sers)]
+    tune = autotune.tune_batch(sers, eps, seed=2, quota=args.quota, round_size=1 << 22,
+                               use_cache=False)
+    runs = []
+    for rep in range(args.batch_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = abc.batch_run(sers, eps, 2, args.quota, round_size=1 << 22, rounds_per_graph=4,
+                          cand_capacity=4 * args.quota)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0, o))
+    wall, o = min(runs, key=lambda r: r[0])
+    st = o["stats"]
+    acc = int(o["count"].sum().item())
+    used = int(o["used"].sum().item())
+    nominal = int(sum(int(o["used"][j].item()) * s.T for j, s in enumerate(ss)))
+    return {
+        "workload": "64 synthetic series, T uniform in [30,200], P log-uniform in [1e5,1e9], "
+                    "theta_true from the prior (seed 5); eps_j = 1e-4 pilot quantile; rounds of "
+                    "2^22 samples until every series has %d accepted" % args.quota,
+        "accepted_per_s": acc / wall,
+        "wall_s": wall,
+        "accepted": acc,
+        "samples": used,
+        "trajectories_per_s": used / wall,
+        "sim_days_per_s_effective": st["sample_days"] / wall,
+        "sim_days_per_s_nominal": nominal / wall,
+        "rounds": st["rounds"],
+        "graph_replays": st["graph_replays"],
+        "rounds_ms": st["rounds_ms"],
+        "rechecked_fp64": st["rechecked"],
+        "launch_shape": [st["spl"], st["block"], st["grid"]],
+        "lds_bytes": st["lds_bytes"],
+        "autotune_best_ms_per_round": tune["ms_per_round"],
+        "autotune_top": tune["table"][:5],
+        "reps": [round(r[0], 4) for r in runs],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +152,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="spl,block,blocks_per_cu")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--quota", type=int, default=1000)
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (scales HBM byte counters)")
     args = ap.parse_args()
@@ -236,6 +291,8 @@ def main():
         },
         "per_country": per_country,
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
     print(json.dumps(out))

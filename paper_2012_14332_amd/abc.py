@@ -58,7 +58,7 @@ class _BatchStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
                 ("sample_days", ctypes.c_int64), ("rechecked", ctypes.c_int64),
                 ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("spl", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("rounds_ms", ctypes.c_float)]
 
 
 _lib = None

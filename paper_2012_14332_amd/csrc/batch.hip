@@ -186,9 +186,10 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
 struct alignas(16) BSlot {
     float a0, al, n, be, ga, de, bh;
     int32_t i0;
-    int32_t series;         // index into desc, -1 = no sample
+    uint32_t c1base, g3, h3, f3;  // per-sample part of Philox rounds 1-3
+    int64_t i;                    // sample index
+    int32_t series;               // index into desc, -1 = no sample
     int32_t pad;
-    int64_t i;              // sample index
 };
 
 struct BLane {
@@ -260,6 +261,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
             const State s0 = init_state(tt.ka, d.P, d.A0, d.R0, d.D0);
             sl.a0 = rr.a0; sl.al = rr.al; sl.n = rr.n; sl.be = rr.be;
             sl.ga = rr.ga; sl.de = rr.de; sl.bh = rr.bh; sl.i0 = s0.I;
+            PhiloxDays ph;
+            ph.begin((uint64_t)i, d.u0, a.key);
+            sl.c1base = ph.c1base; sl.g3 = ph.g3; sl.h3 = ph.h3; sl.f3 = ph.f3;
             sl.series = s;
             sl.i = i;
         } else {
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                         l.s.A = d.A0; l.s.R = d.R0; l.s.D = d.D0; l.s.Ru = 0;
                         l.s.I = sl.i0;
                         l.s.S = d.room - sl.i0;
-                        l.ph.begin((uint64_t)sl.i, d.u0, a.key);
+                        l.ph.c1base = sl.c1base; l.ph.g3 = sl.g3; l.ph.h3 = sl.h3; l.ph.f3 = sl.f3;
                         l.i = sl.i;
                         l.t = 1;
                         l.T = d.T;
@@ -619,11 +623,22 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
         return set_error(ABC_EUNSUPPORTED,
                          "batch needs %zu B of LDS per workgroup (> %d): split the series into groups",
                          lds + static_lds, max_lds);
+    {
+        int np = 1;
+        while (np < (cand_capacity ? cand_capacity : 4 * quota)) np <<= 1;
+        const size_t lds_final = sizeof(int64_t) * np + sizeof(float) * (np + 1) +
+                                 sizeof(double) * 3 * (size_t)maxT + 16;
+        if (lds_final > (size_t)max_lds)
+            return set_error(ABC_EINVAL, "cand_capacity %d needs %zu B of LDS to sort (> %d)",
+                             cand_capacity ? cand_capacity : 4 * quota, lds_final, max_lds);
+    }
     const int per_cu = (int)(163840 / (lds + static_lds));
     const unsigned grid = (unsigned)num_cu * (unsigned)(per_cu < bpc ? (per_cu > 0 ? per_cu : 1) : bpc);
     ABC_REQUIRE(cand_capacity == 0 || (cand_capacity >= quota && cand_capacity <= 16384),
                 "cand_capacity must be 0 (4 quota) or in [quota, 16384]");
     const int cand_cap = cand_capacity ? cand_capacity : 4 * quota;
+    int npow_cap = 1;
+    while (npow_cap < cand_cap) npow_cap <<= 1;
 
     // device buffers (freed on return)
     DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days;
@@ -722,12 +737,24 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
         (max_samples * (int64_t)m + round_size - 1) / round_size / rounds_per_graph + 2;
     int64_t replays = 0;
     *flag_host = 0;
+    hipEvent_t t0, t1;
+    ABC_HIP(hipEventCreate(&t0));
+    ABC_HIP(hipEventCreate(&t1));
+    struct TimerFree {
+        hipEvent_t a, b;
+        ~TimerFree() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } timer_free{t0, t1};
+    ABC_HIP(hipEventRecord(t0, s));
     while (replays < max_replays) {
         ABC_HIP(hipGraphLaunch(exec, s));
         ABC_HIP(hipStreamSynchronize(s));
         ++replays;
         if (*flag_host) break;
     }
+    ABC_HIP(hipEventRecord(t1, s));
+    ABC_HIP(hipEventSynchronize(t1));
+    float rounds_ms = 0.0f;
+    ABC_HIP(hipEventElapsedTime(&rounds_ms, t0, t1));
 
     FinalArgs f{};
     f.b = a;
@@ -741,8 +768,7 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     DevBuf b_re;
     ABC_HIP(hipMalloc(&b_re.p, sizeof(int32_t) * m));
     f.out_rechecked = reinterpret_cast<int32_t*>(b_re.p);
-    int npow = 1;
-    while (npow < cand_cap) npow <<= 1;
+    const int npow = npow_cap;
     const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + sizeof(double) * 3 * maxT + 16;
     ABC_REQUIRE(lds_f <= (size_t)max_lds, "quota too large for the finalisation");
     hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(256), lds_f, s, f);
@@ -769,6 +795,7 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
         stats->block = block;
         stats->spl = spl;
         stats->lds_bytes = (int32_t)(lds + static_lds);
+        stats->rounds_ms = rounds_ms;
     }
     for (int s2 = 0; s2 < m; ++s2) {
         if (cnt[s2] < 0)

@@ -66,21 +66,31 @@ __device__ __forceinline__ void load_or_draw_theta(const SimArgs& a, bool prior,
 // parallelism. The result of each sample depends only on its index and
 // theta, never on the launch shape or on which lane ran it.
 // ---------------------------------------------------------------------------
+// Everything a lane needs to start a sample, prepared by the whole wave so the
+// divergent refill branch only copies 64 bytes out of LDS.
 struct alignas(16) Slot {
     float a0, al, n, be, ga, de, bh;
     int32_t i0;
+    uint32_t c1base, g3, h3, f3;  // per-sample part of Philox rounds 1-3
+    int64_t k;                    // sample offset in the launch (n = no sample)
+    int64_t pad;
 };
 
 template <bool PRIOR>
-__device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, Slot& out)
+__device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, uint32_t u0, Slot& out)
 {
     float thv[8];
     load_or_draw_theta(a, PRIOR, k, a.first + (uint64_t)k, thv);
     const Theta th = theta_from(thv);
     const RatesF r = rates_f32(th);
     const State s0 = init_state(th.ka, a.P, a.A0, a.R0, a.D0);
+    PhiloxDays ph;
+    ph.begin(a.first + (uint64_t)k, u0, a.key);
     out.a0 = r.a0; out.al = r.al; out.n = r.n; out.be = r.be;
     out.ga = r.ga; out.de = r.de; out.bh = r.bh; out.i0 = s0.I;
+    out.c1base = ph.c1base; out.g3 = ph.g3; out.h3 = ph.h3; out.f3 = ph.f3;
+    out.k = k;
+    out.pad = 0;
 }
 
 struct Lane {
@@ -96,9 +106,7 @@ struct Lane {
 template <int NOISE, int DIST, bool KAHAN, bool PRIOR, int SPL>
 __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
 {
-    // 128 entries suffice for any SPL: every slot refill consumes at most 64
-    // positions and is followed by a top-up to 64 ready positions.
-    constexpr int RING = 128;
+    constexpr int RING = 64;  // one chunk of 64 queue positions
     extern __shared__ float lds_f[];
     const int T = a.T;
     const int obs_words = (3 * T + 3) & ~3;
@@ -123,7 +131,6 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     const int64_t nchunks = (a.n + 63) >> 6;
     if (wg >= nchunks) return;
     const int64_t Q = ((nchunks - 1 - wg) / nw + 1) << 6;  // queue positions of this wave
-    auto sample_of = [&](int64_t q) -> int64_t { return ((wg + (q >> 6) * nw) << 6) + (q & 63); };
 
     const PhiloxSeries ps = philox_series(a.series, a.key);
     const float invP = 1.0f / (float)a.P;
@@ -131,50 +138,59 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     const float dscale = DIST == 0 ? 0.693147180559945309417f : 1.0f;
     const uint32_t wdom = a.domain << 4;
 
-    int64_t q_base = 0, p_fill = 0;
-    auto top_up = [&]() {
-        while (p_fill < Q && p_fill - q_base < 64) {
-            const int64_t k = sample_of(p_fill + lane);
-            if (k < a.n) fill_slot<PRIOR>(a, k, ring[(p_fill + lane) & (RING - 1)]);
-            p_fill += 64;
-        }
+    // the ring holds chunk j of this wave: sample offsets (wg + j nw) 64 + lane
+    auto fill = [&](int64_t j) {
+        const int64_t k = ((wg + j * nw) << 6) + lane;
+        Slot& sl = ring[lane];
+        if (k < a.n)
+            fill_slot<PRIOR>(a, k, ps.u0, sl);
+        else
+            sl.k = a.n;
     };
-    top_up();
 
+    int64_t q_base = 0;
+    int64_t filled_j = -1;
     Lane L[SPL];
 #pragma unroll
     for (int j = 0; j < SPL; ++j) L[j].active = false;
     uint32_t days_done = 0;
 
     while (true) {
-        // refill every idle slot from the wave queue, in queue order
+        // refill every idle slot from the wave queue, in queue order; a refill
+        // may span the end of one chunk and the start of the next
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
-            const bool need = !L[j].active;
-            const uint64_t m = __ballot(need);
-            if (m == 0ull) continue;
-            if (need && q_base < Q) {
-                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                const int64_t q = q_base + rank;
-                const int64_t k = q < Q ? sample_of(q) : a.n;
-                if (k < a.n) {
-                    const Slot sl = ring[q & (RING - 1)];
-                    Lane& l = L[j];
-                    l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
-                    l.s.A = a.A0; l.s.R = a.R0; l.s.D = a.D0; l.s.Ru = 0;
-                    l.s.I = sl.i0;
-                    l.s.S = a.P - (a.A0 + a.R0 + a.D0) - sl.i0;
-                    l.ph.begin(a.first + (uint64_t)k, ps.u0, a.key);
-                    l.k = k;
-                    l.t = 1;
-                    l.acc = 0.0f;
-                    l.comp = 0.0f;
-                    l.active = true;
+            uint64_t m = __ballot(!L[j].active);
+            while (m != 0ull && q_base < Q) {
+                const int64_t jc = q_base >> 6;
+                if (jc != filled_j) {
+                    fill(jc);
+                    filled_j = jc;
                 }
+                const int avail = 64 - (int)(q_base & 63);
+                const bool inm = (m >> lane) & 1ull;
+                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                const bool take = inm && rank < avail;
+                if (take) {
+                    const Slot sl = ring[(q_base & 63) + rank];
+                    if (sl.k < a.n) {
+                        Lane& l = L[j];
+                        l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
+                        l.s.A = a.A0; l.s.R = a.R0; l.s.D = a.D0; l.s.Ru = 0;
+                        l.s.I = sl.i0;
+                        l.s.S = a.P - (a.A0 + a.R0 + a.D0) - sl.i0;
+                        l.ph.c1base = sl.c1base; l.ph.g3 = sl.g3; l.ph.h3 = sl.h3; l.ph.f3 = sl.f3;
+                        l.k = sl.k;
+                        l.t = 1;
+                        l.acc = 0.0f;
+                        l.comp = 0.0f;
+                        l.active = true;
+                    }
+                }
+                const int cnt = __popcll(m);
+                q_base += cnt < avail ? cnt : avail;
+                m = __ballot(inm && !take);  // lanes still without a position
             }
-            q_base += __popcll(m);
-            top_up();
         }
         bool any = false;
 #pragma unroll
@@ -464,7 +480,7 @@ static unsigned refill_grid(int64_t n, int block, int blocks_per_cu)
 
 static size_t refill_lds_bytes(int T, int block)
 {
-    return sizeof(float) * (size_t)((3 * T + 3) & ~3) + sizeof(Slot) * 128 * (size_t)(block / 64);
+    return sizeof(float) * (size_t)((3 * T + 3) & ~3) + sizeof(Slot) * 64 * (size_t)(block / 64);
 }
 
 static size_t max_lds_per_block()
