@@ -279,6 +279,98 @@ ABC_API abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
                                  int64_t* out_count, int64_t* out_used, double* out_mean,
                                  double* out_cov, abc_batch_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal (not in the paper, whose proposal is the prior): a
+ * mixture-density network q(theta | x) trained on (theta, x) pairs that the
+ * simulator itself produces, used as an importance-sampling proposal for
+ * rejection ABC at the same eps. x = log1p(A, R, D) at 32 evenly spaced days
+ * d_k = 1 + rint(k (T - 1) / 31), k = 0..31 (96 float32, A block first),
+ * standardised per feature; theta standardised by the prior's mean and sd.
+ * Network 96 -> 256 -> 256 -> 136 (exact-erf GELU), output = 8 logits,
+ * 8x8 means, 8x8 log sd (clamped to [-7, 3]) of a diagonal Gaussian mixture.
+ * Products in bfloat16 on MFMA with float32 accumulation; parameters, loss,
+ * gradients and Adam in float32. The handle owns all device memory.
+ * ------------------------------------------------------------------------ */
+typedef struct abc_mdn abc_mdn;
+
+/* Number of float32 parameters: W1 [96][256], b1 [256], W2 [256][256], b2,
+ * W3 [256][136], b3 [136], in this order, W stored [fan_in][fan_out]. */
+ABC_API int64_t abc_mdn_param_count(void);
+
+/* Create a network for the prior box `prior` (host) with weights drawn
+ * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from stream (init_seed, domain 3),
+ * biases 0, feature standardisation mean 0 / sd 1. Synchronises the device. */
+ABC_API abc_status abc_mdn_create(const abc_prior* prior, uint64_t init_seed, abc_mdn** out);
+ABC_API abc_status abc_mdn_destroy(abc_mdn* net);
+
+/* Device pointers (owned by the net) to the float32 parameters and to the
+ * gradient of the last abc_mdn_loss_grad / training step, both
+ * [abc_mdn_param_count()]. After writing parameters, call abc_mdn_sync_params. */
+ABC_API abc_status abc_mdn_params(abc_mdn* net, float** params, float** grads);
+ABC_API abc_status abc_mdn_sync_params(abc_mdn* net, void* stream);
+/* Copy the float32 parameters in from / out to a device buffer
+ * [param_count] (set also refreshes the bfloat16 copies). */
+ABC_API abc_status abc_mdn_set_params(abc_mdn* net, const float* src, void* stream);
+ABC_API abc_status abc_mdn_get_params(const abc_mdn* net, float* dst, void* stream);
+/* Copy out the feature standardisation (device float32 [96] each). */
+ABC_API abc_status abc_mdn_get_standardizer(const abc_mdn* net, float* mean96, float* sd96,
+                                            void* stream);
+
+/* Training pairs: for samples first..first+n-1 of stream (seed, domain,
+ * series): theta from `prior` (blocks 0-1 of day 0, as abc_sample_prior);
+ * T = T_lo + floor(u (T_hi - T_lo + 1)) and P = rint(10^(log10P_lo + u'
+ * (log10P_hi - log10P_lo))) from block 2 of day 0 (u, u' from its first two
+ * words as in the theta draw); A0 active at day 0, R0 = D0 = 0; the float32
+ * model of abc_simulate_distance on the same stream; features as above,
+ * unstandardised. Outputs device: features [n][96], theta [n][8], TP [n][2]
+ * (T, P; nullable). */
+ABC_API abc_status abc_mdn_simulate_features(const abc_prior* prior, uint64_t seed,
+                                             uint32_t domain, uint32_t series, uint64_t first,
+                                             int64_t n, int32_t T_lo, int32_t T_hi,
+                                             double log10P_lo, double log10P_hi, int32_t A0,
+                                             float* features, float* theta, int32_t* TP,
+                                             void* stream);
+
+/* The 96 unstandardised features of an observed series (ser->obs device). */
+ABC_API abc_status abc_series_features(const abc_series* ser, float* out96, void* stream);
+
+/* Per-feature mean and sd (float64 two-pass, sd floored at 1e-6) of
+ * features [n][96] (device), kept in the net for every later call. */
+ABC_API abc_status abc_mdn_fit_standardizer(abc_mdn* net, const float* features, int64_t n,
+                                            void* stream);
+
+/* Network outputs [n][136] (device, float32) for unstandardised features [n][96]. */
+ABC_API abc_status abc_mdn_forward(abc_mdn* net, const float* features, int64_t n, float* out,
+                                   void* stream);
+
+/* Mean negative log-likelihood of theta [n][8] (original units) under the
+ * network's mixture for features [n][96], and its gradient w.r.t. the float32
+ * parameters (device float32 loss scalar and grad [param_count], nullable). */
+ABC_API abc_status abc_mdn_loss_grad(abc_mdn* net, const float* features, const float* theta,
+                                     int64_t n, float* loss, float* grad, void* stream);
+
+/* Adam (beta 0.9, 0.999, eps 1e-8, learning rate lr) on the mean NLL over
+ * `epochs` passes of n pairs in batches of `batch` (floor(n / batch) steps per
+ * epoch; epoch e visits row (a_e j + c_e) mod n, with (a_e, c_e) from
+ * shuffle_seed). One training step is captured once as a hipGraph and
+ * replayed. loss_log (device float32 [steps], nullable) receives each step's
+ * batch loss; steps_out and train_ms (host, nullable) the step count and the
+ * GPU time of the replays. Blocks the host until done. */
+ABC_API abc_status abc_mdn_train(abc_mdn* net, const float* features, const float* theta,
+                                 int64_t n, int32_t epochs, int32_t batch, float lr,
+                                 uint64_t shuffle_seed, float* loss_log, int64_t* steps_out,
+                                 float* train_ms, void* stream);
+
+/* Proposal draws for samples first..first+n-1 of stream st: with probability
+ * lambda theta ~ prior, otherwise from the mixture given by `mix` (device,
+ * one network output row [136]); draws outside the prior box are redrawn.
+ * weight = prior(theta) / q(theta) with q = (1 - lambda) q_mix + lambda prior
+ * (the truncation constant cancels in self-normalised weights). Outputs
+ * device theta [n][8], weight [n]. */
+ABC_API abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float lambda,
+                                  const abc_stream* st, uint64_t first, int64_t n, float* theta,
+                                  float* weight, void* stream);
+
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);
 

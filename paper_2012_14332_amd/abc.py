@@ -92,6 +92,28 @@ def lib():
                                     ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                     P(_BatchStats), vp]
         L.abc_batch_run.restype = ctypes.c_int32
+        L.abc_mdn_param_count.restype = i64
+        L.abc_mdn_create.argtypes = [P(_Prior), u64, P(vp)]
+        L.abc_mdn_destroy.argtypes = [vp]
+        L.abc_mdn_set_params.argtypes = [vp, vp, vp]
+        L.abc_mdn_get_params.argtypes = [vp, vp, vp]
+        L.abc_mdn_get_standardizer.argtypes = [vp, vp, vp, vp]
+        L.abc_mdn_simulate_features.argtypes = [P(_Prior), u64, ctypes.c_uint32, ctypes.c_uint32,
+                                                u64, i64, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                                vp, vp, vp, vp]
+        L.abc_series_features.argtypes = [P(_Series), vp, vp]
+        L.abc_mdn_fit_standardizer.argtypes = [vp, vp, i64, vp]
+        L.abc_mdn_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.abc_mdn_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.abc_mdn_train.argtypes = [vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, f32, u64,
+                                    vp, P(i64), P(f32), vp]
+        L.abc_mdn_sample.argtypes = [vp, vp, f32, P(_Stream), u64, i64, vp, vp, vp]
+        for f in ("abc_mdn_create", "abc_mdn_destroy", "abc_mdn_set_params",
+                  "abc_mdn_get_params", "abc_mdn_get_standardizer", "abc_mdn_simulate_features",
+                  "abc_series_features", "abc_mdn_fit_standardizer", "abc_mdn_forward",
+                  "abc_mdn_loss_grad", "abc_mdn_train", "abc_mdn_sample"):
+            getattr(L, f).restype = ctypes.c_int32
         L.abc_set_launch_config.argtypes = [ctypes.c_int32] * 3
         L.abc_set_launch_config.restype = ctypes.c_int32
         L.abc_get_launch_config.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
@@ -287,6 +309,111 @@ def batch_run(sers, eps, seed: int, quota: int, *, series_ids=None, round_size: 
     if check:
         _check(rc)
     return out
+
+
+def simulate_features(n: int, seed: int, *, domain: int = 2, series: int = 0, first: int = 0,
+                      T_lo: int = 30, T_hi: int = 200, log10P_lo: float = 5.0,
+                      log10P_hi: float = 9.0, A0: int = 100, prior: Optional[_Prior] = None,
+                      device="cuda"):
+    """(features [n,96], theta [n,8], TP [n,2]) training pairs drawn by the simulator."""
+    feats = torch.empty((n, 96), dtype=torch.float32, device=device)
+    theta = torch.empty((n, 8), dtype=torch.float32, device=device)
+    tp = torch.empty((n, 2), dtype=torch.int32, device=device)
+    pr = prior or make_prior()
+    _check(lib().abc_mdn_simulate_features(ctypes.byref(pr), int(seed), int(domain), int(series),
+                                           int(first), int(n), int(T_lo), int(T_hi),
+                                           float(log10P_lo), float(log10P_hi), int(A0),
+                                           _dptr(feats), _dptr(theta), _dptr(tp),
+                                           _stream_handle()))
+    return feats, theta, tp
+
+
+def series_features(ser: DeviceSeries, device="cuda") -> torch.Tensor:
+    out = torch.empty(96, dtype=torch.float32, device=device)
+    cs = ser.c()
+    _check(lib().abc_series_features(ctypes.byref(cs), _dptr(out), _stream_handle()))
+    return out
+
+
+class Mdn:
+    """Handle of the learned mixture-density proposal (device memory owned by libabc)."""
+
+    def __init__(self, init_seed: int = 0, prior: Optional[_Prior] = None):
+        self.prior = prior or make_prior()
+        h = ctypes.c_void_p()
+        _check(lib().abc_mdn_create(ctypes.byref(self.prior), int(init_seed), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().abc_mdn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().abc_mdn_param_count())
+
+    def set_params(self, p: torch.Tensor):
+        p = p.to(dtype=torch.float32, device="cuda").contiguous()
+        assert p.numel() == self.param_count()
+        _check(lib().abc_mdn_set_params(self.h, _dptr(p), _stream_handle()))
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(self.param_count(), dtype=torch.float32, device="cuda")
+        _check(lib().abc_mdn_get_params(self.h, _dptr(out), _stream_handle()))
+        return out
+
+    def standardizer(self):
+        m = torch.empty(96, dtype=torch.float32, device="cuda")
+        s = torch.empty(96, dtype=torch.float32, device="cuda")
+        _check(lib().abc_mdn_get_standardizer(self.h, _dptr(m), _dptr(s), _stream_handle()))
+        return m, s
+
+    def fit_standardizer(self, feats: torch.Tensor):
+        _check(lib().abc_mdn_fit_standardizer(self.h, _dptr(feats), int(feats.shape[0]),
+                                              _stream_handle()))
+
+    def forward(self, feats: torch.Tensor) -> torch.Tensor:
+        feats = feats.contiguous()
+        n = feats.shape[0]
+        out = torch.empty((n, 136), dtype=torch.float32, device="cuda")
+        _check(lib().abc_mdn_forward(self.h, _dptr(feats), int(n), _dptr(out), _stream_handle()))
+        return out
+
+    def loss_grad(self, feats: torch.Tensor, theta: torch.Tensor):
+        n = feats.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        grad = torch.empty(self.param_count(), dtype=torch.float32, device="cuda")
+        _check(lib().abc_mdn_loss_grad(self.h, _dptr(feats.contiguous()), _dptr(theta.contiguous()),
+                                       int(n), _dptr(loss), _dptr(grad), _stream_handle()))
+        return loss, grad
+
+    def train(self, feats: torch.Tensor, theta: torch.Tensor, *, epochs: int = 20,
+              batch: int = 4096, lr: float = 1e-3, shuffle_seed: int = 0):
+        n = feats.shape[0]
+        steps = (n // batch) * epochs
+        log = torch.zeros(steps, dtype=torch.float32, device="cuda")
+        st = ctypes.c_int64()
+        ms = ctypes.c_float()
+        _check(lib().abc_mdn_train(self.h, _dptr(feats), _dptr(theta), int(n), int(epochs),
+                                   int(batch), float(lr), int(shuffle_seed), _dptr(log),
+                                   ctypes.byref(st), ctypes.byref(ms), _stream_handle()))
+        return log, int(st.value), float(ms.value)
+
+    def sample(self, mix: torch.Tensor, n: int, seed: int, *, lam: float = 0.05, domain: int = 5,
+               series: int = 0, first: int = 0):
+        theta = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+        w = torch.empty(n, dtype=torch.float32, device="cuda")
+        st = make_stream(seed, domain, series)
+        _check(lib().abc_mdn_sample(self.h, _dptr(mix.contiguous()), float(lam), ctypes.byref(st),
+                                    int(first), int(n), _dptr(theta), _dptr(w), _stream_handle()))
+        return theta, w
 
 
 def version() -> str:
