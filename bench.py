@@ -137,6 +137,92 @@ def batched_leg(args):
         "autotune_best_ms_per_round": tune["ms_per_round"],
         "autotune_top": tune["table"][:5],
         "reps": [round(r[0], 4) for r in runs],
+        "_eps": eps,
+        "_used": [int(x) for x in o["used"].cpu().numpy()],
+    }
+
+
+def learned_leg(args, batched):
+    """Learned proposal: 1e6 (theta, x) pairs from the prior, the mixture-density
+    network trained 20 epochs (Adam, lr 1e-3, batch 4096) on the GPU, then
+    importance-weighted ABC on the same 64 series at the same eps, compared
+    with plain ABC (the batched leg's run) on accepted samples/s, effective
+    sample size and the posterior mean/sd criterion."""
+    import numpy as np
+    import torch
+
+    from paper_2012_14332_amd import abc
+    from paper_2012_14332_amd import pipeline as PL
+    from paper_2012_14332_amd import workloads as W
+
+    net, log, steps, train_ms, data_ms = PL.train_proposal(
+        n_pairs=args.mdn_pairs, epochs=args.mdn_epochs, batch=4096, lr=1e-3, seed=6)
+    log = log.cpu().numpy()
+    ss = W.uneven_series(64, 5)
+    sers = [PL.observed_series(s) for s in ss]
+    eps = batched["_eps"]
+    # one forward pass for all 64 observed series
+    feats = torch.stack([abc.series_features(ser) for ser in sers])
+    mix = net.forward(feats)
+    Q = args.quota
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for j, ser in enumerate(sers):
+        run = PL.LearnedABC.__new__(PL.LearnedABC)
+        PL.LearnedABC.__init__(run, net, ser, eps[j], 2, series=j, lam=args.lam,
+                               inflate=args.inflate)
+        run.mix = mix[j].contiguous()
+        res.append(run.run(Q))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    acc = sum(r.n() for r in res)
+    ess = sum(r.ess for r in res)
+    samples = sum(r.samples for r in res)
+    # posterior comparison against plain ABC at the same eps with Qc accepted
+    Qc = args.compare_quota
+    plain = abc.batch_run(sers, eps, 2, Qc, round_size=1 << 22, cand_capacity=4 * Qc)
+    pm = plain["mean"].cpu().numpy()
+    psd = np.sqrt(np.maximum(np.diagonal(plain["cov"].cpu().numpy(), axis1=1, axis2=2), 0))
+    lres = [r if Qc <= Q else None for r in res]
+    if Qc > Q:
+        lres = []
+        for j, ser in enumerate(sers):
+            run = PL.LearnedABC.__new__(PL.LearnedABC)
+            PL.LearnedABC.__init__(run, net, ser, eps[j], 2, series=j, lam=args.lam,
+                                   inflate=args.inflate)
+            run.mix = mix[j].contiguous()
+            lres.append(run.run(Qc))
+    lm = np.stack([r.mean.cpu().numpy() for r in lres])
+    lsd = np.sqrt(np.maximum(np.stack([np.diagonal(r.cov.cpu().numpy()) for r in lres]), 0))
+    ok_mu = np.abs(lm - pm) <= 0.05 * np.maximum(np.abs(pm), psd)
+    ok_sd = np.abs(lsd - psd) <= 0.05 * psd
+    gains = [(r.accepted_total / r.samples) / (Q / u) for r, u in zip(res, batched["_used"])]
+    net.close()
+    return {
+        "workload": "1e6 training pairs (T ~ U[30,200], P log-uniform [1e5,1e9], theta from the "
+                    "prior), 20 epochs Adam lr 1e-3 batch 4096 (BF16 MFMA, FP32 accumulation); "
+                    "importance-weighted ABC on the 64 uneven series at the batched leg's eps, "
+                    "quota %d each; defensive weight %.2f, proposal sd x%.1f" % (Q, args.lam, args.inflate),
+        "train_steps": steps,
+        "train_ms": train_ms,
+        "train_step_us": 1e3 * train_ms / max(steps, 1),
+        "data_ms": data_ms,
+        "loss_first_last": [float(log[:10].mean()), float(log[-10:].mean())],
+        "accepted_per_s": acc / wall,
+        "ess_per_s": ess / wall,
+        "plain_accepted_per_s": batched["accepted_per_s"],
+        "gain_accepted_per_s": (acc / wall) / batched["accepted_per_s"],
+        "gain_ess_per_s": (ess / wall) / batched["accepted_per_s"],
+        "acceptance_rate_gain_median": float(np.median(gains)),
+        "acceptance_rate_gain_range": [float(np.min(gains)), float(np.max(gains))],
+        "ess_median": float(np.median([r.ess for r in res])),
+        "wall_s": wall,
+        "samples": samples,
+        "posterior_check_quota": Qc,
+        "posterior_mean_within_5pct": float(ok_mu.mean()),
+        "posterior_sd_within_5pct": float(ok_sd.mean()),
+        "posterior_both_within_5pct_series": int(np.sum(ok_mu.all(1) & ok_sd.all(1))),
     }
 
 
@@ -155,6 +241,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--quota", type=int, default=1000)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--mdn-pairs", type=int, default=1_000_000)
+    ap.add_argument("--mdn-epochs", type=int, default=20)
+    ap.add_argument("--lam", type=float, default=0.1)
+    ap.add_argument("--inflate", type=float, default=3.0)
+    ap.add_argument("--compare-quota", type=int, default=1000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (scales HBM byte counters)")
     args = ap.parse_args()
@@ -293,6 +385,10 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_leg(args)
+        if not args.no_learned:
+            out["learned"] = learned_leg(args, out["batched"])
+        out["batched"].pop("_eps", None)
+        out["batched"].pop("_used", None)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
     print(json.dumps(out))

@@ -363,13 +363,15 @@ ABC_API abc_status abc_mdn_train(abc_mdn* net, const float* features, const floa
 
 /* Proposal draws for samples first..first+n-1 of stream st: with probability
  * lambda theta ~ prior, otherwise from the mixture given by `mix` (device,
- * one network output row [136]); draws outside the prior box are redrawn.
- * weight = prior(theta) / q(theta) with q = (1 - lambda) q_mix + lambda prior
- * (the truncation constant cancels in self-normalised weights). Outputs
- * device theta [n][8], weight [n]. */
+ * one network output row [136]) with every component sd multiplied by
+ * `inflate` (>= 1; the network estimates the eps -> 0 posterior, which is
+ * narrower than the eps-ABC posterior); draws outside the prior box are
+ * redrawn (attempt a uses day a + 1 of the stream). weight = prior(theta) /
+ * q(theta), q = (1 - lambda) q_mix + lambda prior (the truncation constant
+ * cancels in self-normalised weights). Outputs device theta [n][8], weight [n]. */
 ABC_API abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float lambda,
-                                  const abc_stream* st, uint64_t first, int64_t n, float* theta,
-                                  float* weight, void* stream);
+                                  float inflate, const abc_stream* st, uint64_t first, int64_t n,
+                                  float* theta, float* weight, void* stream);
 
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);

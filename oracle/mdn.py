@@ -80,6 +80,15 @@ def mixture_logpdf(out, t):
     return logsumexp(logpi + comp, axis=1)
 
 
+def mixture_logpdf_unclamped(out, t):
+    """mixture_logpdf with the log sds taken as given (already clamped/shifted)."""
+    logits, mu, ls = split_out(out)
+    logpi = logits - logsumexp(logits, axis=1, keepdims=True)
+    u = (t[:, None, :] - mu) * np.exp(-ls)
+    comp = -0.5 * (u * u).sum(2) - ls.sum(2) - 0.5 * D * LOG_2PI
+    return logsumexp(logpi + comp, axis=1)
+
+
 def loss(p, x, t):
     out, _ = forward(p, x)
     return float(-mixture_logpdf(out, t).mean())
@@ -158,14 +167,18 @@ def mixture_sample(out_row, n, rng):
     return mu[0][k] + sig[k] * rng.standard_normal((n, D))
 
 
-def defensive_logq(out_row, theta, lo, hi, lam):
+def defensive_logq(out_row, theta, lo, hi, lam, inflate=1.0):
     """log of the defensive proposal density at theta (original units):
-    (1 - lam) * mixture (mapped back from the standardised space) + lam * prior."""
+    (1 - lam) * mixture (component sds times `inflate`, mapped back from the
+    standardised space) + lam * prior."""
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
     s = (hi - lo) / math.sqrt(12.0)
     t = theta_standardise(theta, lo, hi)
-    lq_mix = mixture_logpdf(np.repeat(np.asarray(out_row, np.float64)[None], t.shape[0], 0), t) \
-        - np.log(s).sum()
+    row = np.asarray(out_row, np.float64).copy()
+    # inflating every sd = adding log(inflate) to the clamped log sd
+    ls = row[K + K * D:]
+    row[K + K * D:] = np.clip(ls, LOGSIG_LO, LOGSIG_HI) + math.log(inflate)
+    lq_mix = mixture_logpdf_unclamped(np.repeat(row[None], t.shape[0], 0), t) - np.log(s).sum()
     lq_prior = -np.log(hi - lo).sum()
     return np.logaddexp(np.log1p(-lam) + lq_mix, np.log(lam) + lq_prior) if lam > 0 else lq_mix

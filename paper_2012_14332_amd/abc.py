@@ -108,7 +108,7 @@ def lib():
         L.abc_mdn_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.abc_mdn_train.argtypes = [vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, f32, u64,
                                     vp, P(i64), P(f32), vp]
-        L.abc_mdn_sample.argtypes = [vp, vp, f32, P(_Stream), u64, i64, vp, vp, vp]
+        L.abc_mdn_sample.argtypes = [vp, vp, f32, f32, P(_Stream), u64, i64, vp, vp, vp]
         for f in ("abc_mdn_create", "abc_mdn_destroy", "abc_mdn_set_params",
                   "abc_mdn_get_params", "abc_mdn_get_standardizer", "abc_mdn_simulate_features",
                   "abc_series_features", "abc_mdn_fit_standardizer", "abc_mdn_forward",
@@ -406,12 +406,13 @@ class Mdn:
                                    ctypes.byref(st), ctypes.byref(ms), _stream_handle()))
         return log, int(st.value), float(ms.value)
 
-    def sample(self, mix: torch.Tensor, n: int, seed: int, *, lam: float = 0.05, domain: int = 5,
-               series: int = 0, first: int = 0):
+    def sample(self, mix: torch.Tensor, n: int, seed: int, *, lam: float = 0.05,
+               inflate: float = 1.0, domain: int = 5, series: int = 0, first: int = 0):
         theta = torch.empty((n, 8), dtype=torch.float32, device="cuda")
         w = torch.empty(n, dtype=torch.float32, device="cuda")
         st = make_stream(seed, domain, series)
-        _check(lib().abc_mdn_sample(self.h, _dptr(mix.contiguous()), float(lam), ctypes.byref(st),
+        _check(lib().abc_mdn_sample(self.h, _dptr(mix.contiguous()), float(lam), float(inflate),
+                                    ctypes.byref(st),
                                     int(first), int(n), _dptr(theta), _dptr(w), _stream_handle()))
         return theta, w
 

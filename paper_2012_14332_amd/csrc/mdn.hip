@@ -490,6 +490,7 @@ struct SampleArgs {
     const float* mix;     // [136] network output for the series
     float lo[8], hi[8], tc[8], ts[8];
     float lambda;
+    float log_inflate;    // log of the factor applied to every component sd
     Key key;
     uint32_t domain, series;
     uint64_t first;
@@ -498,7 +499,8 @@ struct SampleArgs {
     float* weight;        // [n]
 };
 
-__device__ float mix_logq(const float* o, const float* th, const float* tc, const float* ts)
+__device__ float mix_logq(const float* o, const float* th, const float* tc, const float* ts,
+                          float log_inflate)
 {
     float lmax = -INFINITY;
     for (int k = 0; k < NN_K; ++k) lmax = fmaxf(lmax, o[k]);
@@ -513,7 +515,8 @@ __device__ float mix_logq(const float* o, const float* th, const float* tc, cons
         for (int j = 0; j < NN_D; ++j) {
             const float t = (th[j] - tc[j]) / ts[j];
             const float mu = o[NN_K + k * NN_D + j];
-            const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + k * NN_D + j], LOGSIG_LO), LOGSIG_HI);
+            const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + k * NN_D + j], LOGSIG_LO), LOGSIG_HI) +
+                             log_inflate;
             const float u = (t - mu) * expf(-ls);
             c += -0.5f * u * u - ls;
         }
@@ -575,7 +578,8 @@ __global__ __launch_bounds__(256) void k_mdn_sample(SampleArgs a)
             for (int h = 0; h < 2; ++h) {
                 const int d = j + h;
                 const float mu = o[NN_K + comp * NN_D + d];
-                const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + comp * NN_D + d], LOGSIG_LO), LOGSIG_HI);
+                const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + comp * NN_D + d], LOGSIG_LO), LOGSIG_HI) +
+                                 a.log_inflate;
                 const float t = mu + expf(ls) * (h ? z1 : z0);
                 th[d] = a.tc[d] + a.ts[d] * t;
                 inside = inside && th[d] >= a.lo[d] && th[d] < a.hi[d];
@@ -585,7 +589,7 @@ __global__ __launch_bounds__(256) void k_mdn_sample(SampleArgs a)
     }
     if (!ok)  // practically unreachable: each attempt takes the prior branch with prob. lambda
         for (int j = 0; j < 8; ++j) th[j] = 0.5f * (a.lo[j] + a.hi[j]);
-    const float lq_mix = mix_logq(o, th, a.tc, a.ts);
+    const float lq_mix = mix_logq(o, th, a.tc, a.ts, a.log_inflate);
     const float lq_prior = -logvol;
     float lq;
     if (a.lambda <= 0.0f) lq = lq_mix;
@@ -1007,9 +1011,10 @@ extern "C" abc_status abc_mdn_train(abc_mdn* net, const float* features, const f
 }
 
 extern "C" abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float lambda,
-                                     const abc_stream* st, uint64_t first, int64_t n, float* theta,
-                                     float* weight, void* stream)
+                                     float inflate, const abc_stream* st, uint64_t first,
+                                     int64_t n, float* theta, float* weight, void* stream)
 {
+    ABC_REQUIRE(isfinite(inflate) && inflate >= 1.0f && inflate <= 100.0f, "inflate must be in [1, 100]");
     ABC_REQUIRE(net && mix, "NULL net or mixture");
     abc_status rc;
     if ((rc = check_stream_sel(st))) return rc;
@@ -1023,6 +1028,7 @@ extern "C" abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float
         a.lo[j] = net->lo[j]; a.hi[j] = net->hi[j]; a.tc[j] = net->tc[j]; a.ts[j] = net->ts[j];
     }
     a.lambda = lambda;
+    a.log_inflate = logf(inflate);
     a.key = make_key(st->seed);
     a.domain = st->domain;
     a.series = st->series;

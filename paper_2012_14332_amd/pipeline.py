@@ -92,3 +92,96 @@ class PlainABC:
                                    want_rechecked=want_rechecked)
         mean, cov = abc.posterior_moments(th, n_dev=cnt, device=self.device)
         return PlainResult(idx, th, d, cnt, mean, cov, nre)
+
+
+# ----------------------------------------------------------------------------
+# learned proposal (importance-weighted rejection ABC)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class WeightedResult:
+    idx: torch.Tensor      # [q] int64 sample indices (first q accepted by index)
+    theta: torch.Tensor    # [q, 8]
+    weight: torch.Tensor   # [q] prior / proposal
+    dist: torch.Tensor     # [q]
+    mean: torch.Tensor     # [8] float64, weighted
+    cov: torch.Tensor      # [8, 8] float64, weighted
+    samples: int           # proposal draws simulated
+    ess: float             # (sum w)^2 / sum w^2
+    accepted_total: int    # accepted among all `samples` draws (before keeping the first q)
+
+    def n(self) -> int:
+        return int(self.idx.shape[0])
+
+
+def train_proposal(n_pairs: int = 1_000_000, epochs: int = 20, batch: int = 4096,
+                   lr: float = 1e-3, seed: int = 6, init_seed: int = 0,
+                   T_range=(30, 200), log10P_range=(5.0, 9.0)):
+    """Simulate (theta, x) pairs from the prior (domain 2) and train the
+    mixture-density network on them. Returns (net, loss log, steps, train ms,
+    data ms)."""
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    feats, theta, _ = abc.simulate_features(n_pairs, seed, domain=W.DOMAIN_MDN_DATA,
+                                            T_lo=T_range[0], T_hi=T_range[1],
+                                            log10P_lo=log10P_range[0], log10P_hi=log10P_range[1])
+    net = abc.Mdn(init_seed)
+    net.fit_standardizer(feats)
+    t1.record()
+    torch.cuda.synchronize()
+    data_ms = t0.elapsed_time(t1)
+    log, steps, ms = net.train(feats, theta, epochs=epochs, batch=batch, lr=lr, shuffle_seed=seed)
+    del feats, theta
+    return net, log, steps, ms, data_ms
+
+
+class LearnedABC:
+    """Rejection ABC with theta drawn from the trained mixture for one series
+    (defensive weight lam on the prior), importance weights prior / proposal,
+    the same eps, float32 simulation, compaction with weights, float64 band
+    decision and weighted float64 moments."""
+
+    def __init__(self, net, ser: abc.DeviceSeries, eps: float, seed: int, *, series: int = 0,
+                 lam: float = 0.05, inflate: float = 1.5, band_w: float = DEFAULT_BAND,
+                 chunk0: int = 1 << 14, chunk_max: int = 1 << 20):
+        self.net, self.ser, self.eps, self.seed = net, ser, float(eps), int(seed)
+        self.series, self.lam, self.band_w = int(series), float(lam), float(band_w)
+        self.inflate = float(inflate)
+        self.chunk0, self.chunk_max = int(chunk0), int(chunk_max)
+        self.mix = net.forward(abc.series_features(ser)[None])[0].contiguous()
+        self.dist = torch.empty(self.chunk_max, dtype=torch.float32, device="cuda")
+
+    def run(self, quota: int, max_samples: int = 1 << 34) -> WeightedResult:
+        """Consume proposal indices 0, 1, 2, ... in growing contiguous chunks until
+        `quota` samples are accepted; keep the first `quota` by index."""
+        e_hi = self.eps * (1.0 + self.band_w)
+        parts = []
+        got = 0
+        first = 0
+        chunk = self.chunk0
+        while got < quota and first < max_samples:
+            th, w = self.net.sample(self.mix, chunk, self.seed, lam=self.lam,
+                                    inflate=self.inflate, domain=W.DOMAIN_PROPOSAL,
+                                    series=self.series, first=first)
+            dist = self.dist[:chunk]
+            abc.simulate_distance(self.ser, chunk, self.seed, theta=th, first=first,
+                                  series=self.series, eps_exit=e_hi, out=dist)
+            # capacity = chunk: every draw could be a candidate
+            idx, thc, dc, wc, cnt = abc.accept_compact(dist, e_hi, chunk, theta=th, weight=w,
+                                                       first=first)
+            abc.recheck_band(self.ser, self.seed, self.eps, self.band_w, idx, thc, dc, cnt,
+                             weight=wc, series=self.series)
+            c = int(cnt.item())
+            if c:
+                parts.append((idx[:c], thc[:c], wc[:c], dc[:c]))
+                got += c
+            first += chunk
+            chunk = min(chunk * 2, self.chunk_max)
+        idx = torch.cat([p[0] for p in parts])[:quota]
+        th = torch.cat([p[1] for p in parts])[:quota].contiguous()
+        w = torch.cat([p[2] for p in parts])[:quota].contiguous()
+        d = torch.cat([p[3] for p in parts])[:quota]
+        mean, cov = abc.posterior_moments(th, w)
+        wn = w.double().cpu().numpy()
+        ess = float(wn.sum() ** 2 / (wn * wn).sum()) if wn.size else 0.0
+        return WeightedResult(idx, th, w, d, mean, cov, first, ess, got)

@@ -144,6 +144,11 @@ def test_sampler_weights_and_importance_identity(A):
     lq = ref.defensive_logq(mix_row.astype(np.float64), th[:2000], lo, hi, 0.05)
     w_ref = np.exp(-np.log(hi - lo).sum() - lq)
     np.testing.assert_allclose(w[:2000], w_ref, rtol=2e-4)
+    # the same with inflated component widths
+    th2, w2 = net.sample(mix, 3000, seed=5, lam=0.1, inflate=1.7)
+    th2 = th2.cpu().numpy().astype(np.float64)
+    lq2 = ref.defensive_logq(mix_row.astype(np.float64), th2, lo, hi, 0.1, inflate=1.7)
+    np.testing.assert_allclose(w2.cpu().numpy(), np.exp(-np.log(hi - lo).sum() - lq2), rtol=2e-4)
     # self-normalised importance sampling recovers prior expectations
     est = (w[:, None] * th).sum(0) / w.sum()
     ess = w.sum() ** 2 / (w * w).sum()
