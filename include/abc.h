@@ -373,6 +373,18 @@ ABC_API abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float la
                                   float inflate, const abc_stream* st, uint64_t first, int64_t n,
                                   float* theta, float* weight, void* stream);
 
+/*
+ * Posterior-predictive bands (Sec. 5: projections from accepted samples with
+ * the 5th-95th percentile band): for every day 0..T and compartment
+ * (S, I, A, R, D, Ru) the quantiles q[0..nq-1] (host, in [0, 1], nq <= 16) of
+ * n <= 8192 recorded trajectories traj (device int32 [n][T+1][6], e.g. from
+ * abc_simulate_record of accepted theta over a longer horizon). Quantile q
+ * interpolates linearly between the order statistics at h = (n - 1) q.
+ * out: device float32 [nq][T+1][6].
+ */
+ABC_API abc_status abc_trajectory_bands(const int32_t* traj, int64_t n, int32_t T,
+                                        const double* q, int32_t nq, float* out, void* stream);
+
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);
 

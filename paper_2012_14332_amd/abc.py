@@ -114,6 +114,8 @@ def lib():
                   "abc_series_features", "abc_mdn_fit_standardizer", "abc_mdn_forward",
                   "abc_mdn_loss_grad", "abc_mdn_train", "abc_mdn_sample"):
             getattr(L, f).restype = ctypes.c_int32
+        L.abc_trajectory_bands.argtypes = [vp, i64, ctypes.c_int32, vp, ctypes.c_int32, vp, vp]
+        L.abc_trajectory_bands.restype = ctypes.c_int32
         L.abc_set_launch_config.argtypes = [ctypes.c_int32] * 3
         L.abc_set_launch_config.restype = ctypes.c_int32
         L.abc_get_launch_config.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
@@ -415,6 +417,16 @@ class Mdn:
                                     ctypes.byref(st),
                                     int(first), int(n), _dptr(theta), _dptr(w), _stream_handle()))
         return theta, w
+
+
+def trajectory_bands(traj: torch.Tensor, quantiles=(0.05, 0.5, 0.95)) -> torch.Tensor:
+    """Per-day, per-compartment quantiles [nq, T+1, 6] of trajectories [n, T+1, 6]."""
+    n, T1, _ = traj.shape
+    q = (ctypes.c_double * len(quantiles))(*quantiles)
+    out = torch.empty((len(quantiles), T1, 6), dtype=torch.float32, device=traj.device)
+    _check(lib().abc_trajectory_bands(_dptr(traj.contiguous()), int(n), int(T1 - 1), q,
+                                      len(quantiles), _dptr(out), _stream_handle()))
+    return out
 
 
 def version() -> str:

@@ -185,3 +185,17 @@ class LearnedABC:
         wn = w.double().cpu().numpy()
         ess = float(wn.sum() ** 2 / (wn * wn).sum()) if wn.size else 0.0
         return WeightedResult(idx, th, w, d, mean, cov, first, ess, got)
+
+
+DOMAIN_PROJECTION = 6
+
+
+def predictive_bands(s: W.Series, theta: torch.Tensor, horizon: int = 120, seed: int = 7,
+                     quantiles=(0.05, 0.5, 0.95), flags: int = 0):
+    """Posterior-predictive projection (Sec. 5): simulate every accepted theta
+    over `horizon` days from the series' initial state on a fresh stream
+    (domain 6), return (trajectories [n, horizon+1, 6], bands [nq, horizon+1, 6])."""
+    ser = abc.DeviceSeries(s.P, horizon, A0=s.A0, R0=s.R0, D0=s.D0)
+    traj = abc.simulate_record(ser, theta.contiguous(), seed, domain=DOMAIN_PROJECTION,
+                               series=s.series_id, flags=flags)
+    return traj, abc.trajectory_bands(traj, quantiles)

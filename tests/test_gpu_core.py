@@ -244,3 +244,42 @@ def test_invalid_arguments_raise(A):
         A.simulate_record(ser, A.sample_prior(4, seed=1), seed=1)
     with pytest.raises(A.AbcError):
         A.sample_prior(4, seed=1, domain=16)
+
+
+def test_trajectory_bands_match_numpy_quantiles(A):
+    rng = np.random.default_rng(3)
+    for n, T in [(1, 5), (100, 120), (257, 30), (4096, 10)]:
+        traj = rng.integers(0, 10_000_000, size=(n, T + 1, 6), dtype=np.int64).astype(np.int32)
+        q = (0.0, 0.05, 0.5, 0.95, 1.0)
+        out = A.trajectory_bands(torch.from_numpy(traj).cuda(), q).cpu().numpy()
+        ref = np.quantile(traj.astype(np.float64), q, axis=0)
+        np.testing.assert_allclose(out, ref.astype(np.float32), rtol=1e-6, atol=0.5)
+
+
+def test_predictive_projection_of_accepted_samples(A):
+    from paper_2012_14332_amd import pipeline as P
+
+    s = W.three_countries()[0]
+    ser = P.observed_series(s)
+    eps = P.pilot_eps(ser, 1, n=100_000, q=1e-3, series=0)
+    res = P.PlainABC(ser, 1, eps, 100_000, series=0).run(0)
+    th = res.theta[:res.n()]
+    traj, bands = P.predictive_bands(s, th, horizon=120)
+    tr = traj.cpu().numpy().astype(np.int64)
+    assert tr.shape == (res.n(), 121, 6)
+    assert np.all(tr.sum(axis=2) == s.P)
+    b = bands.cpu().numpy()
+    assert np.all(b[0] <= b[1] + 1e-3) and np.all(b[1] <= b[2] + 1e-3)
+    # the projections reproduce the fitted window: the observed A series lies
+    # inside the 5th-95th band on most of the 49 fitted days
+    obs = ser.obs.cpu().numpy()
+    inside = (obs[0] >= b[0, 1:50, 2] - 1) & (obs[0] <= b[2, 1:50, 2] + 1)
+    assert inside.mean() > 0.5, inside.mean()
+    # float64 projections equal the oracle's trajectories on the same stream,
+    # so their bands equal the quantiles of the oracle's runs
+    traj64, bands64 = P.predictive_bands(s, th, horizon=120, flags=A.ABC_FP64)
+    ref = oracle.record(oracle.make_model(s.P, 120), th.cpu().numpy(), seed=7,
+                        domain=P.DOMAIN_PROJECTION, series=s.series_id)
+    np.testing.assert_array_equal(traj64.cpu().numpy(), ref)
+    qref = np.quantile(ref.astype(np.float64), (0.05, 0.5, 0.95), axis=0)
+    np.testing.assert_allclose(bands64.cpu().numpy(), qref.astype(np.float32), rtol=1e-6, atol=0.5)

@@ -1,0 +1,131 @@
+"""Precision study on the three countries at 1e9 samples in total: FP32
+state + naive FP32 distance sum, FP32 + Kahan-compensated sum, and the FP64
+device path, each against the FP64 oracle on a shared 1e6-sample subset per
+country; at the full 3.33e8 samples per country the FP32 variants (with the
+float64 band decision) against the FP64 device path. Prints one JSON report
+(run with -s to see it).
+
+Bars: on the subset, FP64 device distances within 1e-12 relative of the
+oracle and accept sets identical outside the tie band |d - eps| < 1e-5 eps for
+FP64 and for both FP32 variants with the band decision; at scale, the FP32
+accept sets equal the FP64 ones up to samples whose FP32 error exceeded the
+band (none expected), and the posterior means agree to 1e-3 of the sd.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2012_14332_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TIE = 1e-5
+SUBSET = 1_000_000
+TOTAL = int(os.environ.get("ABC_PRECISION_TOTAL", 1_000_000_000))
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_14332_amd import abc, pipeline as P
+
+    abc.lib()
+    return abc, P
+
+
+def _stats(rel):
+    return {"max": float(rel.max()), "median": float(np.median(rel)),
+            "p99_9": float(np.quantile(rel, 0.999))}
+
+
+def _outside_tie(diff, d_ref, eps, first=0):
+    return [int(i) for i in diff if abs(d_ref[int(i) - first] - eps) >= TIE * eps]
+
+
+def test_precision_study(env):
+    abc, P = env
+    report = {"subset_samples_per_country": SUBSET, "total_samples": TOTAL, "countries": {}}
+    per_country = TOTAL // 3
+    for c, s in enumerate(W.three_countries()):
+        ser = P.observed_series(s)
+        eps = P.pilot_eps(ser, 1, n=100_000, q=1e-4, series=c)
+        m = oracle.make_model(s.P, s.T)
+        obs = oracle.observe(m, s.theta_true, s.obs_seed)
+        first = 100_000
+        ref = oracle.distances(m, obs, seed=1, n=SUBSET, first=first, series=c)
+        rep = {"eps": eps}
+        want = set((np.nonzero(ref <= eps)[0] + first).tolist())
+        # subset: distances without early exit
+        for name, flags in (("fp32_naive", 0), ("fp32_kahan", abc.ABC_KAHAN), ("fp64", abc.ABC_FP64)):
+            d, d64 = abc.simulate_distance(ser, SUBSET, 1, first=first, series=c, flags=flags,
+                                           want64=True)
+            g = d64.cpu().numpy()
+            rel = np.abs(g - ref) / ref
+            near = ref <= 2 * eps
+            r = {"rel_err_all": _stats(rel), "rel_err_near_eps": _stats(rel[near])}
+            decided = set((np.nonzero(g <= eps)[0] + first).tolist())
+            r["accept_mismatch_outside_tie_without_band"] = len(
+                _outside_tie(decided ^ want, ref, eps, first))
+            if flags == abc.ABC_FP64:
+                assert rel.max() <= 1e-12, rel.max()
+                assert r["accept_mismatch_outside_tie_without_band"] == 0
+            else:
+                run = P.PlainABC(ser, 1, eps, SUBSET, series=c, flags=flags, capacity=1 << 14)
+                res = run.run(first)
+                got = set(res.idx[:res.n()].cpu().numpy().tolist())
+                r["accept_mismatch_outside_tie_with_band"] = len(
+                    _outside_tie(got ^ want, ref, eps, first))
+                assert r["accept_mismatch_outside_tie_with_band"] == 0
+            rep[name] = r
+        # full scale: FP32 variants (with the band) against the FP64 device path
+        big = {}
+        chunk = 1 << 25
+        for name, flags in (("fp32_naive", 0), ("fp32_kahan", abc.ABC_KAHAN), ("fp64", abc.ABC_FP64)):
+            idx_all, th_all = [], []
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for f0 in range(first, first + per_country, chunk):
+                n = min(chunk, first + per_country - f0)
+                if flags == abc.ABC_FP64:
+                    dist = abc.simulate_distance(ser, n, 1, first=f0, series=c, flags=flags,
+                                                 eps_exit=eps)
+                    idx, th, _, _, cnt = abc.accept_compact(dist, eps, 1 << 16, first=f0, seed=1,
+                                                            series=c)
+                else:
+                    run = P.PlainABC(ser, 1, eps, n, series=c, flags=flags, capacity=1 << 16)
+                    res = run.run(f0)
+                    idx, th, cnt = res.idx, res.theta, res.count
+                k = int(cnt.item())
+                assert k <= (1 << 16)
+                idx_all.append(idx[:k])
+                th_all.append(th[:k])
+            t1.record()
+            torch.cuda.synchronize()
+            idx = torch.cat(idx_all)
+            th = torch.cat(th_all).contiguous()
+            mean, cov = abc.posterior_moments(th)
+            big[name] = {"idx": idx.cpu().numpy(), "mean": mean.cpu().numpy(),
+                         "cov": cov.cpu().numpy(), "ms": t0.elapsed_time(t1)}
+        ref64 = big["fp64"]
+        sd = np.sqrt(np.diag(ref64["cov"]))
+        for name in ("fp32_naive", "fp32_kahan"):
+            b = big[name]
+            diff = np.setxor1d(b["idx"], ref64["idx"])
+            rep[name]["scale"] = {
+                "accepted": int(b["idx"].size),
+                "accept_set_differences_vs_fp64": int(diff.size),
+                "mean_err_over_sd_max": float(np.max(np.abs(b["mean"] - ref64["mean"]) / sd)),
+                "cov_rel_err_max": float(np.max(np.abs(b["cov"] - ref64["cov"])) /
+                                         np.max(np.abs(ref64["cov"]))),
+                "ms": b["ms"],
+            }
+            assert diff.size <= 2, diff.size
+            assert np.all(np.abs(b["mean"] - ref64["mean"]) <= 1e-3 * sd)
+        rep["fp64"]["scale"] = {"accepted": int(ref64["idx"].size), "ms": ref64["ms"]}
+        report["countries"][s.name] = rep
+    print("PRECISION_REPORT " + json.dumps(report))
