@@ -226,6 +226,65 @@ def learned_leg(args, batched):
     }
 
 
+def smc_leg(args):
+    """ABC-SMC on the first country: N particles, adaptive quantile tolerances
+    from the pilot quantile eps0; compared with rejection ABC at the final
+    tolerance (its acceptance rate measured on a plain pass)."""
+    import torch
+
+    from paper_2012_14332_amd import abc
+    from paper_2012_14332_amd import pipeline as PL
+    from paper_2012_14332_amd import workloads as W
+
+    s = W.three_countries()[0]
+    ser = PL.observed_series(s)
+    eps0 = PL.pilot_eps(ser, 3, n=args.pilot, q=args.smc_q0, series=0)
+    N, G = args.smc_particles, args.smc_generations
+    cfg = abc.smc_config(N, eps0, generations=G, alpha=args.smc_alpha, chunk0=1 << 16,
+                         chunk_max=1 << 22)
+    abc.smc_run(ser, abc.smc_config(N, eps0, generations=2, alpha=args.smc_alpha,
+                                    chunk0=1 << 16, chunk_max=1 << 22), 4)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = abc.smc_run(ser, cfg, 3)
+    torch.cuda.synchronize()
+    smc_s = time.perf_counter() - t0
+    gens = [o["stats"] for o in outs]
+    eps_final = float(gens[-1]["eps"])
+    sims = sum(g["in_support"] for g in gens)
+    proposed = sum(g["proposed"] for g in gens)
+    # rejection ABC at the final tolerance: acceptance rate and speed of a plain pass
+    n_chunk = args.smc_rejection_samples
+    run = PL.PlainABC(ser, 3, eps_final, n_chunk, series=0, band_w=args.band, capacity=1 << 20)
+    run.run(0)
+    torch.cuda.synchronize()
+    acc = n_rej = 0
+    rej_s = 0.0
+    while acc < 200 and n_rej < (1 << 33):
+        t0 = time.perf_counter()
+        acc += run.run(n_rej).n()
+        rej_s += time.perf_counter() - t0
+        n_rej += n_chunk
+    rate = acc / n_rej
+    need = N / rate if acc else float("inf")
+    return {
+        "workload": "%s: N = %d particles, %d generations, alpha %.2f, eps0 = pilot quantile %.0e; "
+                    "rejection ABC at the final eps for comparison (%d samples)" % (
+                        s.name, N, len(gens), args.smc_alpha, args.smc_q0, n_rej),
+        "generations": [{"eps": g["eps"], "samples": g["samples"], "in_support": g["in_support"],
+                         "proposed": g["proposed"], "ess": round(g["ess"], 1)} for g in gens],
+        "wall_s": smc_s,
+        "eps_final": eps_final,
+        "simulations": sims,
+        "proposals": proposed,
+        "rejection_accept_rate_at_eps_final": rate,
+        "rejection_samples_for_N": need,
+        "rejection_s_for_N": need * rej_s / n_rej,
+        "simulation_gain": need / sims if sims else None,
+        "wall_gain": (need * rej_s / n_rej) / smc_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +306,12 @@ def main():
     ap.add_argument("--lam", type=float, default=0.1)
     ap.add_argument("--inflate", type=float, default=3.0)
     ap.add_argument("--compare-quota", type=int, default=1000)
+    ap.add_argument("--no-smc", action="store_true")
+    ap.add_argument("--smc-particles", type=int, default=4096)
+    ap.add_argument("--smc-generations", type=int, default=8)
+    ap.add_argument("--smc-alpha", type=float, default=0.5)
+    ap.add_argument("--smc-q0", type=float, default=1e-2)
+    ap.add_argument("--smc-rejection-samples", type=int, default=1 << 26)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (scales HBM byte counters)")
     args = ap.parse_args()
@@ -389,6 +454,8 @@ def main():
             out["learned"] = learned_leg(args, out["batched"])
         out["batched"].pop("_eps", None)
         out["batched"].pop("_used", None)
+    if not args.no_smc:
+        out["smc"] = smc_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
     print(json.dumps(out))

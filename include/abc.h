@@ -61,6 +61,8 @@ typedef int32_t abc_status;
 #define ABC_NOISE_LITERAL 0x4u /* noise sd = h^(1/4) ("variance sqrt(h)" read literally);
                                   default sd = sqrt(h), i.e. variance h */
 #define ABC_DIST_RAW 0x8u      /* Euclidean distance on raw counts (default: log1p counts) */
+#define ABC_SUPPORT 0x10u      /* supplied theta: rows outside the closed prior box have prior
+                                  density zero and get distance +INF without simulation */
 
 #define ABC_T_MAX 1024         /* longest horizon a series may have */
 
@@ -73,7 +75,8 @@ typedef struct {
 
 /* Random stream selector. domain in [0, 15]: 0 = observation synthesis,
  * 1 = ABC sampling/simulation, 2 = learned-proposal training data,
- * 3 = network initialisation, 5 = learned-proposal draws. */
+ * 3 = network initialisation, 5 = learned-proposal draws, 6 = projections,
+ * 7 = ABC-SMC generations >= 1. */
 typedef struct {
     uint64_t seed;
     uint32_t domain;
@@ -121,7 +124,10 @@ ABC_API abc_status abc_sample_prior(const abc_prior* prior, const abc_stream* st
  *   theta   device float32 [n][8] with non-negative rates, or NULL: then theta
  *           is drawn in-kernel from `prior` (lo >= 0) on the same stream exactly
  *           as abc_sample_prior would.
- *   prior   host; required when theta is NULL, ignored otherwise.
+ *   prior   host; required when theta is NULL or the ABC_SUPPORT flag is set,
+ *           ignored otherwise. With ABC_SUPPORT and supplied theta, a row with
+ *           any theta_k < lo_k, theta_k > hi_k (or NaN) is not simulated and
+ *           reports dist +INF.
  *   eps_exit  early-exit bound: a sample stops as soon as its running squared
  *           distance exceeds eps_exit^2 (with a margin that can never flip an
  *           accept decision at eps <= eps_exit) and reports +INF. Pass +INF to
@@ -384,6 +390,133 @@ ABC_API abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float la
  */
 ABC_API abc_status abc_trajectory_bands(const int32_t* traj, int64_t n, int32_t T,
                                         const double* q, int32_t nq, float* out, void* stream);
+
+/*
+ * Nearest-k rule (the "keep the k nearest prior samples" form of rejection
+ * ABC, Sec. 2.2; the per-run Top-k return of Sec. 3.2): the k samples of a
+ * launch with the smallest distances, ties to the lower sample index, in
+ * sample-index order.
+ *   dist    device float32 [n] (sample first + j at position j), n < 2^32.
+ *   theta   device float32 [n][8] or NULL: then output rows are re-drawn from
+ *           `prior` on stream `st` (as abc_accept_compact does).
+ *   k       1 <= k <= min(n, 4096).
+ *   out_idx device int64 [k]; out_theta device float32 [k][8] or NULL;
+ *   out_dist device float32 [k] or NULL; out_kth device float32 [1] or NULL:
+ *           the k-th smallest distance.
+ * Exact selection by narrowing histograms (no full sort); synchronises the
+ * stream once per narrowing pass (at most 7). NaN sorts above +inf.
+ * Errors: ABC_EINVAL (bad sizes, NULL pointers, fewer than k finite
+ * distances).
+ */
+ABC_API abc_status abc_nearest_k(const float* dist, const float* theta, const abc_prior* prior,
+                                 const abc_stream* st, int64_t n, uint64_t first, int32_t k,
+                                 int64_t* out_idx, float* out_theta, float* out_dist,
+                                 float* out_kth, void* stream);
+
+/*
+ * Nearest-k among n <= 65536 rows with float64 distances (e.g. the float64
+ * re-decision of the candidates of abc_nearest_k): the k rows with the
+ * smallest (dist64, idx), written in increasing idx order. All pointers
+ * device; theta / out_theta optional together; out_dist optional.
+ * Errors: ABC_EINVAL.
+ */
+ABC_API abc_status abc_nearest_k_rows(const double* dist64, const int64_t* idx, const float* theta,
+                                      int64_t n, int32_t k, int64_t* out_idx, float* out_theta,
+                                      double* out_dist, void* stream);
+
+/*
+ * Float64 distances (Sec. 2.2) of listed rows: row q is sample idx[q] of
+ * stream `st` with parameters theta[q] (device float32 [n][8]); the same
+ * float64 simulation as abc_simulate_distance with ABC_FP64, without early
+ * exit. dist64: device float64 [n]. ABC_SUPPORT is ignored.
+ * Errors: ABC_EINVAL (NULL pointers, n < 0, series/model checks).
+ */
+ABC_API abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model* model,
+                                         const abc_stream* st, const int64_t* idx,
+                                         const float* theta, int64_t n, double* dist64,
+                                         void* stream);
+
+/*
+ * ABC-SMC (Sec. 2.2 names sequential Monte Carlo ABC: a population refined
+ * over a decreasing tolerance sequence). Population Monte Carlo ABC
+ * (Beaumont, Cornuet, Marin & Robert 2009) with adaptive tolerances:
+ *   generation 0: rejection ABC from `prior` at eps0 on stream (seed, domain 1,
+ *     series); the population is the first N accepted samples by index, with
+ *     equal weights.
+ *   generation t >= 1: eps_t = max(eps_min, the ceil(alpha N)-th smallest
+ *     float64 distance of generation t-1) rounded to float32; Sigma = 2 x the
+ *     weighted covariance of generation t-1 (sums over particles left to
+ *     right), L its Cholesky factor. Candidate i (stream domain 7, series word
+ *     series | t << 16, day 0 blocks 0..2) draws a 53-bit uniform u and eight
+ *     Box-Muller normals z; its ancestor is the smallest j with
+ *     C_j > u C_{N-1} (C = running sums of the weights); theta* = theta_j + L z
+ *     in float64, rounded to float32. Candidates outside the closed prior box
+ *     are rejected without simulation; the others are simulated (days 1..T of
+ *     the same stream) and accepted iff distance <= eps_t (float32 path,
+ *     float64 decision within the relative band band_w). The first N accepted
+ *     by index form the population; weights W_i are proportional to
+ *     1 / sum_j W_j exp(-(theta_i - theta_j)^T Sigma^-1 (theta_i - theta_j) / 2)
+ *     (the uniform prior and the Gaussian normaliser cancel), normalised.
+ * Every population is independent of chunk sizes and launch shapes.
+ */
+typedef struct {
+    int32_t n_particles;  /* N in [2, 8192] (N >= 9 for a non-singular Sigma) */
+    int32_t generations;  /* for abc_smc_run: at most this many, generation 0 included */
+    double alpha;         /* (0, 1]: quantile of the next tolerance */
+    float eps0;           /* tolerance of generation 0 */
+    float eps_min;        /* floor of the tolerance sequence; abc_smc_run stops after the
+                             generation that reaches it (0 = no floor) */
+    float band_w;         /* relative band of the float64 decision, [0, 1) */
+    int32_t pad;
+    int64_t chunk0;       /* candidates in the first chunk of a generation (doubling) */
+    int64_t chunk_max;    /* largest chunk, <= 2^26 */
+    int64_t max_samples;  /* candidate budget per generation: ABC_EOVERFLOW beyond it */
+} abc_smc_config;
+
+typedef struct {
+    float eps;            /* tolerance of the generation */
+    int32_t pad;
+    int64_t samples;      /* candidates consumed: index of the N-th accepted + 1 */
+    int64_t in_support;   /* of those, inside the prior box (= simulated) */
+    int64_t proposed;     /* candidates drawn (whole chunks) */
+    double ess;           /* 1 / sum W^2 */
+} abc_smc_gen_stats;
+
+/*
+ * One generation `gen` of ABC-SMC for the observed series `ser` (float32 path;
+ * ABC_FP64 is rejected). prev_theta [n_prev][8] float32, prev_w [n_prev]
+ * (normalised) and prev_dist [n_prev] float64 are the previous generation
+ * (device; ignored for gen 0). Outputs (device, cfg->n_particles rows):
+ * idx (candidate index), theta (16-byte aligned), w (normalised float64
+ * weights), dist (float64 distance of each particle, re-simulated in float64);
+ * stats (host) as described above; ancestors (device int32 [N] or NULL):
+ * index of each particle's ancestor in the previous population.
+ * Workspace is allocated stream-ordered on `stream` and freed before return;
+ * the call synchronises the stream once per chunk.
+ * Errors: ABC_EINVAL (bad arguments, or a previous population whose Sigma is
+ * not positive definite), ABC_EOVERFLOW (fewer than N accepted within
+ * max_samples candidates), ABC_EHIP.
+ */
+ABC_API abc_status abc_smc_generation(const abc_series* ser, const abc_model* model,
+                                      const abc_prior* prior, uint64_t seed, uint32_t series,
+                                      int32_t gen, const float* prev_theta, const double* prev_w,
+                                      const double* prev_dist, int32_t n_prev,
+                                      const abc_smc_config* cfg, int64_t* idx, float* theta,
+                                      double* w, double* dist, abc_smc_gen_stats* stats,
+                                      int32_t* ancestors, void* stream);
+
+/*
+ * Generations 0, 1, ... of ABC-SMC (see abc_smc_generation) until
+ * cfg->generations are done or a generation's tolerance reaches eps_min.
+ * Outputs are device arrays with one block of N rows per generation:
+ * idx [G][N], theta [G][N][8], w [G][N], dist [G][N]; stats host [G];
+ * *gens_done (host) = generations completed.
+ */
+ABC_API abc_status abc_smc_run(const abc_series* ser, const abc_model* model,
+                               const abc_prior* prior, uint64_t seed, uint32_t series,
+                               const abc_smc_config* cfg, int64_t* idx, float* theta, double* w,
+                               double* dist, abc_smc_gen_stats* stats, int32_t* gens_done,
+                               void* stream);
 
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);

@@ -20,6 +20,7 @@ ABC_FP64 = 0x1
 ABC_KAHAN = 0x2
 ABC_NOISE_LITERAL = 0x4
 ABC_DIST_RAW = 0x8
+ABC_SUPPORT = 0x10
 T_MAX = 1024
 
 PRIOR_LO = (0.0,) * 8
@@ -62,6 +63,19 @@ class _BatchStats(ctypes.Structure):
 
 
 _lib = None
+
+
+class _SmcConfig(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int32), ("generations", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("eps0", ctypes.c_float), ("eps_min", ctypes.c_float),
+                ("band_w", ctypes.c_float), ("pad", ctypes.c_int32), ("chunk0", ctypes.c_int64),
+                ("chunk_max", ctypes.c_int64), ("max_samples", ctypes.c_int64)]
+
+
+class _SmcGenStats(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_float), ("pad", ctypes.c_int32), ("samples", ctypes.c_int64),
+                ("in_support", ctypes.c_int64), ("proposed", ctypes.c_int64),
+                ("ess", ctypes.c_double)]
 
 
 def lib():
@@ -114,6 +128,21 @@ def lib():
                   "abc_series_features", "abc_mdn_fit_standardizer", "abc_mdn_forward",
                   "abc_mdn_loss_grad", "abc_mdn_train", "abc_mdn_sample"):
             getattr(L, f).restype = ctypes.c_int32
+        L.abc_smc_generation.argtypes = [P(_Series), P(_Model), P(_Prior), u64, ctypes.c_uint32,
+                                         ctypes.c_int32, vp, vp, vp, ctypes.c_int32, P(_SmcConfig),
+                                         vp, vp, vp, vp, P(_SmcGenStats), vp, vp]
+        L.abc_smc_generation.restype = ctypes.c_int32
+        L.abc_smc_run.argtypes = [P(_Series), P(_Model), P(_Prior), u64, ctypes.c_uint32,
+                                  P(_SmcConfig), vp, vp, vp, vp, P(_SmcGenStats),
+                                  ctypes.POINTER(ctypes.c_int32), vp]
+        L.abc_smc_run.restype = ctypes.c_int32
+        L.abc_nearest_k.argtypes = [vp, vp, P(_Prior), P(_Stream), i64, u64, ctypes.c_int32, vp, vp,
+                                    vp, vp, vp]
+        L.abc_nearest_k.restype = ctypes.c_int32
+        L.abc_nearest_k_rows.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp]
+        L.abc_nearest_k_rows.restype = ctypes.c_int32
+        L.abc_simulate_rows_f64.argtypes = [P(_Series), P(_Model), P(_Stream), vp, vp, i64, vp, vp]
+        L.abc_simulate_rows_f64.restype = ctypes.c_int32
         L.abc_trajectory_bands.argtypes = [vp, i64, ctypes.c_int32, vp, ctypes.c_int32, vp, vp]
         L.abc_trajectory_bands.restype = ctypes.c_int32
         L.abc_set_launch_config.argtypes = [ctypes.c_int32] * 3
@@ -417,6 +446,107 @@ class Mdn:
                                     ctypes.byref(st),
                                     int(first), int(n), _dptr(theta), _dptr(w), _stream_handle()))
         return theta, w
+
+
+def nearest_k(dist: torch.Tensor, k: int, *, theta: Optional[torch.Tensor] = None, first: int = 0,
+              seed: int = 0, domain: int = 1, series: int = 0, prior: Optional[_Prior] = None,
+              device="cuda"):
+    """The k samples with the smallest distances (ties to the lower index), in index order:
+    (idx [k] int64, theta [k,8], dist [k], kth [1] = k-th smallest distance)."""
+    n = int(dist.shape[0])
+    out_idx = torch.empty(k, dtype=torch.int64, device=device)
+    out_th = torch.empty((k, 8), dtype=torch.float32, device=device)
+    out_d = torch.empty(k, dtype=torch.float32, device=device)
+    kth = torch.empty(1, dtype=torch.float32, device=device)
+    pr = prior or make_prior()
+    st = make_stream(seed, domain, series)
+    _check(lib().abc_nearest_k(_dptr(dist), _dptr(theta), ctypes.byref(pr), ctypes.byref(st), n,
+                               int(first), int(k), _dptr(out_idx), _dptr(out_th), _dptr(out_d),
+                               _dptr(kth), _stream_handle()))
+    return out_idx, out_th, out_d, kth
+
+
+def nearest_k_rows(dist64: torch.Tensor, idx: torch.Tensor, theta: torch.Tensor, k: int,
+                   device="cuda"):
+    """k rows with the smallest (float64 distance, index), in index order."""
+    n = int(dist64.shape[0])
+    out_idx = torch.empty(k, dtype=torch.int64, device=device)
+    out_th = torch.empty((k, 8), dtype=torch.float32, device=device)
+    out_d = torch.empty(k, dtype=torch.float64, device=device)
+    _check(lib().abc_nearest_k_rows(_dptr(dist64), _dptr(idx), _dptr(theta), n, int(k),
+                                    _dptr(out_idx), _dptr(out_th), _dptr(out_d), _stream_handle()))
+    return out_idx, out_th, out_d
+
+
+def simulate_rows_f64(ser: DeviceSeries, seed: int, idx: torch.Tensor, theta: torch.Tensor, *,
+                      domain: int = 1, series: int = 0, flags: int = 0, noise_scale: float = 1.0,
+                      device="cuda") -> torch.Tensor:
+    """Float64 distances of rows (sample idx[q], theta[q])."""
+    n = int(idx.shape[0])
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    st = make_stream(seed, domain, series)
+    md = _Model(float(noise_scale), int(flags))
+    cs = ser.c()
+    _check(lib().abc_simulate_rows_f64(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(st),
+                                       _dptr(idx), _dptr(theta), n, _dptr(out), _stream_handle()))
+    return out
+
+
+def smc_config(n_particles: int, eps0: float, *, generations: int = 5, alpha: float = 0.5,
+               eps_min: float = 0.0, band_w: float = 0.02, chunk0: int = 1 << 14,
+               chunk_max: int = 1 << 20, max_samples: int = 1 << 34) -> _SmcConfig:
+    return _SmcConfig(int(n_particles), int(generations), float(alpha), float(eps0), float(eps_min),
+                      float(band_w), 0, int(chunk0), int(chunk_max), int(max_samples))
+
+
+def _gen_stats(st: _SmcGenStats) -> dict:
+    return {k: getattr(st, k) for k, _ in _SmcGenStats._fields_ if k != "pad"}
+
+
+def smc_generation(ser: DeviceSeries, cfg: _SmcConfig, seed: int, gen: int, prev=None, *,
+                   series: int = 0, flags: int = 0, noise_scale: float = 1.0,
+                   prior: Optional[_Prior] = None, want_ancestors: bool = False, device="cuda"):
+    """One ABC-SMC generation. prev = (theta [Np,8] f32, w [Np] f64, dist [Np] f64) device
+    tensors for gen >= 1. Returns a dict of device tensors + the generation statistics."""
+    N = cfg.n_particles
+    out = {"idx": torch.empty(N, dtype=torch.int64, device=device),
+           "theta": torch.empty((N, 8), dtype=torch.float32, device=device),
+           "w": torch.empty(N, dtype=torch.float64, device=device),
+           "dist": torch.empty(N, dtype=torch.float64, device=device),
+           "ancestors": torch.empty(N, dtype=torch.int32, device=device) if want_ancestors else None}
+    pt, pw, pd = prev if prev is not None else (None, None, None)
+    np_ = 0 if prev is None else int(pt.shape[0])
+    st = _SmcGenStats()
+    pr = prior or make_prior()
+    md = _Model(float(noise_scale), int(flags))
+    cs = ser.c()
+    _check(lib().abc_smc_generation(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(pr), int(seed),
+                                    int(series), int(gen), _dptr(pt), _dptr(pw), _dptr(pd), np_,
+                                    ctypes.byref(cfg), _dptr(out["idx"]), _dptr(out["theta"]),
+                                    _dptr(out["w"]), _dptr(out["dist"]), ctypes.byref(st),
+                                    _dptr(out["ancestors"]), _stream_handle()))
+    out["stats"] = _gen_stats(st)
+    return out
+
+
+def smc_run(ser: DeviceSeries, cfg: _SmcConfig, seed: int, *, series: int = 0, flags: int = 0,
+            noise_scale: float = 1.0, prior: Optional[_Prior] = None, device="cuda"):
+    """All generations of ABC-SMC; returns a list of per-generation dicts (views)."""
+    G, N = cfg.generations, cfg.n_particles
+    idx = torch.empty((G, N), dtype=torch.int64, device=device)
+    th = torch.empty((G, N, 8), dtype=torch.float32, device=device)
+    w = torch.empty((G, N), dtype=torch.float64, device=device)
+    d = torch.empty((G, N), dtype=torch.float64, device=device)
+    stats = (_SmcGenStats * G)()
+    done = ctypes.c_int32(0)
+    pr = prior or make_prior()
+    md = _Model(float(noise_scale), int(flags))
+    cs = ser.c()
+    _check(lib().abc_smc_run(ctypes.byref(cs), ctypes.byref(md), ctypes.byref(pr), int(seed),
+                             int(series), ctypes.byref(cfg), _dptr(idx), _dptr(th), _dptr(w), _dptr(d),
+                             stats, ctypes.byref(done), _stream_handle()))
+    return [{"idx": idx[t], "theta": th[t], "w": w[t], "dist": d[t], "stats": _gen_stats(stats[t])}
+            for t in range(done.value)]
 
 
 def trajectory_bands(traj: torch.Tensor, quantiles=(0.05, 0.5, 0.95)) -> torch.Tensor:

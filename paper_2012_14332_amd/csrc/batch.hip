@@ -352,7 +352,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
             const bool exited = l.acc > l.exit2;
             if (exited || t == l.T) {
                 if (!exited) {
-                    const float dd = sqrtf(l.acc) * 0.693147180559945309417f;
+                    const float dd = finish_distance_f32(l.acc, 0.693147180559945309417f);
                     const SeriesDesc& ds = desc_sh[l.series];
                     if (dd <= ds.eps_hi) {
                         const int pos = atomicAdd(&a.state[l.series].cand, 1);

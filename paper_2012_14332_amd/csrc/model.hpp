@@ -85,6 +85,14 @@ __device__ __forceinline__ void day_fields(uint4 w, uint32_t f[6])
 
 // Standard normals scaled by the noise scale s: the factor enters under the
 // Box-Muller square root, c = -2 ln(2) s^2, so it costs nothing per draw.
+// Final float32 distance from the squared-sum accumulator: one hardware
+// square root (about 1 ulp) times the unit scale (ln 2 for the log2-unit
+// log1p distance, 1 for raw counts).
+__device__ __forceinline__ float finish_distance_f32(float acc, float scale)
+{
+    return __builtin_amdgcn_sqrtf(acc) * scale;
+}
+
 __device__ __forceinline__ void normals_f32(uint4 w, float c, float z[5])
 {
     uint32_t f[6];

@@ -23,6 +23,8 @@ struct SimArgs {
     const float* theta;  // [n][8] or null -> prior draw
     float lo[8];
     float width[8];
+    float hi[8];         // support check of supplied theta (box != 0)
+    int32_t box;
     Key key;
     uint32_t domain;
     uint32_t series;
@@ -50,6 +52,15 @@ __device__ __forceinline__ void load_or_draw_theta(const SimArgs& a, bool prior,
         th[0] = x.x; th[1] = x.y; th[2] = x.z; th[3] = x.w;
         th[4] = y.x; th[5] = y.y; th[6] = y.z; th[7] = y.w;
     }
+}
+
+// Prior support of a supplied theta (closed box; NaN is outside).
+__device__ __forceinline__ bool outside_box(const SimArgs& a, const float th[8])
+{
+    bool out = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) out |= !(th[j] >= a.lo[j] && th[j] <= a.hi[j]);
+    return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -90,7 +101,7 @@ __device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, uint32_t 
     out.ga = r.ga; out.de = r.de; out.bh = r.bh; out.i0 = s0.I;
     out.c1base = ph.c1base; out.g3 = ph.g3; out.h3 = ph.h3; out.f3 = ph.f3;
     out.k = k;
-    out.pad = 0;
+    out.pad = (!PRIOR && a.box && outside_box(a, thv)) ? 1 : 0;  // 1: prior density zero
 }
 
 struct Lane {
@@ -130,7 +141,8 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t nchunks = (a.n + 63) >> 6;
     if (wg >= nchunks) return;
-    const int64_t Q = ((nchunks - 1 - wg) / nw + 1) << 6;  // queue positions of this wave
+    // queue positions of this wave (fits 32 bits: the host limits n per launch)
+    const uint32_t Q = (uint32_t)(((nchunks - 1 - wg) / nw + 1) << 6);
 
     const PhiloxSeries ps = philox_series(a.series, a.key);
     const float invP = 1.0f / (float)a.P;
@@ -139,8 +151,8 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     const uint32_t wdom = a.domain << 4;
 
     // the ring holds chunk j of this wave: sample offsets (wg + j nw) 64 + lane
-    auto fill = [&](int64_t j) {
-        const int64_t k = ((wg + j * nw) << 6) + lane;
+    auto fill = [&](uint32_t j) {
+        const int64_t k = ((wg + (int64_t)j * nw) << 6) + lane;
         Slot& sl = ring[lane];
         if (k < a.n)
             fill_slot<PRIOR>(a, k, ps.u0, sl);
@@ -148,8 +160,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
             sl.k = a.n;
     };
 
-    int64_t q_base = 0;
-    int64_t filled_j = -1;
+    // wave-uniform queue state, kept in scalar registers
+    uint32_t qb = 0;               // next queue position
+    uint32_t filled = 0xFFFFFFFFu; // chunk currently in the ring
     Lane L[SPL];
 #pragma unroll
     for (int j = 0; j < SPL; ++j) L[j].active = false;
@@ -161,19 +174,22 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
             uint64_t m = __ballot(!L[j].active);
-            while (m != 0ull && q_base < Q) {
-                const int64_t jc = q_base >> 6;
-                if (jc != filled_j) {
+            while (m != 0ull && qb < Q) {
+                const uint32_t jc = qb >> 6;
+                if (jc != filled) {
                     fill(jc);
-                    filled_j = jc;
+                    filled = jc;
                 }
-                const int avail = 64 - (int)(q_base & 63);
+                const uint32_t avail = 64u - (qb & 63u);
                 const bool inm = (m >> lane) & 1ull;
-                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
                 const bool take = inm && rank < avail;
                 if (take) {
-                    const Slot sl = ring[(q_base & 63) + rank];
-                    if (sl.k < a.n) {
+                    const Slot sl = ring[(qb & 63u) + rank];
+                    if (!PRIOR && sl.k < a.n && sl.pad != 0) {
+                        a.dist[sl.k] = INFINITY;
+                        if (a.dist64) a.dist64[sl.k] = (double)INFINITY;
+                    } else if (sl.k < a.n) {
                         Lane& l = L[j];
                         l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
                         l.s.A = a.A0; l.s.R = a.R0; l.s.D = a.D0; l.s.Ru = 0;
@@ -187,15 +203,15 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
                         l.active = true;
                     }
                 }
-                const int cnt = __popcll(m);
-                q_base += cnt < avail ? cnt : avail;
+                const uint32_t cnt = (uint32_t)__popcll(m);
+                qb = __builtin_amdgcn_readfirstlane(qb + (cnt < avail ? cnt : avail));
                 m = __ballot(inm && !take);  // lanes still without a position
             }
         }
         bool any = false;
 #pragma unroll
         for (int j = 0; j < SPL; ++j) any |= L[j].active;
-        if (__ballot(any) == 0ull && q_base >= Q) break;
+        if (__ballot(any) == 0ull && qb >= Q) break;
 
         // one day of every active slot
 #pragma unroll
@@ -224,13 +240,13 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
                     l.acc = fmaf(d, d, l.acc);
                 }
             }
-            ++days_done;
             const bool exited = l.acc > a.exit_f32;
             if (exited || t == T) {
-                const float dd = exited ? INFINITY : sqrtf(l.acc) * dscale;
+                const float dd = exited ? INFINITY : finish_distance_f32(l.acc, dscale);
                 a.dist[l.k] = dd;
                 if (a.dist64) a.dist64[l.k] = (double)dd;
                 l.active = false;
+                days_done += (uint32_t)t;
             } else {
                 l.t = t + 1;
             }
@@ -259,6 +275,11 @@ __global__ __launch_bounds__(SIM_BLOCK) void k_simulate_f64(SimArgs a)
     const uint64_t i = a.first + (uint64_t)k;
     float thv[8];
     load_or_draw_theta(a, PRIOR, k, i, thv);
+    if (!PRIOR && a.box && outside_box(a, thv)) {
+        a.dist[k] = INFINITY;
+        if (a.dist64) a.dist64[k] = (double)INFINITY;
+        return;
+    }
     const double dd = simulate_one_f64<NOISE, DIST>(thv, i, a.key, a.series, a.domain, a.P, a.A0,
                                                     a.R0, a.D0, a.T, (double)a.scale, lds_d,
                                                     a.exit_f64);
@@ -370,6 +391,30 @@ __global__ __launch_bounds__(256) void k_recheck_compact(RecheckArgs r)
 __global__ void k_zero_i32(int32_t* p)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// float64 distances of listed rows (sample idx[q], theta[q]), one lane each.
+struct RowsArgs {
+    SimArgs sim;
+    const int64_t* idx;
+    double* dist64;
+};
+
+template <int NOISE, int DIST>
+__global__ __launch_bounds__(64) void k_rows_f64(RowsArgs r)
+{
+    extern __shared__ double lds_w[];
+    const SimArgs& a = r.sim;
+    stage_obs_f64<DIST>(a.obs, a.T, lds_w);
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n) return;
+    float thv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) thv[j] = a.theta[8 * q + j];
+    r.dist64[q] = simulate_one_f64<NOISE, DIST>(thv, (uint64_t)r.idx[q], a.key, a.series, a.domain,
+                                                a.P, a.A0, a.R0, a.D0, a.T, (double)a.scale, lds_w,
+                                                (double)INFINITY);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,7 +613,7 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
     if ((rc = check_series(ser, true))) return rc;
     if ((rc = check_model(model))) return rc;
     if ((rc = check_stream_sel(st))) return rc;
-    ABC_REQUIRE(n >= 0, "n = %lld < 0", (long long)n);
+    ABC_REQUIRE(n >= 0 && n <= ((int64_t)1 << 36), "n = %lld outside [0, 2^36]", (long long)n);
     ABC_REQUIRE(!(eps_exit < 0.0f) && !isnan(eps_exit), "eps_exit must be >= 0 (or +INF)");
     if (n == 0) return ABC_OK;
     ABC_REQUIRE(dist != nullptr, "dist is NULL");
@@ -580,6 +625,11 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
             ABC_REQUIRE(prior->lo[k] >= 0.0f, "model rates must be non-negative: prior lo[%d] < 0", k);
     } else {
         ABC_REQUIRE(aligned16(theta), "theta must be 16-byte aligned");
+        if (model->flags & ABC_SUPPORT) {
+            if ((rc = prior_lo_width(prior, a.lo, a.width))) return rc;
+            for (int k = 0; k < 8; ++k) a.hi[k] = prior->hi[k];
+            a.box = 1;
+        }
     }
     fill_series(a, ser, model, st, first, n);
     a.theta = theta;
@@ -728,4 +778,34 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     hipError_t e = hipFreeAsync(scratch, s);
     if (rc == ABC_OK && e != hipSuccess) return set_error(ABC_EHIP, "hipFreeAsync: %s", hipGetErrorString(e));
     return rc;
+}
+
+extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model* model,
+                                            const abc_stream* st, const int64_t* idx,
+                                            const float* theta, int64_t n, double* dist64,
+                                            void* stream)
+{
+    abc_status rc;
+    if ((rc = check_series(ser, true))) return rc;
+    if ((rc = check_model(model))) return rc;
+    if ((rc = check_stream_sel(st))) return rc;
+    ABC_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return ABC_OK;
+    ABC_REQUIRE(idx && theta && dist64, "idx/theta/dist64 NULL");
+    const size_t lds = sizeof(double) * 3 * (size_t)ser->T;
+    ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 path");
+    RowsArgs r{};
+    fill_series(r.sim, ser, model, st, 0, n);
+    r.sim.theta = theta;
+    r.idx = idx;
+    r.dist64 = dist64;
+    const hipStream_t s = as_stream(stream);
+    const int noise = (model->flags & ABC_NOISE_LITERAL) ? 1 : 0;
+    const int distm = (model->flags & ABC_DIST_RAW) ? 1 : 0;
+    const dim3 g((unsigned)((n + 63) / 64)), b(64);
+    if (noise == 0 && distm == 0) hipLaunchKernelGGL((k_rows_f64<0, 0>), g, b, lds, s, r);
+    else if (noise == 0) hipLaunchKernelGGL((k_rows_f64<0, 1>), g, b, lds, s, r);
+    else if (distm == 0) hipLaunchKernelGGL((k_rows_f64<1, 0>), g, b, lds, s, r);
+    else hipLaunchKernelGGL((k_rows_f64<1, 1>), g, b, lds, s, r);
+    return check_launch("k_rows_f64");
 }

@@ -1,0 +1,626 @@
+// ABC-SMC: population Monte Carlo ABC over a decreasing tolerance sequence
+// (Sec. 2.2 names the method; the algorithm is that of Beaumont, Cornuet,
+// Marin & Robert, Biometrika 2009, with the adaptive quantile tolerance of
+// Del Moral, Doucet & Jasra, Stat. Comput. 2012), and its C-ABI entry points
+// abc_smc_generation and abc_smc_run.
+//
+// One generation t >= 1 on the device:
+//   k_smc_setup     one workgroup: weighted mean and covariance of generation
+//                   t-1 (left-to-right float64 sums), Sigma = 2 cov, its
+//                   Cholesky factor L, running weight sums C_j, whitened
+//                   particles y_j = L^-1 theta_j, and eps_t from an LDS sort of
+//                   the previous distances.
+//   k_smc_propose   one lane per candidate: ancestor by binary search of
+//                   u C_{N-1} in C, theta* = theta_anc + L z (float64, rounded
+//                   to float32).
+//   simulate / compact / float64 band decision: the rejection-ABC kernels,
+//                   with the prior-support check (candidates outside the box
+//                   are rejected unsimulated); the first N accepted by index
+//                   form the population.
+//   float64 distances of the population (for eps_{t+1}), abc_simulate_rows_f64.
+//   k_smc_sums      importance-weight denominators sum_j W_j exp(-|y_i - y_j|^2 / 2),
+//                   split over the previous particles for parallelism.
+//   k_smc_finish    w_i = 1 / denominator, W = w / sum w (left to right), ESS.
+// Generation 0 is plain rejection ABC from the prior on the ABC stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "model.hpp"
+#include "philox.hpp"
+
+namespace abc {
+
+constexpr int SMC_MAX_N = 8192;
+constexpr uint32_t DOMAIN_SMC = 7;
+constexpr uint32_t DOMAIN_ABC_PLAIN = 1;
+
+struct SmcState {
+    double L[64];     // row-major, lower triangle
+    double mean[8];
+    double sigma[64]; // 2 x weighted covariance
+    double total;     // C_{N-1}
+    double eps64;     // order statistic before the floor and the float32 rounding
+    float eps;
+    int32_t status;   // 0 ok, 1 Sigma not positive definite
+};
+
+struct SetupArgs {
+    const float* theta;   // [N][8]
+    const double* w;      // [N] normalised weights
+    const double* dist;   // [N] float64 distances
+    int32_t N;
+    int32_t kth;          // ceil(alpha N), 1-based
+    float eps_min;
+    SmcState* st;
+    double* C;            // [N]
+    double* y;            // [N][8]
+};
+
+// One workgroup of 1024 threads. Sums run left to right over the particles in
+// single lanes so that every rounding matches the plainly written definition.
+__global__ __launch_bounds__(1024) void k_smc_setup(SetupArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ double sd[SMC_MAX_N];
+    __shared__ double m_sh[8];
+    __shared__ double v_sh;
+    const int tid = threadIdx.x;
+    const int N = a.N;
+    // phase A: running weight sums (lane 64), sums of W theta (lanes 0..7)
+    if (tid == 64) {
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) {
+            s = s + a.w[j];
+            a.C[j] = s;
+        }
+        v_sh = s;
+        a.st->total = s;
+    }
+    if (tid < 8) {
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) s = s + a.w[j] * (double)a.theta[8 * j + tid];
+        m_sh[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 8) {
+        m_sh[tid] = m_sh[tid] / v_sh;
+        a.st->mean[tid] = m_sh[tid];
+    }
+    __syncthreads();
+    // phase B: covariance entries (a >= b), one lane each
+    if (tid < 36) {
+        int r = 0;
+        while ((r + 1) * (r + 2) / 2 <= tid) ++r;
+        const int c = tid - r * (r + 1) / 2;
+        const double mr = m_sh[r], mc = m_sh[c];
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) {
+            const double dr = (double)a.theta[8 * j + r] - mr;
+            const double dc = (double)a.theta[8 * j + c] - mc;
+            s = s + a.w[j] * (dr * dc);
+        }
+        const double sg = 2.0 * (s / v_sh);
+        a.st->sigma[8 * r + c] = sg;
+        a.st->sigma[8 * c + r] = sg;
+    }
+    // previous distances into LDS, padded with +inf to a power of two
+    int npow = 1;
+    while (npow < N) npow <<= 1;
+    for (int j = tid; j < npow; j += blockDim.x) sd[j] = j < N ? a.dist[j] : (double)INFINITY;
+    __syncthreads();
+    // phase C: Cholesky-Banachiewicz, row by row (lane 0)
+    if (tid == 0) {
+        double L[64];
+        int bad = 0;
+        for (int i = 0; i < 64; ++i) L[i] = 0.0;
+        for (int i = 0; i < 8 && !bad; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double s = a.st->sigma[8 * i + j];
+                for (int k = 0; k < j; ++k) s = s - L[8 * i + k] * L[8 * j + k];
+                if (i == j) {
+                    if (!(s > 0.0)) {
+                        bad = 1;
+                        break;
+                    }
+                    L[8 * i + i] = sqrt(s);
+                } else {
+                    L[8 * i + j] = s / L[8 * j + j];
+                }
+            }
+        for (int i = 0; i < 64; ++i) a.st->L[i] = L[i];
+        a.st->status = bad;
+    }
+    // phase D: bitonic sort of the distances (ascending)
+    for (int k = 2; k <= npow; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = tid; t < npow; t += blockDim.x) {
+                const int p = t ^ j;
+                if (p > t) {
+                    const bool up = (t & k) == 0;
+                    const double x = sd[t], yv = sd[p];
+                    if ((x > yv) == up) {
+                        sd[t] = yv;
+                        sd[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    if (tid == 0) {
+        const double q = sd[a.kth - 1];
+        a.st->eps64 = q;
+        const double f = (double)a.eps_min;
+        a.st->eps = (float)(q > f ? q : f);
+    }
+    __syncthreads();
+    // phase E: whitened particles y_j = L^-1 theta_j (forward substitution)
+    if (a.st->status == 0) {
+        double L[36];
+        for (int i = 0, q = 0; i < 8; ++i)
+            for (int j = 0; j <= i; ++j) L[q++] = a.st->L[8 * i + j];
+        for (int j = tid; j < N; j += blockDim.x) {
+            double yv[8];
+            for (int r = 0, q = 0; r < 8; ++r) {
+                double s = (double)a.theta[8 * j + r];
+                for (int k = 0; k < r; ++k) s = s - L[q + k] * yv[k];
+                yv[r] = s / L[q + r];
+                q += r + 1;
+            }
+            for (int r = 0; r < 8; ++r) a.y[8 * j + r] = yv[r];
+        }
+    }
+}
+
+struct ProposeArgs {
+    Key key;
+    uint32_t series;      // series | gen << 16
+    uint64_t first;
+    int64_t n;
+    const float* prev;    // [N][8]
+    const double* C;      // [N]
+    int32_t N;
+    const SmcState* st;
+    float* theta;         // [n][8]
+    int32_t* anc;         // [n] or null
+};
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1)
+{
+#pragma clang fp contract(off)
+    const double u1 = ((double)a + 1.0) * 0x1p-32;
+    const double r = sqrt(-2.0 * log(u1));
+    const double phi = 6.283185307179586 * ((double)b * 0x1p-32);
+    z0 = r * cos(phi);
+    z1 = r * sin(phi);
+}
+
+__global__ __launch_bounds__(256) void k_smc_propose(ProposeArgs a)
+{
+#pragma clang fp contract(off)
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const uint64_t i = a.first + (uint64_t)k;
+    const uint4 w0 = stream_words(a.key, i, a.series, ctr_word3(0, DOMAIN_SMC, 0));
+    const uint4 w1 = stream_words(a.key, i, a.series, ctr_word3(0, DOMAIN_SMC, 1));
+    const uint4 w2 = stream_words(a.key, i, a.series, ctr_word3(0, DOMAIN_SMC, 2));
+    const double u = (double)(((uint64_t)w0.x << 21) | (uint64_t)(w0.y >> 11)) * 0x1p-53;
+    double z[8];
+    box_muller(w0.z, w0.w, z[0], z[1]);
+    box_muller(w1.x, w1.y, z[2], z[3]);
+    box_muller(w1.z, w1.w, z[4], z[5]);
+    box_muller(w2.x, w2.y, z[6], z[7]);
+    // smallest j with C_j > u C_{N-1}
+    const double target = u * a.C[a.N - 1];
+    int lo = 0, hi = a.N;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.C[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    const int j = lo < a.N ? lo : a.N - 1;
+    float out[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        double acc = (double)a.prev[8 * j + r];
+#pragma unroll
+        for (int c = 0; c <= r; ++c) acc = acc + a.st->L[8 * r + c] * z[c];
+        out[r] = (float)acc;
+    }
+    float4* p = reinterpret_cast<float4*>(a.theta + 8 * k);
+    p[0] = make_float4(out[0], out[1], out[2], out[3]);
+    p[1] = make_float4(out[4], out[5], out[6], out[7]);
+    if (a.anc) a.anc[k] = j;
+}
+
+// Number of rows of theta [m][8] inside the closed box (added to *count).
+__global__ __launch_bounds__(256) void k_smc_count_box(const float* theta, int64_t m, abc_prior box,
+                                                       unsigned long long* count)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool in = false;
+    if (k < m) {
+        in = true;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float x = theta[8 * k + j];
+            in &= x >= box.lo[j] && x <= box.hi[j];
+        }
+    }
+    const uint64_t bal = __ballot(in);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(count, (unsigned long long)__popcll(bal));
+}
+
+// ancestors of the kept candidate rows (row r is candidate oidx[r] - first of the chunk)
+__global__ __launch_bounds__(256) void k_smc_gather_anc(const int64_t* oidx, int64_t take, int64_t first,
+                                                        const int32_t* anc_chunk, int32_t* out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < take) out[r] = anc_chunk[oidx[r] - first];
+}
+
+struct SumsArgs {
+    const float* theta;   // new population [N][8]
+    int32_t N;
+    const double* y;      // previous, whitened [Np][8]
+    const double* w;      // previous normalised weights [Np]
+    int32_t Np;
+    int32_t per_split;    // previous particles per blockIdx.y
+    const SmcState* st;
+    double* partial;      // [splits][N]
+};
+
+constexpr int SUMS_BLOCK = 256;
+
+__global__ __launch_bounds__(SUMS_BLOCK) void k_smc_sums(SumsArgs a)
+{
+    __shared__ double ys[SUMS_BLOCK][9];  // y_j (8) and W_j
+    const int i = blockIdx.x * SUMS_BLOCK + threadIdx.x;
+    const int j0 = blockIdx.y * a.per_split;
+    const int j1 = min(j0 + a.per_split, a.Np);
+    double yi[8];
+    if (i < a.N) {
+        const double* L = a.st->L;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            double s = (double)a.theta[8 * i + r];
+#pragma unroll
+            for (int c = 0; c < r; ++c) s -= L[8 * r + c] * yi[c];
+            yi[r] = s / L[8 * r + r];
+        }
+    }
+    double acc = 0.0;
+    for (int t0 = j0; t0 < j1; t0 += SUMS_BLOCK) {
+        const int j = t0 + threadIdx.x;
+        if (j < j1) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) ys[threadIdx.x][r] = a.y[8 * j + r];
+            ys[threadIdx.x][8] = a.w[j];
+        }
+        __syncthreads();
+        const int m = min(SUMS_BLOCK, j1 - t0);
+        if (i < a.N)
+            for (int jj = 0; jj < m; ++jj) {
+                double q = 0.0;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const double d = yi[r] - ys[jj][r];
+                    q = fma(d, d, q);
+                }
+                acc = fma(ys[jj][8], exp(-0.5 * q), acc);
+            }
+        __syncthreads();
+    }
+    if (i < a.N) a.partial[(int64_t)blockIdx.y * a.N + i] = acc;
+}
+
+// w_i = 1 / sum_s partial[s][i]; W = w / (w_0 + ... + w_{N-1}); ESS = 1 / sum W^2.
+__global__ __launch_bounds__(1024) void k_smc_finish(const double* partial, int32_t splits,
+                                                     int32_t N, double* W, double* ess)
+{
+#pragma clang fp contract(off)
+    __shared__ double v_sh;
+    __shared__ double red[1024];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double s = 0.0;
+        for (int sp = 0; sp < splits; ++sp) s = s + partial[(int64_t)sp * N + i];
+        W[i] = 1.0 / s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < N; ++i) s = s + W[i];
+        v_sh = s;
+    }
+    __syncthreads();
+    double q = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const double x = W[i] / v_sh;
+        W[i] = x;
+        q = q + x * x;
+    }
+    red[threadIdx.x] = q;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *ess = 1.0 / red[0];
+}
+
+__global__ __launch_bounds__(256) void k_smc_equal(double* W, int32_t N, double* ess)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) W[i] = 1.0 / (double)N;
+    if (i == 0) *ess = (double)N;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+};
+
+static abc_status check_cfg(const abc_smc_config* c)
+{
+    ABC_REQUIRE(c != nullptr, "config is NULL");
+    ABC_REQUIRE(c->n_particles >= 2 && c->n_particles <= SMC_MAX_N, "n_particles must be in [2, %d]",
+                SMC_MAX_N);
+    ABC_REQUIRE(c->generations >= 1 && c->generations <= 65535, "generations must be in [1, 65535]");
+    ABC_REQUIRE(c->alpha > 0.0 && c->alpha <= 1.0, "alpha must be in (0, 1]");
+    ABC_REQUIRE(isfinite(c->eps0) && c->eps0 >= 0.0f, "eps0 must be finite and >= 0");
+    ABC_REQUIRE(isfinite(c->eps_min) && c->eps_min >= 0.0f, "eps_min must be finite and >= 0");
+    ABC_REQUIRE(isfinite(c->band_w) && c->band_w >= 0.0f && c->band_w < 1.0f, "band_w must be in [0, 1)");
+    ABC_REQUIRE(c->chunk0 >= 1 && c->chunk_max >= c->chunk0 && c->chunk_max <= ((int64_t)1 << 26),
+                "need 1 <= chunk0 <= chunk_max <= 2^26");
+    ABC_REQUIRE(c->max_samples >= 1, "max_samples must be >= 1");
+    return ABC_OK;
+}
+
+static abc_status sync(hipStream_t s)
+{
+    ABC_HIP(hipStreamSynchronize(s));
+    return ABC_OK;
+}
+
+}  // namespace abc
+
+using namespace abc;
+
+extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model* model,
+                                         const abc_prior* prior, uint64_t seed, uint32_t series,
+                                         int32_t gen, const float* prev_theta,
+                                         const double* prev_w, const double* prev_dist,
+                                         int32_t n_prev, const abc_smc_config* cfg, int64_t* idx,
+                                         float* theta, double* w, double* dist,
+                                         abc_smc_gen_stats* stats, int32_t* ancestors,
+                                         void* stream)
+{
+    abc_status rc;
+    if ((rc = check_series(ser, true))) return rc;
+    if ((rc = check_model(model))) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    float lo[8], width[8];
+    if ((rc = prior_lo_width(prior, lo, width))) return rc;
+    for (int k = 0; k < 8; ++k)
+        ABC_REQUIRE(prior->lo[k] >= 0.0f, "model rates must be non-negative: prior lo[%d] < 0", k);
+    ABC_REQUIRE(series < 65536u, "series must be < 65536 (the generation shares its counter word)");
+    ABC_REQUIRE(gen >= 0 && gen <= 65535, "gen must be in [0, 65535]");
+    ABC_REQUIRE(idx && theta && w && dist && stats, "NULL output");
+    ABC_REQUIRE((reinterpret_cast<uintptr_t>(theta) & 15u) == 0, "theta must be 16-byte aligned");
+    if (gen > 0) {
+        ABC_REQUIRE(prev_theta && prev_w && prev_dist, "generation >= 1 needs the previous population");
+        ABC_REQUIRE(n_prev >= 2 && n_prev <= SMC_MAX_N, "n_prev must be in [2, %d]", SMC_MAX_N);
+    }
+    ABC_REQUIRE(!(model->flags & ABC_FP64), "ABC-SMC runs the float32 path with the float64 band decision");
+    const hipStream_t s = as_stream(stream);
+    const int N = cfg->n_particles;
+    const int64_t cap = cfg->chunk_max;
+    const uint32_t ss = gen == 0 ? series : (series | ((uint32_t)gen << 16));
+    const abc_stream st{seed, gen == 0 ? DOMAIN_ABC_PLAIN : DOMAIN_SMC, ss};
+    abc_model md = *model;
+    if (gen > 0) md.flags |= ABC_SUPPORT;
+
+    // workspace
+    const int np = gen > 0 ? n_prev : 1;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_state = 0;
+    const size_t o_C = o_state + up(sizeof(SmcState));
+    const size_t o_y = o_C + up(sizeof(double) * np);
+    const size_t o_cth = o_y + up(sizeof(double) * 8 * np);
+    const size_t o_cd = o_cth + up(sizeof(float) * 8 * cap);
+    const size_t o_oidx = o_cd + up(sizeof(float) * cap);
+    const size_t o_oth = o_oidx + up(sizeof(int64_t) * cap);
+    const size_t o_od = o_oth + up(sizeof(float) * 8 * cap);
+    const size_t o_cnt = o_od + up(sizeof(float) * cap);
+    const size_t o_box = o_cnt + 256;
+    const size_t o_ess = o_box + 256;
+    const size_t o_anc = o_ess + 256;
+    const size_t total = o_anc + up(sizeof(int32_t) * cap);
+    DevBuf ws;
+    ws.s = s;
+    ABC_HIP(hipMallocAsync(&ws.p, total, s));
+    char* base = static_cast<char*>(ws.p);
+    SmcState* dstate = reinterpret_cast<SmcState*>(base + o_state);
+    double* dC = reinterpret_cast<double*>(base + o_C);
+    double* dy = reinterpret_cast<double*>(base + o_y);
+    float* cth = reinterpret_cast<float*>(base + o_cth);
+    float* cd = reinterpret_cast<float*>(base + o_cd);
+    int64_t* oidx = reinterpret_cast<int64_t*>(base + o_oidx);
+    float* oth = reinterpret_cast<float*>(base + o_oth);
+    float* od = reinterpret_cast<float*>(base + o_od);
+    int64_t* dcnt = reinterpret_cast<int64_t*>(base + o_cnt);
+    unsigned long long* dbox = reinterpret_cast<unsigned long long*>(base + o_box);
+    double* dess = reinterpret_cast<double*>(base + o_ess);
+    int32_t* danc = reinterpret_cast<int32_t*>(base + o_anc);
+
+    float eps = cfg->eps0;
+    if (gen > 0) {
+        SetupArgs sa{};
+        sa.theta = prev_theta;
+        sa.w = prev_w;
+        sa.dist = prev_dist;
+        sa.N = n_prev;
+        int kth = (int)ceil(cfg->alpha * (double)n_prev);
+        sa.kth = kth < 1 ? 1 : (kth > n_prev ? n_prev : kth);
+        sa.eps_min = cfg->eps_min;
+        sa.st = dstate;
+        sa.C = dC;
+        sa.y = dy;
+        hipLaunchKernelGGL(k_smc_setup, dim3(1), dim3(1024), 0, s, sa);
+        if ((rc = check_launch("k_smc_setup"))) return rc;
+        struct {
+            float eps;
+            int32_t status;
+        } h{};
+        ABC_HIP(hipMemcpyAsync(&h, &dstate->eps, sizeof h, hipMemcpyDeviceToHost, s));
+        if ((rc = sync(s))) return rc;
+        if (h.status)
+            return set_error(ABC_EINVAL, "generation %d: kernel covariance of the previous population "
+                             "is not positive definite", gen);
+        eps = h.eps;
+    }
+    ABC_HIP(hipMemsetAsync(dbox, 0, sizeof(unsigned long long), s));
+
+    const float e_hi = cfg->band_w > 0.0f ? (float)((double)eps * (1.0 + (double)cfg->band_w)) : eps;
+    int got = 0;
+    int64_t first = 0, chunk = cfg->chunk0, proposed = 0, samples = 0;
+    while (got < N) {
+        if (first >= cfg->max_samples)
+            return set_error(ABC_EOVERFLOW, "generation %d: %d of %d particles after %lld candidates",
+                             gen, got, N, (long long)first);
+        const float* th_in = nullptr;
+        if (gen > 0) {
+            ProposeArgs pa{};
+            pa.key = make_key(seed);
+            pa.series = ss;
+            pa.first = (uint64_t)first;
+            pa.n = chunk;
+            pa.prev = prev_theta;
+            pa.C = dC;
+            pa.N = n_prev;
+            pa.st = dstate;
+            pa.theta = cth;
+            pa.anc = ancestors ? danc : nullptr;
+            hipLaunchKernelGGL(k_smc_propose, dim3((unsigned)((chunk + 255) / 256)), dim3(256), 0, s, pa);
+            if ((rc = check_launch("k_smc_propose"))) return rc;
+            th_in = cth;
+        }
+        if ((rc = abc_simulate_distance(ser, &md, &st, th_in, prior, (uint64_t)first, chunk, e_hi, cd,
+                                        nullptr, nullptr, stream)))
+            return rc;
+        if ((rc = abc_accept_compact(cd, th_in, nullptr, prior, &st, chunk, (uint64_t)first, e_hi, cap,
+                                     oidx, oth, od, nullptr, dcnt, stream)))
+            return rc;
+        if (cfg->band_w > 0.0f &&
+            (rc = abc_recheck_band(ser, &md, &st, eps, cfg->band_w, cap, oidx, oth, od, nullptr, dcnt,
+                                   nullptr, stream)))
+            return rc;
+        int64_t c = 0;
+        ABC_HIP(hipMemcpyAsync(&c, dcnt, sizeof c, hipMemcpyDeviceToHost, s));
+        if ((rc = sync(s))) return rc;
+        if (c > cap) return set_error(ABC_EOVERFLOW, "candidate count %lld exceeds chunk_max", (long long)c);
+        const int take = (int)(c < (int64_t)(N - got) ? c : (int64_t)(N - got));
+        int64_t used = chunk;  // candidates of this chunk that the population consumes
+        if (take > 0) {
+            ABC_HIP(hipMemcpyAsync(idx + got, oidx, sizeof(int64_t) * take, hipMemcpyDeviceToDevice, s));
+            ABC_HIP(hipMemcpyAsync(theta + 8 * (size_t)got, oth, sizeof(float) * 8 * take,
+                                   hipMemcpyDeviceToDevice, s));
+            if (gen > 0 && ancestors) {
+                hipLaunchKernelGGL(k_smc_gather_anc, dim3((unsigned)((take + 255) / 256)), dim3(256), 0,
+                                   s, oidx, take, first, danc, ancestors + got);
+                if ((rc = check_launch("k_smc_gather_anc"))) return rc;
+            }
+        }
+        if (got + take == N) {
+            int64_t last = 0;
+            ABC_HIP(hipMemcpyAsync(&last, oidx + take - 1, sizeof last, hipMemcpyDeviceToHost, s));
+            if ((rc = sync(s))) return rc;
+            samples = last + 1;
+            used = samples - first;
+        }
+        if (gen > 0) {
+            hipLaunchKernelGGL(k_smc_count_box, dim3((unsigned)((used + 255) / 256)), dim3(256), 0, s,
+                               cth, used, *prior, dbox);
+            if ((rc = check_launch("k_smc_count_box"))) return rc;
+        }
+        got += take;
+        proposed += chunk;
+        first += chunk;
+        chunk = chunk * 2 < cfg->chunk_max ? chunk * 2 : cfg->chunk_max;
+    }
+
+    // float64 distances of the population
+    if ((rc = abc_simulate_rows_f64(ser, model, &st, idx, theta, N, dist, stream))) return rc;
+    // weights
+    if (gen == 0) {
+        hipLaunchKernelGGL(k_smc_equal, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w, N, dess);
+        if ((rc = check_launch("k_smc_equal"))) return rc;
+    } else {
+        const int bx = (N + SUMS_BLOCK - 1) / SUMS_BLOCK;
+        int splits = 2048 / bx;
+        const int max_splits = (n_prev + SUMS_BLOCK - 1) / SUMS_BLOCK;
+        if (splits > max_splits) splits = max_splits;
+        if (splits < 1) splits = 1;
+        const int per = (n_prev + splits - 1) / splits;
+        DevBuf part;
+        part.s = s;
+        ABC_HIP(hipMallocAsync(&part.p, sizeof(double) * (size_t)splits * N, s));
+        SumsArgs sa{};
+        sa.theta = theta;
+        sa.N = N;
+        sa.y = dy;
+        sa.w = prev_w;
+        sa.Np = n_prev;
+        sa.per_split = per;
+        sa.st = dstate;
+        sa.partial = static_cast<double*>(part.p);
+        hipLaunchKernelGGL(k_smc_sums, dim3(bx, splits), dim3(SUMS_BLOCK), 0, s, sa);
+        if ((rc = check_launch("k_smc_sums"))) return rc;
+        hipLaunchKernelGGL(k_smc_finish, dim3(1), dim3(1024), 0, s, sa.partial, splits, N, w, dess);
+        if ((rc = check_launch("k_smc_finish"))) return rc;
+    }
+    unsigned long long inbox = 0;
+    double ess = 0.0;
+    ABC_HIP(hipMemcpyAsync(&inbox, dbox, sizeof inbox, hipMemcpyDeviceToHost, s));
+    ABC_HIP(hipMemcpyAsync(&ess, dess, sizeof ess, hipMemcpyDeviceToHost, s));
+    if ((rc = sync(s))) return rc;
+    stats->eps = eps;
+    stats->pad = 0;
+    stats->samples = samples;
+    stats->in_support = gen == 0 ? samples : (int64_t)inbox;
+    stats->proposed = proposed;
+    stats->ess = ess;
+    return ABC_OK;
+}
+
+extern "C" abc_status abc_smc_run(const abc_series* ser, const abc_model* model,
+                                  const abc_prior* prior, uint64_t seed, uint32_t series,
+                                  const abc_smc_config* cfg, int64_t* idx, float* theta, double* w,
+                                  double* dist, abc_smc_gen_stats* stats, int32_t* gens_done,
+                                  void* stream)
+{
+    abc_status rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    ABC_REQUIRE(gens_done != nullptr && stats != nullptr, "NULL output");
+    *gens_done = 0;
+    const int N = cfg->n_particles;
+    for (int t = 0; t < cfg->generations; ++t) {
+        if (t > 0 && cfg->eps_min > 0.0f && stats[t - 1].eps <= cfg->eps_min) break;
+        const size_t o = (size_t)t * N, op = (size_t)(t - 1) * N;
+        rc = abc_smc_generation(ser, model, prior, seed, series, t,
+                                t ? theta + 8 * op : nullptr, t ? w + op : nullptr,
+                                t ? dist + op : nullptr, t ? N : 0, cfg, idx + o, theta + 8 * o,
+                                w + o, dist + o, stats + t, nullptr, stream);
+        if (rc) return rc;
+        *gens_done = t + 1;
+    }
+    return ABC_OK;
+}

@@ -94,6 +94,49 @@ class PlainABC:
         return PlainResult(idx, th, d, cnt, mean, cov, nre)
 
 
+@dataclasses.dataclass
+class NearestResult:
+    idx: torch.Tensor      # [k] int64, index order
+    theta: torch.Tensor    # [k, 8]
+    dist: torch.Tensor     # [k] float64
+    mean: torch.Tensor     # [8] float64
+    cov: torch.Tensor      # [8, 8] float64
+    candidates: int        # rows decided in float64
+
+
+class NearestABC:
+    """Keep the k nearest of n prior samples (the single-country workload):
+    float32 simulation of every day, device nearest-k, then the float64
+    decision -- every sample within (1 + band_w) of the k-th float32 distance
+    is simulated again in float64 and the k nearest of those by (float64
+    distance, index) are kept; float64 moments of their theta."""
+
+    def __init__(self, ser: abc.DeviceSeries, seed: int, n: int, k: int, *, series: int = 0,
+                 band_w: float = DEFAULT_BAND, capacity: int = 1 << 16, device="cuda"):
+        self.ser, self.seed, self.n, self.k = ser, int(seed), int(n), int(k)
+        self.series, self.band_w, self.cap = int(series), float(band_w), int(capacity)
+        self.dist = torch.empty(self.n, dtype=torch.float32, device=device)
+        self.device = device
+
+    def run(self, first: int = 0) -> NearestResult:
+        abc.simulate_distance(self.ser, self.n, self.seed, first=first, series=self.series,
+                              out=self.dist, device=self.device)
+        _, _, _, kth = abc.nearest_k(self.dist, self.k, first=first, seed=self.seed,
+                                     series=self.series, device=self.device)
+        tau = float(kth.item()) * (1.0 + self.band_w)
+        cidx, cth, _, _, cnt = abc.accept_compact(self.dist, tau, self.cap, first=first,
+                                                  seed=self.seed, series=self.series,
+                                                  device=self.device)
+        c = int(cnt.item())
+        if c > self.cap:
+            raise abc.AbcError("nearest-k band holds %d rows, capacity %d" % (c, self.cap))
+        d64 = abc.simulate_rows_f64(self.ser, self.seed, cidx[:c], cth[:c], series=self.series,
+                                    device=self.device)
+        idx, th, d = abc.nearest_k_rows(d64, cidx[:c], cth[:c], self.k, device=self.device)
+        mean, cov = abc.posterior_moments(th, device=self.device)
+        return NearestResult(idx, th, d, mean, cov, c)
+
+
 # ----------------------------------------------------------------------------
 # learned proposal (importance-weighted rejection ABC)
 # ----------------------------------------------------------------------------
