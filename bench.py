@@ -306,6 +306,7 @@ def main():
     ap.add_argument("--lam", type=float, default=0.1)
     ap.add_argument("--inflate", type=float, default=3.0)
     ap.add_argument("--compare-quota", type=int, default=1000)
+    ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")
     ap.add_argument("--no-smc", action="store_true")
     ap.add_argument("--smc-particles", type=int, default=4096)
     ap.add_argument("--smc-generations", type=int, default=8)
@@ -333,6 +334,8 @@ def main():
     abc.lib()
     if args.launch:
         abc.set_launch_config(*[int(x) for x in args.launch.split(",")])
+    if args.refill_min:
+        abc.set_refill_min(args.refill_min)
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -427,6 +430,7 @@ def main():
             "eps": eps,
             "band_w": args.band,
             "launch_config": list(abc.get_launch_config()),
+            "refill_min": abc.get_refill_min(),
         },
         "trajectories_per_s": traj / wall,
         "sim_days_per_s_effective": eff_days / wall,

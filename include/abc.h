@@ -221,11 +221,20 @@ ABC_API abc_status abc_posterior_moments(const float* theta, const float* weight
  * by the calling thread (the autotuner's knob): spl = independent samples
  * per lane (1, 2, 4 or 8; more than 1 only for the default noise and
  * distance), block = workgroup size (multiple of 64 in [64, 1024/spl]),
- * blocks_per_cu = resident workgroups per compute unit (1..64). 0 selects the
- * default (1, 512, 4). Results never depend on these settings, only speed.
+ * blocks_per_cu = resident workgroups per compute unit (1..64). A 0 selects
+ * that argument's default: spl 1, block 1024 / spl, blocks_per_cu 1. Results
+ * never depend on these settings, only speed.
  */
 ABC_API abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu);
 ABC_API abc_status abc_get_launch_config(int32_t* spl, int32_t* block, int32_t* blocks_per_cu);
+
+/* Lane-refill threshold of the float32 refill kernels (abc_simulate_distance
+ * and abc_batch_run) for the calling thread: a wavefront refills its idle
+ * lanes from its queue once at least `lanes` of its 64 lanes are idle
+ * (1 = at every step; default 8). Results never depend on it.
+ * Errors: ABC_EINVAL unless 1 <= lanes <= 64 (0 selects the default). */
+ABC_API abc_status abc_set_refill_min(int32_t lanes);
+ABC_API int32_t abc_get_refill_min(void);
 
 /* One observed series of a batch: as abc_series, plus its tolerance and its
  * stream series id (counter word 2; give every series of a batch its own). */

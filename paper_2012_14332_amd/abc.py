@@ -143,6 +143,10 @@ def lib():
         L.abc_nearest_k_rows.restype = ctypes.c_int32
         L.abc_simulate_rows_f64.argtypes = [P(_Series), P(_Model), P(_Stream), vp, vp, i64, vp, vp]
         L.abc_simulate_rows_f64.restype = ctypes.c_int32
+        L.abc_set_refill_min.argtypes = [ctypes.c_int32]
+        L.abc_set_refill_min.restype = ctypes.c_int32
+        L.abc_get_refill_min.argtypes = []
+        L.abc_get_refill_min.restype = ctypes.c_int32
         L.abc_trajectory_bands.argtypes = [vp, i64, ctypes.c_int32, vp, ctypes.c_int32, vp, vp]
         L.abc_trajectory_bands.restype = ctypes.c_int32
         L.abc_set_launch_config.argtypes = [ctypes.c_int32] * 3
@@ -547,6 +551,14 @@ def smc_run(ser: DeviceSeries, cfg: _SmcConfig, seed: int, *, series: int = 0, f
                              stats, ctypes.byref(done), _stream_handle()))
     return [{"idx": idx[t], "theta": th[t], "w": w[t], "dist": d[t], "stats": _gen_stats(stats[t])}
             for t in range(done.value)]
+
+
+def set_refill_min(lanes: int):
+    _check(lib().abc_set_refill_min(int(lanes)))
+
+
+def get_refill_min() -> int:
+    return int(lib().abc_get_refill_min())
 
 
 def trajectory_bands(traj: torch.Tensor, quantiles=(0.05, 0.5, 0.95)) -> torch.Tensor:

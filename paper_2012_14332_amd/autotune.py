@@ -1,8 +1,8 @@
 """Launch-shape autotuner for the float32 simulate kernels.
 
 Sweeps samples per lane (SPL), workgroup size and resident workgroups per CU,
-times each shape with HIP events on short runs of the real workload, and
-keeps the fastest. Results never depend on the shape (every random number is
+then the lane-refill threshold at the best shape, times each setting with HIP
+events on short runs of the real workload, and keeps the fastest. Results never depend on the shape (every random number is
 fixed by the sample's counter), so the tuner only trades speed. Choices are
 cached as JSON per (device, kernel, T bucket) in $ABC_TUNE_CACHE (default
 ~/.cache/abc_mi355x/tune.json).
@@ -23,6 +23,7 @@ SPL_PLAIN = (1, 2, 4, 8)
 SPL_BATCH = (1, 2, 4)
 BLOCKS = (64, 128, 256, 512, 1024)
 PER_CU = (1, 2, 4, 8)
+REFILL = (1, 4, 8, 16, 24)
 
 
 def cache_path() -> str:
@@ -84,21 +85,33 @@ def tune_plain(ser: abc.DeviceSeries, eps_exit: float, n: int = 4_000_000, seed:
     key = "%s|plain|T%d" % (device_key(), t_bucket(ser.T))
     if use_cache:
         rec = _load().get(key)
-        if rec:
-            abc.set_launch_config(*rec["shape"])
+        if rec and "refill" in rec:
+            _apply(rec)
             return rec
     out = torch.empty(n, dtype=torch.float32, device="cuda")
+    run = lambda: abc.simulate_distance(ser, n, seed, eps_exit=eps_exit, out=out)
     table = []
     for sh in shapes(SPL_PLAIN):
         abc.set_launch_config(*sh)
-        ms = _time(lambda: abc.simulate_distance(ser, n, seed, eps_exit=eps_exit, out=out), reps)
-        table.append((ms, sh))
+        table.append((_time(run, reps), sh))
     table.sort()
-    rec = {"shape": list(table[0][1]), "ms": table[0][0], "n": n,
-           "table": [[round(ms, 4)] + list(sh) for ms, sh in table]}
-    abc.set_launch_config(*rec["shape"])
+    abc.set_launch_config(*table[0][1])
+    rtable = []
+    for lanes in REFILL:
+        abc.set_refill_min(lanes)
+        rtable.append((_time(run, reps), lanes))
+    rtable.sort()
+    rec = {"shape": list(table[0][1]), "refill": rtable[0][1], "ms": rtable[0][0], "n": n,
+           "table": [[round(ms, 4)] + list(sh) for ms, sh in table],
+           "refill_table": [[round(ms, 4), lanes] for ms, lanes in rtable]}
+    _apply(rec)
     _store(key, rec)
     return rec
+
+
+def _apply(rec: Dict):
+    abc.set_launch_config(*rec["shape"])
+    abc.set_refill_min(rec.get("refill", 0))
 
 
 def tune_batch(sers, eps, seed: int = 1, quota: int = 1000, round_size: int = 1 << 22,
@@ -107,28 +120,38 @@ def tune_batch(sers, eps, seed: int = 1, quota: int = 1000, round_size: int = 1 
     key = "%s|batch|T%d|m%d" % (device_key(), t_bucket(max(s.T for s in sers)), len(sers))
     if use_cache:
         rec = _load().get(key)
-        if rec:
-            abc.set_launch_config(*rec["shape"])
+        if rec and "refill" in rec:
+            _apply(rec)
             return rec
-    table = []
-    for sh in shapes(SPL_BATCH):
-        abc.set_launch_config(*sh)
+
+    def per_round() -> float:
         best = math.inf
         for _ in range(2):
             o = abc.batch_run(sers, eps, seed, quota, round_size=round_size,
                               max_samples=rounds * round_size // len(sers), rounds_per_graph=1,
                               cand_capacity=4096, check=False)
             if o["status"] not in (0, -5):
-                best = math.inf
-                break
+                return math.inf
             st = o["stats"]
             best = min(best, st["rounds_ms"] / max(st["rounds"], 1))
-        table.append((best, sh))
+        return best
+
+    table = []
+    for sh in shapes(SPL_BATCH):
+        abc.set_launch_config(*sh)
+        table.append((per_round(), sh))
     table.sort()
     if not math.isfinite(table[0][0]):
         raise abc.AbcError("autotune: no launch shape ran the batch")
-    rec = {"shape": list(table[0][1]), "ms_per_round": table[0][0],
-           "table": [[round(ms, 4)] + list(sh) for ms, sh in table]}
-    abc.set_launch_config(*rec["shape"])
+    abc.set_launch_config(*table[0][1])
+    rtable = []
+    for lanes in REFILL:
+        abc.set_refill_min(lanes)
+        rtable.append((per_round(), lanes))
+    rtable.sort()
+    rec = {"shape": list(table[0][1]), "refill": rtable[0][1], "ms_per_round": rtable[0][0],
+           "table": [[round(ms, 4)] + list(sh) for ms, sh in table],
+           "refill_table": [[round(ms, 4), lanes] for ms, lanes in rtable]}
+    _apply(rec)
     _store(key, rec)
     return rec

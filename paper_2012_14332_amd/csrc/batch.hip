@@ -82,6 +82,7 @@ struct BatchArgs {
     unsigned long long* days;
     float nc;               // -2 ln(2) s^2 of the Box-Muller radius
     float scale;
+    int32_t refill_min;     // refill a wave's idle lanes once at least this many are idle
 };
 
 // ----------------------------------------------------------------------------
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
 #pragma unroll
         for (int k = 0; k < SPL; ++k) {
             uint64_t m = __ballot(!L[k].active);
+            if (__popcll(m) < a.refill_min) continue;  // let a few more lanes finish first
             while (m != 0ull && q_base < Q) {
                 const int64_t j = q_base >> 6;
                 if (j != filled_j) {
@@ -611,8 +613,9 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
         obs_ptr[s] = b.obs;
         if (b.T > maxT) maxT = b.T;
     }
-    int32_t spl = 1, block = 512, bpc = 4;
+    int32_t spl = 1, block = 1024, bpc = 1;
     abc_get_launch_config(&spl, &block, &bpc);
+    const int32_t refill_min = abc_get_refill_min();
     const size_t lds = batch_lds_bytes(m, obs_words, block);
     int dev = 0, num_cu = 0, max_lds = 0;
     ABC_HIP(hipGetDevice(&dev));
@@ -698,6 +701,7 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     a.days = reinterpret_cast<unsigned long long*>(b_days.p);
     a.nc = -1.38629436111989061883f * model->noise_scale * model->noise_scale;
     a.scale = model->noise_scale;
+    a.refill_min = refill_min;
 
     hipLaunchKernelGGL(k_batch_obs, dim3(m), dim3(256), 0, s,
                        reinterpret_cast<const int32_t* const*>(b_ptrs.p), a.desc, m,

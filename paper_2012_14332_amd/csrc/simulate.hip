@@ -39,6 +39,7 @@ struct SimArgs {
     double* dist64;
     unsigned long long* days;  // nullable: += sample-days executed
     int32_t* traj;       // record mode: [n][T+1][6]
+    int32_t refill_min;  // refill a wave's idle lanes once at least this many are idle
 };
 
 __device__ __forceinline__ void load_or_draw_theta(const SimArgs& a, bool prior, int64_t k,
@@ -134,6 +135,11 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     }
     __syncthreads();
 
+    // The float32 waves take issue priority over waves of other kernels
+    // sharing the compute unit (the float64 band decision of the previous
+    // launch runs beside this one and fills the gaps instead of holding up
+    // the waves whose static share of the launch it would delay).
+    __builtin_amdgcn_s_setprio(1);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     Slot* ring = ring_all + wv * RING;
@@ -141,7 +147,8 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t nchunks = (a.n + 63) >> 6;
     if (wg >= nchunks) return;
-    // queue positions of this wave (fits 32 bits: the host limits n per launch)
+    // queue positions of this wave (fits 32 bits: the host limits n per launch);
+    // its j-th chunk is wg + j nw
     const uint32_t Q = (uint32_t)(((nchunks - 1 - wg) / nw + 1) << 6);
 
     const PhiloxSeries ps = philox_series(a.series, a.key);
@@ -150,9 +157,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     const float dscale = DIST == 0 ? 0.693147180559945309417f : 1.0f;
     const uint32_t wdom = a.domain << 4;
 
-    // the ring holds chunk j of this wave: sample offsets (wg + j nw) 64 + lane
-    auto fill = [&](uint32_t j) {
-        const int64_t k = ((wg + (int64_t)j * nw) << 6) + lane;
+    // the ring holds one chunk: sample offsets 64 c + lane
+    auto fill = [&](int64_t c) {
+        const int64_t k = (c << 6) + lane;
         Slot& sl = ring[lane];
         if (k < a.n)
             fill_slot<PRIOR>(a, k, ps.u0, sl);
@@ -174,10 +181,11 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
             uint64_t m = __ballot(!L[j].active);
+            if (__popcll(m) < a.refill_min) continue;  // let a few more lanes finish first
             while (m != 0ull && qb < Q) {
                 const uint32_t jc = qb >> 6;
                 if (jc != filled) {
-                    fill(jc);
+                    fill(wg + (int64_t)jc * nw);
                     filled = jc;
                 }
                 const uint32_t avail = 64u - (qb & 63u);
@@ -306,39 +314,47 @@ struct RecheckArgs {
     int32_t* rechecked;  // nullable: number of rows simulated in float64
 };
 
-// Pass 1: one lane per candidate row. Workgroups without in-band rows skip
-// the staging of the observed series and only write their keep flags.
+// Pass 1: one wavefront per in-band candidate row (simulate_row_f64_wave);
+// rows outside the band only get their keep flag. Workgroups that meet no
+// in-band row never stage the observed series. Spreading the rows over many
+// wavefronts keeps the time any one SIMD spends on them short: this kernel
+// runs beside the next float32 launch, which it should not hold up.
 template <int NOISE, int DIST>
 __global__ __launch_bounds__(64) void k_recheck_flags(RecheckArgs r)
 {
-    extern __shared__ double lds_r[];
+    extern __shared__ double lds_r[];  // obs [3 T] | z [5 T] | counts [3 T] int32
     const SimArgs& a = r.sim;
     const int64_t count = *r.count;
     if (count > r.capacity) return;  // overflowed candidate set: left for the caller to rerun
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int64_t)blockIdx.x * blockDim.x >= count) return;
-    const float d = q < count ? r.dist[q] : INFINITY;
-    const bool band = q < count && d > r.band_lo && d <= r.band_hi;
-    if (__ballot(band) == 0ull) {
-        if (q < count) r.keep[q] = d <= r.eps ? 1 : 0;
-        return;
-    }
-    stage_obs_f64<DIST>(a.obs, a.T, lds_r);
-    __syncthreads();
-    if (q >= count) return;
-    bool keep = d <= r.eps;
-    if (band) {
+    const int T = a.T;
+    double* lobs = lds_r;
+    double* zs = lds_r + 3 * T;
+    int32_t* xs = reinterpret_cast<int32_t*>(zs + 5 * T);
+    bool staged = false;
+    for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
+        const float d = r.dist[q];
+        if (!(d > r.band_lo && d <= r.band_hi)) {
+            if (threadIdx.x == 0) r.keep[q] = d <= r.eps ? 1 : 0;
+            continue;
+        }
+        if (!staged) {
+            stage_obs_f64<DIST>(a.obs, T, lobs);
+            __syncthreads();
+            staged = true;
+        }
         float thv[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) thv[j] = r.theta[8 * q + j];
-        const double d64 = simulate_one_f64<NOISE, DIST>(
-            thv, (uint64_t)r.idx[q], a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, a.T,
-            (double)a.scale, lds_r, (double)INFINITY);
-        keep = d64 <= (double)r.eps;
-        r.dist[q] = (float)d64;
-        if (r.rechecked) atomicAdd(r.rechecked, 1);
+        const double d64 = simulate_row_f64_wave<NOISE, DIST>(
+            thv, (uint64_t)r.idx[q], a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
+            (double)a.scale, lobs, zs, xs);
+        if (threadIdx.x == 0) {
+            r.keep[q] = d64 <= (double)r.eps ? 1 : 0;
+            r.dist[q] = (float)d64;
+            if (r.rechecked) atomicAdd(r.rechecked, 1);
+        }
+        __syncthreads();  // the scratch is reused by the next row
     }
-    r.keep[q] = keep ? 1 : 0;
 }
 
 // Pass 2: stable in-place compaction of the kept rows, 256 rows at a time.
@@ -393,6 +409,7 @@ __global__ void k_zero_i32(int32_t* p)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+
 // float64 distances of listed rows (sample idx[q], theta[q]), one lane each.
 struct RowsArgs {
     SimArgs sim;
@@ -403,18 +420,24 @@ struct RowsArgs {
 template <int NOISE, int DIST>
 __global__ __launch_bounds__(64) void k_rows_f64(RowsArgs r)
 {
-    extern __shared__ double lds_w[];
+    extern __shared__ double lds_w[];  // obs [3 T] | z [5 T] | counts [3 T] int32
     const SimArgs& a = r.sim;
-    stage_obs_f64<DIST>(a.obs, a.T, lds_w);
+    const int T = a.T;
+    double* lobs = lds_w;
+    double* zs = lds_w + 3 * T;
+    int32_t* xs = reinterpret_cast<int32_t*>(zs + 5 * T);
+    stage_obs_f64<DIST>(a.obs, T, lobs);
     __syncthreads();
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.n) return;
-    float thv[8];
+    for (int64_t q = blockIdx.x; q < a.n; q += gridDim.x) {
+        float thv[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) thv[j] = a.theta[8 * q + j];
-    r.dist64[q] = simulate_one_f64<NOISE, DIST>(thv, (uint64_t)r.idx[q], a.key, a.series, a.domain,
-                                                a.P, a.A0, a.R0, a.D0, a.T, (double)a.scale, lds_w,
-                                                (double)INFINITY);
+        for (int j = 0; j < 8; ++j) thv[j] = a.theta[8 * q + j];
+        const double d64 = simulate_row_f64_wave<NOISE, DIST>(
+            thv, (uint64_t)r.idx[q], a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
+            (double)a.scale, lobs, zs, xs);
+        if (threadIdx.x == 0) r.dist64[q] = d64;
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -490,6 +513,13 @@ static abc_status fill_series(SimArgs& a, const abc_series* ser, const abc_model
     return ABC_OK;
 }
 
+// float64 row kernels: one wavefront per row, rows strided over the grid
+constexpr int64_t ROW_WAVE_GRID = 2048;
+static size_t row_wave_lds_bytes(int T)
+{
+    return (sizeof(double) * 8 + sizeof(int32_t) * 3) * (size_t)T;
+}
+
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + SIM_BLOCK - 1) / SIM_BLOCK); }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -498,8 +528,9 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 // per lane, workgroup size and resident workgroups per CU (0 = default).
 struct LaunchConfig {
     int spl = 1;
-    int block = 512;
-    int blocks_per_cu = 4;
+    int block = 1024;
+    int blocks_per_cu = 1;
+    int refill_min = 8;
 };
 static thread_local LaunchConfig g_launch;
 
@@ -554,7 +585,7 @@ static void launch_f32_spl(const SimArgs& a, bool prior, hipStream_t s)
 }
 
 template <int NOISE, int DIST, bool KAHAN>
-static void launch_f32(const SimArgs& a, bool prior, size_t /*unused*/, hipStream_t s)
+static void launch_f32(const SimArgs& a, bool prior, hipStream_t s)
 {
     // several samples per lane only for the paper's model and distance
     if constexpr (NOISE == 0 && DIST == 0) {
@@ -636,6 +667,7 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
     a.dist = dist;
     a.dist64 = dist64;
     a.days = days;
+    a.refill_min = g_launch.refill_min;
     // Early-exit bounds with a relative margin that keeps every exited sample
     // strictly above eps_exit after the final square root and rounding.
     const double e2 = (double)eps_exit * (double)eps_exit;
@@ -661,15 +693,15 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
                          a.T, g_launch.block, lds, max_lds_per_block());
     const bool kahan = (model->flags & ABC_KAHAN) != 0;
     if (kahan) {
-        if (noise == 0 && distm == 0) launch_f32<0, 0, true>(a, use_prior, lds, s);
-        else if (noise == 0 && distm == 1) launch_f32<0, 1, true>(a, use_prior, lds, s);
-        else if (noise == 1 && distm == 0) launch_f32<1, 0, true>(a, use_prior, lds, s);
-        else launch_f32<1, 1, true>(a, use_prior, lds, s);
+        if (noise == 0 && distm == 0) launch_f32<0, 0, true>(a, use_prior, s);
+        else if (noise == 0 && distm == 1) launch_f32<0, 1, true>(a, use_prior, s);
+        else if (noise == 1 && distm == 0) launch_f32<1, 0, true>(a, use_prior, s);
+        else launch_f32<1, 1, true>(a, use_prior, s);
     } else {
-        if (noise == 0 && distm == 0) launch_f32<0, 0, false>(a, use_prior, lds, s);
-        else if (noise == 0 && distm == 1) launch_f32<0, 1, false>(a, use_prior, lds, s);
-        else if (noise == 1 && distm == 0) launch_f32<1, 0, false>(a, use_prior, lds, s);
-        else launch_f32<1, 1, false>(a, use_prior, lds, s);
+        if (noise == 0 && distm == 0) launch_f32<0, 0, false>(a, use_prior, s);
+        else if (noise == 0 && distm == 1) launch_f32<0, 1, false>(a, use_prior, s);
+        else if (noise == 1 && distm == 0) launch_f32<1, 0, false>(a, use_prior, s);
+        else launch_f32<1, 1, false>(a, use_prior, s);
     }
     return check_launch("k_simulate_f32");
 }
@@ -707,8 +739,8 @@ extern "C" abc_status abc_simulate_record(const abc_series* ser, const abc_model
 extern "C" abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu)
 {
     if (spl == 0) spl = 1;
-    if (block == 0) block = 512;
-    if (blocks_per_cu == 0) blocks_per_cu = 4;
+    if (block == 0) block = 1024 / spl;
+    if (blocks_per_cu == 0) blocks_per_cu = 1;
     ABC_REQUIRE(spl == 1 || spl == 2 || spl == 4 || spl == 8, "spl must be 1, 2, 4 or 8");
     ABC_REQUIRE(block >= 64 && block <= 1024 / spl && block % 64 == 0,
                 "block must be a multiple of 64 in [64, 1024/spl]");
@@ -744,7 +776,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     ABC_REQUIRE(count != nullptr, "count is NULL");
     if (capacity == 0) return ABC_OK;
     ABC_REQUIRE(idx && theta && dist, "idx/theta/dist NULL");
-    const size_t lds = sizeof(double) * 3 * (size_t)ser->T;
+    const size_t lds = row_wave_lds_bytes(ser->T);
     ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 recheck");
     const hipStream_t s = as_stream(stream);
     RecheckArgs r{};
@@ -765,7 +797,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     const int noise = (model->flags & ABC_NOISE_LITERAL) ? 1 : 0;
     const int distm = (model->flags & ABC_DIST_RAW) ? 1 : 0;
     if (rechecked) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, rechecked);
-    const dim3 g((unsigned)((capacity + 63) / 64)), b(64);
+    const dim3 g((unsigned)(capacity < ROW_WAVE_GRID ? capacity : ROW_WAVE_GRID)), b(64);
     if (noise == 0 && distm == 0) hipLaunchKernelGGL((k_recheck_flags<0, 0>), g, b, lds, s, r);
     else if (noise == 0) hipLaunchKernelGGL((k_recheck_flags<0, 1>), g, b, lds, s, r);
     else if (distm == 0) hipLaunchKernelGGL((k_recheck_flags<1, 0>), g, b, lds, s, r);
@@ -792,7 +824,7 @@ extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_mod
     ABC_REQUIRE(n >= 0, "n < 0");
     if (n == 0) return ABC_OK;
     ABC_REQUIRE(idx && theta && dist64, "idx/theta/dist64 NULL");
-    const size_t lds = sizeof(double) * 3 * (size_t)ser->T;
+    const size_t lds = row_wave_lds_bytes(ser->T);
     ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 path");
     RowsArgs r{};
     fill_series(r.sim, ser, model, st, 0, n);
@@ -802,10 +834,20 @@ extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_mod
     const hipStream_t s = as_stream(stream);
     const int noise = (model->flags & ABC_NOISE_LITERAL) ? 1 : 0;
     const int distm = (model->flags & ABC_DIST_RAW) ? 1 : 0;
-    const dim3 g((unsigned)((n + 63) / 64)), b(64);
+    const dim3 g((unsigned)(n < ROW_WAVE_GRID ? n : ROW_WAVE_GRID)), b(64);
     if (noise == 0 && distm == 0) hipLaunchKernelGGL((k_rows_f64<0, 0>), g, b, lds, s, r);
     else if (noise == 0) hipLaunchKernelGGL((k_rows_f64<0, 1>), g, b, lds, s, r);
     else if (distm == 0) hipLaunchKernelGGL((k_rows_f64<1, 0>), g, b, lds, s, r);
     else hipLaunchKernelGGL((k_rows_f64<1, 1>), g, b, lds, s, r);
     return check_launch("k_rows_f64");
 }
+
+extern "C" abc_status abc_set_refill_min(int32_t lanes)
+{
+    if (lanes == 0) lanes = 8;
+    ABC_REQUIRE(lanes >= 1 && lanes <= 64, "lanes must be in [1, 64]");
+    g_launch.refill_min = lanes;
+    return ABC_OK;
+}
+
+extern "C" int32_t abc_get_refill_min(void) { return g_launch.refill_min; }

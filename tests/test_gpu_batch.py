@@ -69,9 +69,10 @@ def test_batch_independent_of_round_size_and_launch(env):
     ref = abc.batch_run(sers, eps, 9, 30, round_size=1 << 15, rounds_per_graph=1,
                         cand_capacity=4096)
     ref_idx = ref["idx"].cpu().numpy()
-    for rs, rpg, cfg in [(1 << 17, 4, (1, 512, 4)), (1 << 16, 8, (2, 256, 4)), (50_000, 2, (4, 128, 2)),
-                         (1 << 20, 1, (1, 1024, 1))]:
+    for rs, rpg, cfg, lanes in [(1 << 17, 4, (1, 512, 4), 1), (1 << 16, 8, (2, 256, 4), 16),
+                                (50_000, 2, (4, 128, 2), 64), (1 << 20, 1, (1, 1024, 1), 9)]:
         abc.set_launch_config(*cfg)
+        abc.set_refill_min(lanes)
         o = abc.batch_run(sers, eps, 9, 30, round_size=rs, rounds_per_graph=rpg,
                           cand_capacity=4096)
         np.testing.assert_array_equal(o["idx"].cpu().numpy(), ref_idx, err_msg=str((rs, rpg, cfg)))
@@ -79,6 +80,7 @@ def test_batch_independent_of_round_size_and_launch(env):
         np.testing.assert_array_equal(o["dist"].cpu().numpy(), ref["dist"].cpu().numpy())
         np.testing.assert_allclose(o["mean"].cpu().numpy(), ref["mean"].cpu().numpy(), rtol=1e-13)
     abc.set_launch_config(0, 0, 0)
+    abc.set_refill_min(0)
 
 
 def test_batch_equals_plain_path(env):

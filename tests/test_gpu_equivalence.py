@@ -57,6 +57,24 @@ def test_launch_configs_bit_identical(A, ser):
     A.set_launch_config(0, 0, 0)
 
 
+def test_refill_threshold_bit_identical(A, ser):
+    A.set_launch_config(0, 0, 0)
+    A.set_refill_min(0)
+    assert A.get_refill_min() == 8
+    ref_inf = _run(A, ser)
+    eps = float(np.quantile(ref_inf, 0.01))
+    ref_eps = _run(A, ser, eps_exit=eps)
+    for lanes, shape in [(1, (1, 512, 4)), (32, (2, 256, 4)), (64, (1, 64, 1)), (17, (4, 128, 2))]:
+        A.set_refill_min(lanes)
+        A.set_launch_config(*shape)
+        np.testing.assert_array_equal(_run(A, ser), ref_inf, err_msg=str(lanes))
+        np.testing.assert_array_equal(_run(A, ser, eps_exit=eps), ref_eps, err_msg=str(lanes))
+    with pytest.raises(A.AbcError):
+        A.set_refill_min(65)
+    A.set_refill_min(0)
+    A.set_launch_config(0, 0, 0)
+
+
 def test_invalid_launch_config(A):
     with pytest.raises(A.AbcError):
         A.set_launch_config(3, 256, 8)
