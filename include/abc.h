@@ -294,6 +294,40 @@ ABC_API abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
                                  int64_t* out_count, int64_t* out_used, double* out_mean,
                                  double* out_cov, abc_batch_stats* stats, void* stream);
 
+/* Learned proposal of a batched run (not in the paper): per series a row of
+ * the network output (abc_mdn_forward of the series' features), drawn as the
+ * defensive mixture of abc_mdn_sample with the prior box `prior`. */
+typedef struct {
+    const float* mix;   /* device float32 [m][136], row s for series s */
+    float lambda;       /* defensive prior weight in [0, 1] */
+    float inflate;      /* factor on every component sd, [1, 100] */
+    uint32_t domain;    /* stream domain of the proposal draws (5 in this build) */
+    uint32_t pad;
+} abc_batch_proposal;
+
+/*
+ * abc_batch_run with theta drawn from the learned proposal instead of the
+ * prior: sample i of series s takes theta and its importance weight
+ * prior/proposal from abc_mdn_sample's draw on stream (seed, prop->domain,
+ * series id, i), and its simulation noise from (seed, domain, series id, i)
+ * as in abc_batch_run. Outputs as abc_batch_run plus out_w (device float32
+ * [m][quota]); out_mean / out_cov are the weighted moments (sum w theta / V1,
+ * sum w (theta - mean)(theta - mean)^T / (V1 - V2/V1)). The kept rows are the
+ * first `quota` accepted by index, so the result equals the per-series
+ * learned-proposal pass run until the same quota. Errors as abc_batch_run,
+ * plus ABC_EINVAL for a NULL proposal or out_w, lambda outside [0, 1] or
+ * inflate outside [1, 100].
+ */
+ABC_API abc_status abc_batch_run_weighted(const abc_batch_series* series, int32_t m,
+                                          const abc_prior* prior, const abc_model* model,
+                                          uint64_t seed, uint32_t domain, int32_t quota,
+                                          int64_t round_size, int64_t max_samples, float band_w,
+                                          int32_t rounds_per_graph, int32_t cand_capacity,
+                                          const abc_batch_proposal* prop, int64_t* out_idx,
+                                          float* out_theta, float* out_w, float* out_dist,
+                                          int64_t* out_count, int64_t* out_used, double* out_mean,
+                                          double* out_cov, abc_batch_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned proposal (not in the paper, whose proposal is the prior): a
  * mixture-density network q(theta | x) trained on (theta, x) pairs that the
@@ -380,10 +414,13 @@ ABC_API abc_status abc_mdn_train(abc_mdn* net, const float* features, const floa
  * lambda theta ~ prior, otherwise from the mixture given by `mix` (device,
  * one network output row [136]) with every component sd multiplied by
  * `inflate` (>= 1; the network estimates the eps -> 0 posterior, which is
- * narrower than the eps-ABC posterior); draws outside the prior box are
- * redrawn (attempt a uses day a + 1 of the stream). weight = prior(theta) /
- * q(theta), q = (1 - lambda) q_mix + lambda prior (the truncation constant
- * cancels in self-normalised weights). Outputs device theta [n][8], weight [n]. */
+ * narrower than the eps-ABC posterior) and every component truncated to the
+ * prior box dimension by dimension (inverse-CDF draws, one per dimension; a
+ * component whose mass in the box is below 1e-30 in some dimension is
+ * dropped). Day 1 of the stream: block 0 words 0, 1 choose prior/mixture and
+ * the component, blocks 1-2 give the eight uniforms. weight = prior(theta) /
+ * q(theta), q = (1 - lambda) q_trunc + lambda prior, q_trunc the truncated
+ * mixture's density. Outputs device theta [n][8], weight [n]. */
 ABC_API abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float lambda,
                                   float inflate, const abc_stream* st, uint64_t first, int64_t n,
                                   float* theta, float* weight, void* stream);

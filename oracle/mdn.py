@@ -15,7 +15,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import erf, logsumexp
+from scipy.special import erf, logsumexp, ndtr
 
 N_IN, N_H, K, D = 96, 256, 8, 8
 N_OUT = K + 2 * K * D  # 136
@@ -167,18 +167,54 @@ def mixture_sample(out_row, n, rng):
     return mu[0][k] + sig[k] * rng.standard_normal((n, D))
 
 
-def defensive_logq(out_row, theta, lo, hi, lam, inflate=1.0):
-    """log of the defensive proposal density at theta (original units):
-    (1 - lam) * mixture (component sds times `inflate`, mapped back from the
-    standardised space) + lam * prior."""
+def truncated_masses(out_row, lo, hi, inflate=1.0):
+    """Z [K, D]: the mass of component k's normal in dimension j (sd times
+    `inflate`, standardised units) inside the box, computed on the side of the
+    tail it lies in."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    c = (lo + hi) / 2
+    s = (hi - lo) / math.sqrt(12.0)
+    _, mu, ls = split_out(np.asarray(out_row, np.float64)[None])
+    sig = np.exp(np.clip(ls[0], LOGSIG_LO, LOGSIG_HI) + math.log(inflate))
+    a = (lo - c) / s
+    b = (hi - c) / s
+    al = (a[None, :] - mu[0]) / sig
+    be = (b[None, :] - mu[0]) / sig
+    upper = al >= 0
+    lower = be <= 0
+    Z = ndtr(be) - ndtr(al)
+    Z = np.where(upper, ndtr(-al) - ndtr(-be), Z)
+    Z = np.where(lower, ndtr(be) - ndtr(al), Z)
+    return Z
+
+
+def truncated_logq(out_row, theta, lo, hi, inflate=1.0):
+    """log density (original units) of the mixture with every component
+    truncated to the box dimension by dimension: component weights
+    renormalised over the components whose masses are all >= 1e-30,
+    log q = logsumexp_k [log w_k - sum_j log Z_kj + sum_j log N(t_j; mu_kj, sig_kj)]
+            - sum_j log s_j."""
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
     s = (hi - lo) / math.sqrt(12.0)
     t = theta_standardise(theta, lo, hi)
-    row = np.asarray(out_row, np.float64).copy()
-    # inflating every sd = adding log(inflate) to the clamped log sd
-    ls = row[K + K * D:]
-    row[K + K * D:] = np.clip(ls, LOGSIG_LO, LOGSIG_HI) + math.log(inflate)
-    lq_mix = mixture_logpdf_unclamped(np.repeat(row[None], t.shape[0], 0), t) - np.log(s).sum()
+    logits, mu, ls = split_out(np.asarray(out_row, np.float64)[None])
+    lsig = np.clip(ls[0], LOGSIG_LO, LOGSIG_HI) + math.log(inflate)
+    Z = truncated_masses(out_row, lo, hi, inflate)
+    keep = np.all(Z >= 1e-30, axis=1)
+    lw = np.where(keep, logits[0], -np.inf)
+    lw = lw - logsumexp(lw)
+    u = (t[:, None, :] - mu[0][None]) / np.exp(lsig)[None]
+    comp = (-0.5 * u * u - lsig[None] - 0.5 * LOG_2PI).sum(2) - np.log(np.where(keep, Z, 1.0)).sum(1)[None]
+    return logsumexp(lw[None] + comp, axis=1) - np.log(s).sum()
+
+
+def defensive_logq(out_row, theta, lo, hi, lam, inflate=1.0):
+    """log of the defensive proposal density at theta (original units):
+    (1 - lam) * truncated mixture (component sds times `inflate`) + lam * prior."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    lq_mix = truncated_logq(out_row, theta, lo, hi, inflate)
     lq_prior = -np.log(hi - lo).sum()
     return np.logaddexp(np.log1p(-lam) + lq_mix, np.log(lam) + lq_prior) if lam > 0 else lq_mix

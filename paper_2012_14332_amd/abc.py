@@ -65,6 +65,11 @@ class _BatchStats(ctypes.Structure):
 _lib = None
 
 
+class _BatchProposal(ctypes.Structure):
+    _fields_ = [("mix", ctypes.c_void_p), ("lam", ctypes.c_float), ("inflate", ctypes.c_float),
+                ("domain", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
 class _SmcConfig(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_int32), ("generations", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("eps0", ctypes.c_float), ("eps_min", ctypes.c_float),
@@ -128,6 +133,11 @@ def lib():
                   "abc_series_features", "abc_mdn_fit_standardizer", "abc_mdn_forward",
                   "abc_mdn_loss_grad", "abc_mdn_train", "abc_mdn_sample"):
             getattr(L, f).restype = ctypes.c_int32
+        L.abc_batch_run_weighted.argtypes = [P(_BatchSeries), ctypes.c_int32, P(_Prior), P(_Model),
+                                             u64, ctypes.c_uint32, ctypes.c_int32, i64, i64, f32,
+                                             ctypes.c_int32, ctypes.c_int32, P(_BatchProposal),
+                                             vp, vp, vp, vp, vp, vp, vp, vp, P(_BatchStats), vp]
+        L.abc_batch_run_weighted.restype = ctypes.c_int32
         L.abc_smc_generation.argtypes = [P(_Series), P(_Model), P(_Prior), u64, ctypes.c_uint32,
                                          ctypes.c_int32, vp, vp, vp, ctypes.c_int32, P(_SmcConfig),
                                          vp, vp, vp, vp, P(_SmcGenStats), vp, vp]
@@ -311,9 +321,12 @@ def get_launch_config():
 def batch_run(sers, eps, seed: int, quota: int, *, series_ids=None, round_size: int = 1 << 22,
               max_samples: int = 1 << 40, band_w: float = 0.02, rounds_per_graph: int = 4,
               domain: int = 1, noise_scale: float = 1.0, prior: Optional[_Prior] = None,
-              cand_capacity: int = 0, device="cuda", check: bool = True):
+              cand_capacity: int = 0, device="cuda", check: bool = True, mix=None,
+              lam: float = 0.05, inflate: float = 1.5, prop_domain: int = 5):
     """Batched persistent ABC over DeviceSeries `sers` with tolerances `eps` until each has
-    `quota` accepted samples. Returns a dict of device tensors and the run statistics."""
+    `quota` accepted samples. With `mix` (device [m,136] network outputs) theta comes from
+    the learned proposal and the result carries importance weights `w`. Returns a dict of
+    device tensors and the run statistics."""
     m = len(sers)
     ids = list(range(m)) if series_ids is None else list(series_ids)
     arr = (_BatchSeries * m)()
@@ -332,13 +345,28 @@ def batch_run(sers, eps, seed: int, quota: int, *, series_ids=None, round_size: 
     st = _BatchStats()
     pr = prior or make_prior()
     md = _Model(float(noise_scale), 0)
-    rc = lib().abc_batch_run(arr, m, ctypes.byref(pr), ctypes.byref(md), int(seed), int(domain),
-                             int(quota), int(round_size), int(max_samples), float(band_w),
-                             int(rounds_per_graph), int(cand_capacity), _dptr(out["idx"]),
-                             _dptr(out["theta"]),
-                             _dptr(out["dist"]), _dptr(out["count"]), _dptr(out["used"]),
-                             _dptr(out["mean"]), _dptr(out["cov"]), ctypes.byref(st),
-                             _stream_handle())
+    if mix is None:
+        rc = lib().abc_batch_run(arr, m, ctypes.byref(pr), ctypes.byref(md), int(seed), int(domain),
+                                 int(quota), int(round_size), int(max_samples), float(band_w),
+                                 int(rounds_per_graph), int(cand_capacity), _dptr(out["idx"]),
+                                 _dptr(out["theta"]),
+                                 _dptr(out["dist"]), _dptr(out["count"]), _dptr(out["used"]),
+                                 _dptr(out["mean"]), _dptr(out["cov"]), ctypes.byref(st),
+                                 _stream_handle())
+    else:
+        mix = mix.contiguous()
+        if tuple(mix.shape) != (m, 136):
+            raise AbcError("mix must have shape [m, 136]")
+        out["w"] = torch.zeros((m, quota), dtype=torch.float32, device=device)
+        prop = _BatchProposal(mix.data_ptr(), float(lam), float(inflate), int(prop_domain), 0)
+        rc = lib().abc_batch_run_weighted(arr, m, ctypes.byref(pr), ctypes.byref(md), int(seed),
+                                          int(domain), int(quota), int(round_size),
+                                          int(max_samples), float(band_w), int(rounds_per_graph),
+                                          int(cand_capacity), ctypes.byref(prop), _dptr(out["idx"]),
+                                          _dptr(out["theta"]), _dptr(out["w"]), _dptr(out["dist"]),
+                                          _dptr(out["count"]), _dptr(out["used"]),
+                                          _dptr(out["mean"]), _dptr(out["cov"]), ctypes.byref(st),
+                                          _stream_handle())
     out["status"] = rc
     out["stats"] = {k: getattr(st, k) for k, _ in _BatchStats._fields_}
     if check:

@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "model.hpp"
+#include "proposal.hpp"
 
 namespace abc {
 
@@ -83,7 +84,21 @@ struct BatchArgs {
     float nc;               // -2 ln(2) s^2 of the Box-Muller radius
     float scale;
     int32_t refill_min;     // refill a wave's idle lanes once at least this many are idle
+    const float* mix;       // null: prior draws; else [m][136] proposal rows (learned proposal)
+    const MixTable* tables; // [m] truncated-mixture tables of the rows
+    ProposalBox prop;
+    uint32_t prop_domain;   // stream domain of the proposal draws
 };
+
+// theta of sample i of series s (desc d): the prior draw, or the learned
+// proposal's draw with its importance weight
+__device__ __forceinline__ float batch_theta(const BatchArgs& a, int s, const SeriesDesc& d, uint64_t i,
+                                             float th[8])
+{
+    if (a.mix) return proposal_draw(a.tables[s], a.prop, a.key, i, d.series_id, a.prop_domain, th);
+    prior_draw(a.key, i, d.series_id, a.domain, a.lo, a.width, th);
+    return 1.0f;
+}
 
 // ----------------------------------------------------------------------------
 // setup: log2(1 + O) table of all series
@@ -105,6 +120,18 @@ __global__ void k_batch_init(BatchArgs a)
         a.state[s].certain = 0;
         a.state[s].cand = 0;
     }
+}
+
+// truncated-mixture table of each series' proposal row: one workgroup per
+// series, one thread per (component, dimension)
+__global__ __launch_bounds__(64) void k_batch_tables(const float* mix, ProposalBox p, MixTable* tables)
+{
+    const int s = blockIdx.x;
+    const float* o = mix + (int64_t)s * MIX_OUT;
+    MixTable& t = tables[s];
+    mix_table_entry(o, p, threadIdx.x / MIX_D, threadIdx.x % MIX_D, t);
+    __syncthreads();
+    if (threadIdx.x == 0) mix_table_finish(o, t);
 }
 
 // ----------------------------------------------------------------------------
@@ -147,6 +174,10 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
             int64_t lim = room > 0 ? room * next / (2 * (cand + 1)) : 0;
             if (lim < 64) lim = 64;
             if (n_s > lim) n_s = lim;
+        } else if (n_s > 2 * (int64_t)a.cand_cap) {
+            // first round: no rate seen yet; at most twice the capacity, safe
+            // for any acceptance rate up to one half
+            n_s = 2 * (int64_t)a.cand_cap;
         }
     }
     const int chunks = (int)((n_s + 63) / 64);
@@ -256,7 +287,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
             const SeriesDesc& d = desc_sh[s];
             const int64_t i = tab_sh.first[r] + local;
             float th[8];
-            prior_draw(a.key, (uint64_t)i, d.series_id, a.domain, a.lo, a.width, th);
+            (void)batch_theta(a, s, d, (uint64_t)i, th);
             const Theta tt = theta_from(th);
             const RatesF rr = rates_f32(tt);
             const State s0 = init_state(tt.ka, d.P, d.A0, d.R0, d.D0);
@@ -401,6 +432,7 @@ struct FinalArgs {
     float band_w;
     int64_t* out_idx;    // [m][quota]
     float* out_theta;    // [m][quota][8]
+    float* out_w;        // [m][quota] importance weights, or null
     float* out_dist;     // [m][quota]
     int64_t* out_count;  // [m]
     int64_t* out_used;   // [m] samples consumed
@@ -455,7 +487,7 @@ __global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
             v = a.cand_dist[(int64_t)s * a.cand_cap + q];
             if (v > d.eps_lo) {
                 float th[8];
-                prior_draw(a.key, (uint64_t)k, d.series_id, a.domain, a.lo, a.width, th);
+                (void)batch_theta(a, s, d, (uint64_t)k, th);
                 const double d64 = simulate_one_f64<0, 0>(th, (uint64_t)k, a.key, d.series_id,
                                                           a.domain, d.P, d.A0, d.R0, d.D0, d.T,
                                                           (double)a.scale, obs64,
@@ -475,9 +507,10 @@ __global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
             f.out_idx[(int64_t)s * a.quota + q] = key[q];
             f.out_dist[(int64_t)s * a.quota + q] = val[q];
             float th[8];
-            prior_draw(a.key, (uint64_t)key[q], d.series_id, a.domain, a.lo, a.width, th);
+            const float w = batch_theta(a, s, d, (uint64_t)key[q], th);
 #pragma unroll
             for (int j = 0; j < 8; ++j) f.out_theta[((int64_t)s * a.quota + q) * 8 + j] = th[j];
+            if (f.out_w) f.out_w[(int64_t)s * a.quota + q] = w;
             atomicAdd(&nkeep, 1);
         }
     }
@@ -504,25 +537,42 @@ __device__ double block_sum_f64(double v, double* red)
     return t;
 }
 
-__global__ __launch_bounds__(256) void k_batch_moments(const float* theta, const int64_t* count,
-                                                       int quota, double* mean, double* cov)
+__global__ __launch_bounds__(256) void k_batch_moments(const float* theta, const float* weight,
+                                                       const int64_t* count, int quota, double* mean,
+                                                       double* cov)
 {
     __shared__ double red[4];
     const int s = blockIdx.x;
     const int64_t n = count[s] > 0 ? (count[s] < quota ? count[s] : quota) : 0;
     const float* th = theta + (int64_t)s * quota * 8;
+    const float* w = weight ? weight + (int64_t)s * quota : nullptr;
+    // unweighted: mean and the unbiased (n - 1) covariance; weighted: sum w theta / V1
+    // and sum w (theta - mean)(theta - mean)^T / (V1 - V2 / V1)
+    double v1 = (double)n, v2 = (double)n;
+    if (w) {
+        double a1 = 0.0, a2 = 0.0;
+        for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+            const double x = (double)w[r];
+            a1 += x;
+            a2 += x * x;
+        }
+        v1 = block_sum_f64(a1, red);
+        v2 = block_sum_f64(a2, red);
+    }
     double mu[8];
     for (int j = 0; j < 8; ++j) {
         double v = 0.0;
-        for (int64_t r = threadIdx.x; r < n; r += blockDim.x) v += (double)th[8 * r + j];
-        mu[j] = block_sum_f64(v, red) / (double)n;
+        for (int64_t r = threadIdx.x; r < n; r += blockDim.x)
+            v += (w ? (double)w[r] : 1.0) * (double)th[8 * r + j];
+        mu[j] = block_sum_f64(v, red) / v1;
     }
+    const double denom = w ? v1 - v2 / v1 : (double)(n - 1);
     for (int j = 0; j < 8; ++j)
         for (int l = j; l < 8; ++l) {
             double v = 0.0;
             for (int64_t r = threadIdx.x; r < n; r += blockDim.x)
-                v += ((double)th[8 * r + j] - mu[j]) * ((double)th[8 * r + l] - mu[l]);
-            const double c = block_sum_f64(v, red) / (double)(n - 1);
+                v += (w ? (double)w[r] : 1.0) * (((double)th[8 * r + j] - mu[j]) * ((double)th[8 * r + l] - mu[l]));
+            const double c = block_sum_f64(v, red) / denom;
             if (threadIdx.x == 0) {
                 cov[(int64_t)s * 64 + 8 * j + l] = c;
                 cov[(int64_t)s * 64 + 8 * l + j] = c;
@@ -557,15 +607,13 @@ void launch_round(const BatchArgs& a, unsigned grid, int block, size_t lds, hipS
 
 }  // namespace
 
-extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
-                                    const abc_prior* prior, const abc_model* model,
-                                    uint64_t seed, uint32_t domain, int32_t quota,
-                                    int64_t round_size, int64_t max_samples, float band_w,
-                                    int32_t rounds_per_graph, int32_t cand_capacity,
-                                    int64_t* out_idx,
-                                    float* out_theta, float* out_dist, int64_t* out_count,
-                                    int64_t* out_used, double* out_mean, double* out_cov,
-                                    abc_batch_stats* stats, void* stream)
+static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc_prior* prior,
+                            const abc_model* model, uint64_t seed, uint32_t domain, int32_t quota,
+                            int64_t round_size, int64_t max_samples, float band_w,
+                            int32_t rounds_per_graph, int32_t cand_capacity,
+                            const abc_batch_proposal* prop, int64_t* out_idx, float* out_theta,
+                            float* out_w, float* out_dist, int64_t* out_count, int64_t* out_used,
+                            double* out_mean, double* out_cov, abc_batch_stats* stats, void* stream)
 {
     abc_status rc;
     ABC_REQUIRE(series != nullptr && m >= 1 && m <= BT_MAX_SERIES, "need 1 <= m <= %d series", BT_MAX_SERIES);
@@ -583,6 +631,13 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     float lo[8], width[8];
     if ((rc = prior_lo_width(prior, lo, width))) return rc;
     for (int k = 0; k < 8; ++k) ABC_REQUIRE(prior->lo[k] >= 0.0f, "prior lo[%d] < 0", k);
+    if (prop) {
+        ABC_REQUIRE(prop->mix != nullptr && out_w != nullptr, "proposal rows and out_w are required");
+        ABC_REQUIRE(prop->lambda >= 0.0f && prop->lambda <= 1.0f, "lambda must be in [0, 1]");
+        ABC_REQUIRE(isfinite(prop->inflate) && prop->inflate >= 1.0f && prop->inflate <= 100.0f,
+                    "inflate must be in [1, 100]");
+        ABC_REQUIRE(prop->domain <= 15u, "proposal domain > 15");
+    }
 
     // host-side series descriptors
     std::vector<SeriesDesc> desc(m);
@@ -644,7 +699,7 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     while (npow_cap < cand_cap) npow_cap <<= 1;
 
     // device buffers (freed on return)
-    DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days;
+    DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days, b_mixtab;
     ABC_HIP(hipMalloc(&b_desc.p, sizeof(SeriesDesc) * m));
     ABC_HIP(hipMalloc(&b_state.p, sizeof(SeriesState) * m));
     ABC_HIP(hipMalloc(&b_table.p, sizeof(RoundTable)));
@@ -702,6 +757,19 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     a.nc = -1.38629436111989061883f * model->noise_scale * model->noise_scale;
     a.scale = model->noise_scale;
     a.refill_min = refill_min;
+    if (prop) {
+        a.mix = prop->mix;
+        for (int k = 0; k < 8; ++k) { a.prop.lo[k] = prior->lo[k]; a.prop.hi[k] = prior->hi[k]; }
+        proposal_standardiser(a.prop.lo, a.prop.hi, a.prop.tc, a.prop.ts);
+        a.prop.lambda = prop->lambda;
+        a.prop.log_inflate = logf(prop->inflate);
+        a.prop_domain = prop->domain;
+        ABC_HIP(hipMalloc(&b_mixtab.p, sizeof(MixTable) * m));
+        a.tables = reinterpret_cast<const MixTable*>(b_mixtab.p);
+        hipLaunchKernelGGL(k_batch_tables, dim3(m), dim3(MIX_K * MIX_D), 0, s, a.mix, a.prop,
+                           reinterpret_cast<MixTable*>(b_mixtab.p));
+        if ((rc = check_launch("k_batch_tables"))) return rc;
+    }
 
     hipLaunchKernelGGL(k_batch_obs, dim3(m), dim3(256), 0, s,
                        reinterpret_cast<const int32_t* const*>(b_ptrs.p), a.desc, m,
@@ -766,6 +834,7 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     f.band_w = band_w;
     f.out_idx = out_idx;
     f.out_theta = out_theta;
+    f.out_w = prop ? out_w : nullptr;
     f.out_dist = out_dist;
     f.out_count = out_count;
     f.out_used = out_used;
@@ -776,8 +845,8 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
     const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + sizeof(double) * 3 * maxT + 16;
     ABC_REQUIRE(lds_f <= (size_t)max_lds, "quota too large for the finalisation");
     hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(256), lds_f, s, f);
-    hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, out_count, quota,
-                       out_mean, out_cov);
+    hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, f.out_w, out_count,
+                       quota, out_mean, out_cov);
     if ((rc = check_launch("k_batch finalisation"))) return rc;
     std::vector<int32_t> rech(m);
     unsigned long long days = 0;
@@ -813,4 +882,35 @@ extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
         return set_error(ABC_EOVERFLOW, "stopped after %lld graph replays before every quota was met",
                          (long long)replays);
     return ABC_OK;
+}
+
+extern "C" abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
+                                    const abc_prior* prior, const abc_model* model,
+                                    uint64_t seed, uint32_t domain, int32_t quota,
+                                    int64_t round_size, int64_t max_samples, float band_w,
+                                    int32_t rounds_per_graph, int32_t cand_capacity,
+                                    int64_t* out_idx,
+                                    float* out_theta, float* out_dist, int64_t* out_count,
+                                    int64_t* out_used, double* out_mean, double* out_cov,
+                                    abc_batch_stats* stats, void* stream)
+{
+    return batch_run(series, m, prior, model, seed, domain, quota, round_size, max_samples, band_w,
+                     rounds_per_graph, cand_capacity, nullptr, out_idx, out_theta, nullptr, out_dist,
+                     out_count, out_used, out_mean, out_cov, stats, stream);
+}
+
+extern "C" abc_status abc_batch_run_weighted(const abc_batch_series* series, int32_t m,
+                                             const abc_prior* prior, const abc_model* model,
+                                             uint64_t seed, uint32_t domain, int32_t quota,
+                                             int64_t round_size, int64_t max_samples, float band_w,
+                                             int32_t rounds_per_graph, int32_t cand_capacity,
+                                             const abc_batch_proposal* prop, int64_t* out_idx,
+                                             float* out_theta, float* out_w, float* out_dist,
+                                             int64_t* out_count, int64_t* out_used, double* out_mean,
+                                             double* out_cov, abc_batch_stats* stats, void* stream)
+{
+    ABC_REQUIRE(prop != nullptr, "proposal is NULL");
+    return batch_run(series, m, prior, model, seed, domain, quota, round_size, max_samples, band_w,
+                     rounds_per_graph, cand_capacity, prop, out_idx, out_theta, out_w, out_dist,
+                     out_count, out_used, out_mean, out_cov, stats, stream);
 }

@@ -20,6 +20,7 @@
 
 #include "common.hpp"
 #include "model.hpp"
+#include "proposal.hpp"
 
 namespace abc {
 
@@ -28,6 +29,9 @@ constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + NN_IN * NN_H, OFF_W2 = OFF_B1 + 
                   OFF_B2 = OFF_W2 + NN_H * NN_H, OFF_W3 = OFF_B2 + NN_H,
                   OFF_B3 = OFF_W3 + NN_H * NN_OUT, NN_PARAMS = OFF_B3 + NN_OUT;
 constexpr float LOGSIG_LO = -7.0f, LOGSIG_HI = 3.0f;
+static_assert(NN_K == MIX_K && NN_D == MIX_D && NN_OUT == MIX_OUT && LOGSIG_LO == MIX_LOGSIG_LO &&
+                  LOGSIG_HI == MIX_LOGSIG_HI,
+              "network output layout and proposal layout must agree");
 
 typedef uint16_t bf16;
 
@@ -488,9 +492,7 @@ __global__ void k_mdn_init(float* p, uint64_t seed)
 // ----------------------------------------------------------------------------
 struct SampleArgs {
     const float* mix;     // [136] network output for the series
-    float lo[8], hi[8], tc[8], ts[8];
-    float lambda;
-    float log_inflate;    // log of the factor applied to every component sd
+    ProposalBox prop;
     Key key;
     uint32_t domain, series;
     uint64_t first;
@@ -499,110 +501,23 @@ struct SampleArgs {
     float* weight;        // [n]
 };
 
-__device__ float mix_logq(const float* o, const float* th, const float* tc, const float* ts,
-                          float log_inflate)
-{
-    float lmax = -INFINITY;
-    for (int k = 0; k < NN_K; ++k) lmax = fmaxf(lmax, o[k]);
-    float se = 0.0f;
-    for (int k = 0; k < NN_K; ++k) se += expf(o[k] - lmax);
-    const float lse_logits = lmax + logf(se);
-    float L[NN_K], Lmax = -INFINITY;
-    float logjac = 0.0f;
-    for (int j = 0; j < NN_D; ++j) logjac += logf(ts[j]);
-    for (int k = 0; k < NN_K; ++k) {
-        float c = o[k] - lse_logits - 0.5f * NN_D * 1.83787706640934548356f - logjac;
-        for (int j = 0; j < NN_D; ++j) {
-            const float t = (th[j] - tc[j]) / ts[j];
-            const float mu = o[NN_K + k * NN_D + j];
-            const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + k * NN_D + j], LOGSIG_LO), LOGSIG_HI) +
-                             log_inflate;
-            const float u = (t - mu) * expf(-ls);
-            c += -0.5f * u * u - ls;
-        }
-        L[k] = c;
-        Lmax = fmaxf(Lmax, c);
-    }
-    float s = 0.0f;
-    for (int k = 0; k < NN_K; ++k) s += expf(L[k] - Lmax);
-    return Lmax + logf(s);
-}
-
 __global__ __launch_bounds__(256) void k_mdn_sample(SampleArgs a)
 {
     __shared__ float o[NN_OUT];
+    __shared__ MixTable tab;
     for (int q = threadIdx.x; q < NN_OUT; q += blockDim.x) o[q] = a.mix[q];
+    __syncthreads();
+    if (threadIdx.x < MIX_K * MIX_D) mix_table_entry(o, a.prop, threadIdx.x / MIX_D, threadIdx.x % MIX_D, tab);
+    __syncthreads();
+    if (threadIdx.x == 0) mix_table_finish(o, tab);
     __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
-    const uint64_t i = a.first + (uint64_t)k;
-    // component probabilities
-    float lmax = -INFINITY;
-    for (int c = 0; c < NN_K; ++c) lmax = fmaxf(lmax, o[c]);
-    float pi[NN_K], tot = 0.0f;
-    for (int c = 0; c < NN_K; ++c) { pi[c] = expf(o[c] - lmax); tot += pi[c]; }
     float th[8];
-    float logvol = 0.0f;
-    for (int j = 0; j < 8; ++j) logvol += logf(a.hi[j] - a.lo[j]);
-    bool ok = false;
-    for (int att = 0; att < 1024 && !ok; ++att) {
-        const uint32_t day = (uint32_t)att + 1;
-        const uint4 w0 = stream_words(a.key, i, a.series, ctr_word3(day, a.domain, 0));
-        const float u_sel = (float)(w0.x >> 8) * 0x1p-24f;
-        if (u_sel < a.lambda) {
-            const uint4 w1 = stream_words(a.key, i, a.series, ctr_word3(day, a.domain, 1));
-            const uint4 w2 = stream_words(a.key, i, a.series, ctr_word3(day, a.domain, 2));
-            const uint32_t ww[8] = {w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w};
-            for (int j = 0; j < 8; ++j)
-                th[j] = fmaf(a.hi[j] - a.lo[j], (float)(ww[j] >> 8) * 0x1p-24f, a.lo[j]);
-            ok = true;
-            break;
-        }
-        // component by inverse CDF of the softmax
-        const float u_c = (float)(w0.y >> 8) * 0x1p-24f * tot;
-        int comp = NN_K - 1;
-        float acc = 0.0f;
-        for (int c = 0; c < NN_K; ++c) {
-            acc += pi[c];
-            if (u_c < acc) { comp = c; break; }
-        }
-        const uint4 w1 = stream_words(a.key, i, a.series, ctr_word3(day, a.domain, 1));
-        const uint4 w2 = stream_words(a.key, i, a.series, ctr_word3(day, a.domain, 2));
-        const uint32_t ww[8] = {w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w};
-        bool inside = true;
-        for (int j = 0; j < 8; j += 2) {
-            const float u1 = fmaf((float)(ww[j] >> 9), 0x1p-23f, 0x1p-24f);
-            const float u2 = (float)(ww[j + 1] >> 9) * 0x1p-23f;
-            const float r = sqrtf(-2.0f * logf(u1));
-            const float z0 = r * cospif(2.0f * u2), z1 = r * sinpif(2.0f * u2);
-            for (int h = 0; h < 2; ++h) {
-                const int d = j + h;
-                const float mu = o[NN_K + comp * NN_D + d];
-                const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + comp * NN_D + d], LOGSIG_LO), LOGSIG_HI) +
-                                 a.log_inflate;
-                const float t = mu + expf(ls) * (h ? z1 : z0);
-                th[d] = a.tc[d] + a.ts[d] * t;
-                inside = inside && th[d] >= a.lo[d] && th[d] < a.hi[d];
-            }
-        }
-        ok = inside;
-    }
-    if (!ok)  // practically unreachable: each attempt takes the prior branch with prob. lambda
-        for (int j = 0; j < 8; ++j) th[j] = 0.5f * (a.lo[j] + a.hi[j]);
-    const float lq_mix = mix_logq(o, th, a.tc, a.ts, a.log_inflate);
-    const float lq_prior = -logvol;
-    float lq;
-    if (a.lambda <= 0.0f) lq = lq_mix;
-    else if (a.lambda >= 1.0f) lq = lq_prior;
-    else {
-        const float x = logf(1.0f - a.lambda) + lq_mix, y = logf(a.lambda) + lq_prior;
-        const float mx = fmaxf(x, y);
-        lq = mx + logf(expf(x - mx) + expf(y - mx));
-    }
+    const float w = proposal_draw(tab, a.prop, a.key, a.first + (uint64_t)k, a.series, a.domain, th);
     for (int j = 0; j < 8; ++j) a.theta[8 * k + j] = th[j];
-    a.weight[k] = expf(lq_prior - lq);
+    a.weight[k] = w;
 }
-
 
 // K range per split for the weight-gradient products (reduction over the
 // batch): 128 rows per split once K >= 512, else no split.
@@ -786,7 +701,7 @@ extern "C" abc_status abc_mdn_create(const abc_prior* prior, uint64_t init_seed,
         n->lo[j] = prior->lo[j];
         n->hi[j] = prior->hi[j];
         n->tc[j] = 0.5f * (prior->lo[j] + prior->hi[j]);
-        n->ts[j] = (prior->hi[j] - prior->lo[j]) / 3.46410161513775458705f;
+        n->ts[j] = (prior->hi[j] - prior->lo[j]) / 3.46410161513775458705f;  // as proposal_standardiser
     }
     hipError_t e = hipSuccess;
     e = e ? e : hipMalloc((void**)&n->p, NN_PARAMS * sizeof(float));
@@ -1025,10 +940,11 @@ extern "C" abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float
     SampleArgs a{};
     a.mix = mix;
     for (int j = 0; j < 8; ++j) {
-        a.lo[j] = net->lo[j]; a.hi[j] = net->hi[j]; a.tc[j] = net->tc[j]; a.ts[j] = net->ts[j];
+        a.prop.lo[j] = net->lo[j]; a.prop.hi[j] = net->hi[j];
+        a.prop.tc[j] = net->tc[j]; a.prop.ts[j] = net->ts[j];
     }
-    a.lambda = lambda;
-    a.log_inflate = logf(inflate);
+    a.prop.lambda = lambda;
+    a.prop.log_inflate = logf(inflate);
     a.key = make_key(st->seed);
     a.domain = st->domain;
     a.series = st->series;

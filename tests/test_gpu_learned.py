@@ -91,3 +91,28 @@ def test_lambda_one_is_plain_abc(env):
         # draws: the accepted counts agree within binomial noise
         n_plain, n_learn = plain.n(), lr.accepted_total
         assert abs(n_plain - n_learn) < 6 * math.sqrt(n_plain + n_learn) + 5, (n_plain, n_learn)
+
+
+def test_batched_learned_equals_per_series_pass(env):
+    """The persistent batched kernel with the learned proposal keeps exactly the
+    samples, parameters and weights the per-series pass keeps (first quota by
+    index), and its weighted moments follow the oracle's formula."""
+    import oracle
+
+    abc, P, net = env
+    ss, sers, eps = _series(P, 3)
+    quota = 200
+    lam, infl = 0.1, 3.0
+    mix = torch.stack([net.forward(abc.series_features(ser)[None])[0] for ser in sers])
+    b = abc.batch_run(sers, eps, 2, quota, round_size=1 << 18, mix=mix, lam=lam, inflate=infl)
+    for j, ser in enumerate(sers):
+        lr = P.LearnedABC(net, ser, eps[j], 2, series=j, lam=lam, inflate=infl).run(quota)
+        np.testing.assert_array_equal(b["idx"][j].cpu().numpy(), lr.idx.cpu().numpy())
+        np.testing.assert_array_equal(b["theta"][j].cpu().numpy(), lr.theta.cpu().numpy())
+        np.testing.assert_array_equal(b["w"][j].cpu().numpy(), lr.weight.cpu().numpy())
+        m, c = oracle.moments(b["theta"][j].cpu().numpy(), b["w"][j].cpu().numpy())
+        np.testing.assert_allclose(b["mean"][j].cpu().numpy(), m, rtol=1e-12)
+        np.testing.assert_allclose(b["cov"][j].cpu().numpy(), c, rtol=1e-9, atol=1e-13)
+    # lambda = 1: the proposal is the prior and every weight is exactly 1
+    b1 = abc.batch_run(sers, eps, 2, 100, round_size=1 << 18, mix=mix, lam=1.0)
+    assert torch.all(b1["w"] == 1.0)

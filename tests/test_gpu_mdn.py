@@ -138,7 +138,7 @@ def test_sampler_weights_and_importance_identity(A):
     th = th.cpu().numpy().astype(np.float64)
     w = w.cpu().numpy().astype(np.float64)
     lo, hi = W.PRIOR_LO.astype(np.float64), W.PRIOR_HI.astype(np.float64)
-    assert np.all(th >= lo) and np.all(th < hi)
+    assert np.all(th >= lo) and np.all(th <= hi)
     assert np.all(w > 0) and np.all(w <= 1 / 0.05 * (1 + 1e-5))
     # weights = prior / q with the reference density
     lq = ref.defensive_logq(mix_row.astype(np.float64), th[:2000], lo, hi, 0.05)

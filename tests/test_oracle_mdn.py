@@ -98,3 +98,64 @@ def test_subsample_days():
     d = mdn.subsample_days(30)
     assert d[0] == 1 and d[-1] == 30 and np.all(np.diff(d) >= 0)
     assert mdn.subsample_days(200)[-1] == 200
+
+
+LO = np.zeros(8)
+HI = np.array([1, 100, 2, 1, 1, 1, 1, 2], dtype=np.float64)
+
+
+def _row(seed, spread=0.5, shift=0.0):
+    rng = np.random.default_rng(seed)
+    out = rng.standard_normal(mdn.N_OUT) * spread
+    out[mdn.K:mdn.K + mdn.K * mdn.D] += shift
+    return out
+
+
+@pytest.mark.parametrize("inflate,shift", [(1.0, 0.0), (3.0, 0.0), (1.5, 2.5)])
+def test_truncated_proposal_integrates_to_one_on_the_box(inflate, shift):
+    # E over uniform theta in the box of q(theta) * volume = integral of q = 1
+    out = _row(5, shift=shift)
+    rng = np.random.default_rng(6)
+    n = 400_000
+    th = LO + (HI - LO) * rng.random((n, 8))
+    lq = mdn.truncated_logq(out, th, LO, HI, inflate)
+    est = np.exp(lq + np.log(HI - LO).sum()).mean()
+    se = np.exp(lq + np.log(HI - LO).sum()).std() / math.sqrt(n)
+    assert abs(est - 1.0) < max(5 * se, 0.01), (est, se)
+    # and the defensive mixture too
+    lqd = mdn.defensive_logq(out, th, LO, HI, 0.3, inflate)
+    assert abs(np.exp(lqd + np.log(HI - LO).sum()).mean() - 1.0) < max(5 * se, 0.01)
+
+
+def test_truncated_proposal_single_component_is_scipy_truncnorm():
+    out = np.zeros(mdn.N_OUT)
+    out[0] = 60.0  # one component
+    mu = np.linspace(-2.5, 2.5, mdn.D)      # some means outside the box in standardised units
+    ls = np.linspace(-1.0, 0.8, mdn.D)
+    out[mdn.K:mdn.K + mdn.D] = mu
+    out[mdn.K + mdn.K * mdn.D:mdn.K + mdn.K * mdn.D + mdn.D] = ls
+    s = (HI - LO) / math.sqrt(12.0)
+    c = (LO + HI) / 2
+    rng = np.random.default_rng(1)
+    th = LO + (HI - LO) * rng.random((50, 8))
+    got = mdn.truncated_logq(out, th, LO, HI, 1.7)
+    sig = np.exp(ls + math.log(1.7))
+    a = ((LO - c) / s - mu) / sig
+    b = ((HI - c) / s - mu) / sig
+    t = (th - c) / s
+    ref = stats.truncnorm.logpdf(t, a, b, loc=mu, scale=sig).sum(1) - np.log(s).sum()
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_truncated_proposal_without_truncation_is_the_mixture():
+    # components far inside a huge box: every mass is 1 and nothing changes
+    out = _row(7, spread=0.2)
+    out[mdn.K + mdn.K * mdn.D:] = -4.0  # narrow components
+    lo, hi = -1e4 * np.ones(8), 1e4 * np.ones(8)
+    s = (hi - lo) / math.sqrt(12.0)
+    rng = np.random.default_rng(2)
+    t = rng.standard_normal((20, 8)) * 0.05
+    th = (lo + hi) / 2 + s * t
+    got = mdn.truncated_logq(out, th, lo, hi, 1.0)
+    ref = mdn.mixture_logpdf(np.repeat(out[None], 20, 0), t) - np.log(s).sum()
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
