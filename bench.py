@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")
     ap.add_argument("--no-smc", action="store_true")
     ap.add_argument("--smc-particles", type=int, default=4096)
-    ap.add_argument("--smc-generations", type=int, default=8)
+    ap.add_argument("--smc-generations", type=int, default=16)
     ap.add_argument("--smc-alpha", type=float, default=0.5)
     ap.add_argument("--smc-q0", type=float, default=1e-2)
     ap.add_argument("--smc-rejection-samples", type=int, default=1 << 26)

@@ -556,7 +556,10 @@ ABC_API abc_status abc_smc_generation(const abc_series* ser, const abc_model* mo
  * cfg->generations are done or a generation's tolerance reaches eps_min.
  * Outputs are device arrays with one block of N rows per generation:
  * idx [G][N], theta [G][N][8], w [G][N], dist [G][N]; stats host [G];
- * *gens_done (host) = generations completed.
+ * *gens_done (host) = generations completed. From generation 2 on, the first
+ * chunk is sized from the previous generation's consumption (1.25 x its
+ * samples, rounded up to chunk0 x 2^k, at most chunk_max); chunking never
+ * changes a population.
  */
 ABC_API abc_status abc_smc_run(const abc_series* ser, const abc_model* model,
                                const abc_prior* prior, uint64_t seed, uint32_t series,

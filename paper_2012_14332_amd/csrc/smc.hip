@@ -612,12 +612,22 @@ extern "C" abc_status abc_smc_run(const abc_series* ser, const abc_model* model,
     ABC_REQUIRE(gens_done != nullptr && stats != nullptr, "NULL output");
     *gens_done = 0;
     const int N = cfg->n_particles;
+    abc_smc_config c = *cfg;
     for (int t = 0; t < cfg->generations; ++t) {
         if (t > 0 && cfg->eps_min > 0.0f && stats[t - 1].eps <= cfg->eps_min) break;
+        if (t > 1) {
+            // first chunk sized from the previous generation's consumption (the
+            // chunk schedule never changes the population, only the number of
+            // round trips)
+            const int64_t want = stats[t - 1].samples + stats[t - 1].samples / 4;
+            int64_t c0 = cfg->chunk0;
+            while (c0 < want && c0 < cfg->chunk_max) c0 <<= 1;
+            c.chunk0 = c0 < cfg->chunk_max ? c0 : cfg->chunk_max;
+        }
         const size_t o = (size_t)t * N, op = (size_t)(t - 1) * N;
         rc = abc_smc_generation(ser, model, prior, seed, series, t,
                                 t ? theta + 8 * op : nullptr, t ? w + op : nullptr,
-                                t ? dist + op : nullptr, t ? N : 0, cfg, idx + o, theta + 8 * o,
+                                t ? dist + op : nullptr, t ? N : 0, &c, idx + o, theta + 8 * o,
                                 w + o, dist + o, stats + t, nullptr, stream);
         if (rc) return rc;
         *gens_done = t + 1;

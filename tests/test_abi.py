@@ -83,3 +83,53 @@ def test_host_validation_rejects_bad_arguments(built):
     assert rc == -1 and b"flags" in L.abc_last_error()
     # n = 0 is a no-op that needs no device pointers
     assert L.abc_sample_prior(ctypes.byref(pr), ctypes.byref(st), 0, 0, None, None) == 0
+
+
+def test_host_validation_of_the_newer_entry_points(built):
+    """Bad sizes and options of the nearest-k, bands, SMC, batched-proposal and
+    tuning entry points are rejected on the host (ABC_EINVAL), no GPU needed."""
+    from paper_2012_14332_amd import abc
+
+    L = abc.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    pr = abc.make_prior()
+    st = abc.make_stream(1, 1, 0)
+    # nearest-k: k = 0, k > n, k > 4096
+    for n, k in [(10, 0), (10, 11), (100000, 4097)]:
+        assert L.abc_nearest_k(fake, None, ctypes.byref(pr), ctypes.byref(st), n, 0, k, fake, None,
+                               None, None, None) == -1
+    # bands: n > 8192, more than 16 quantiles, a quantile outside [0, 1]
+    q = (ctypes.c_double * 17)(*([0.5] * 17))
+    assert L.abc_trajectory_bands(fake, 8193, 10, q, 1, fake, None) == -1
+    assert L.abc_trajectory_bands(fake, 10, 10, q, 17, fake, None) == -1
+    qb = (ctypes.c_double * 1)(1.5)
+    assert L.abc_trajectory_bands(fake, 10, 10, qb, 1, fake, None) == -1
+    # SMC: population size and alpha out of range
+    ser = abc._Series(1000000, 100, 0, 0, 10, 0x1000)
+    md = abc._Model(1.0, 0)
+    stats = abc._SmcGenStats()
+    for cfg in (abc.smc_config(1, 10.0), abc.smc_config(8193, 10.0), abc.smc_config(100, 10.0, alpha=0.0),
+                abc.smc_config(100, 10.0, chunk0=0)):
+        assert L.abc_smc_generation(ctypes.byref(ser), ctypes.byref(md), ctypes.byref(pr), 1, 0, 0,
+                                    None, None, None, 0, ctypes.byref(cfg), fake, fake, fake, fake,
+                                    ctypes.byref(stats), None, None) == -1
+    # ABC_FP64 is not an SMC mode
+    md64 = abc._Model(1.0, abc.ABC_FP64)
+    cfg = abc.smc_config(100, 10.0)
+    assert L.abc_smc_generation(ctypes.byref(ser), ctypes.byref(md64), ctypes.byref(pr), 1, 0, 0,
+                                None, None, None, 0, ctypes.byref(cfg), fake, fake, fake, fake,
+                                ctypes.byref(stats), None, None) == -1
+    # refill threshold
+    assert L.abc_set_refill_min(65) == -1 and L.abc_set_refill_min(-1) == -1
+    assert L.abc_get_refill_min() == 8
+    # batched proposal: NULL proposal, lambda and inflate out of range
+    bs = (abc._BatchSeries * 1)(abc._BatchSeries(1000000, 100, 0, 0, 10, 0x1000, 1.0, 0))
+    bst = abc._BatchStats()
+    assert L.abc_batch_run_weighted(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 10, 4096, 100,
+                                    0.02, 1, 0, None, fake, fake, fake, fake, fake, fake, fake, fake,
+                                    ctypes.byref(bst), None) == -1
+    for lam, infl in [(1.5, 2.0), (0.5, 0.5), (0.5, 200.0)]:
+        prop = abc._BatchProposal(0x1000, lam, infl, 5, 0)
+        assert L.abc_batch_run_weighted(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 10, 4096,
+                                        100, 0.02, 1, 0, ctypes.byref(prop), fake, fake, fake, fake,
+                                        fake, fake, fake, fake, ctypes.byref(bst), None) == -1
