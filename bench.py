@@ -183,18 +183,39 @@ def learned_leg(args, batched):
     used = lb["used"].cpu().numpy()
     samples = int(used.sum())
     # posterior comparison against plain ABC at the same eps with Qc accepted each
+    # posterior check: independent runs on other seeds pooled, >= 1e4 plain
+    # accepts and >= 1e4 effective learned samples per series, weighted moments
+    # of the pooled rows by the same FP64 moments kernel
     Qc = args.compare_quota
-    cap_c = min(4 * Qc, 8192)  # the finalisation sorts the candidates of a series in LDS
-    plain = abc.batch_run(sers, eps, 2, Qc, round_size=1 << 22, cand_capacity=cap_c)
-    pm = plain["mean"].cpu().numpy()
-    psd = np.sqrt(np.maximum(np.diagonal(plain["cov"].cpu().numpy(), axis1=1, axis2=2), 0))
-    lc = lb if Qc == Q else abc.batch_run(sers, eps, 2, Qc, **dict(kw, cand_capacity=cap_c))
-    lm = lc["mean"].cpu().numpy()
-    lsd = np.sqrt(np.maximum(np.diagonal(lc["cov"].cpu().numpy(), axis1=1, axis2=2), 0))
-    wc = lc["w"].double().cpu().numpy()
-    ess_c = wc.sum(1) ** 2 / (wc * wc).sum(1)
-    ok_mu = np.abs(lm - pm) <= 0.05 * np.maximum(np.abs(pm), psd)
+    cap_c = min(2 * Qc, 8192)  # the finalisation sorts the candidates of a series in LDS
+
+    def pooled(runs_kw, seeds):
+        th, ww = [], []
+        for sd in seeds:
+            o = abc.batch_run(sers, eps, sd, Qc, round_size=1 << 22, cand_capacity=cap_c, **runs_kw)
+            th.append(o["theta"])
+            ww.append(o["w"] if "w" in o else torch.ones((len(sers), Qc), device="cuda"))
+        th = torch.cat(th, dim=1)
+        ww = torch.cat(ww, dim=1)
+        mean = np.zeros((len(sers), 8))
+        sd_ = np.zeros((len(sers), 8))
+        ess_ = np.zeros(len(sers))
+        for j in range(len(sers)):
+            m_, c_ = abc.posterior_moments(th[j].contiguous(), ww[j].contiguous())
+            mean[j] = m_.cpu().numpy()
+            sd_[j] = np.sqrt(np.maximum(np.diag(c_.cpu().numpy()), 0))
+            wj = ww[j].double().cpu().numpy()
+            ess_[j] = wj.sum() ** 2 / (wj * wj).sum()
+        return mean, sd_, ess_
+
+    pm, psd, pn = pooled({}, args.compare_seeds_plain)
+    lkw = dict(mix=mix, lam=args.lam, inflate=args.inflate)
+    lm, lsd, ess_c = pooled(lkw, args.compare_seeds_learned)
+    tol_mu = 0.05 * np.maximum(np.abs(pm), psd)
+    ok_mu = np.abs(lm - pm) <= tol_mu
     ok_sd = np.abs(lsd - psd) <= 0.05 * psd
+    worst_mu = (np.abs(lm - pm) / tol_mu).max(1)
+    worst_sd = (np.abs(lsd - psd) / (0.05 * psd)).max(1)
     gains = [(Q / u) / (Q / pu) for u, pu in zip(used, batched["_used"])]
     net.close()
     return {
@@ -218,8 +239,14 @@ def learned_leg(args, batched):
         "ess_median": float(np.median(ess_series)),
         "wall_s": wall,
         "samples": samples,
-        "posterior_check_quota": Qc,
+        "posterior_check": "plain: %d seeds x %d accepted per series pooled; learned: %d seeds x %d "
+                           "accepted pooled (weights kept)" % (len(args.compare_seeds_plain), Qc,
+                                                               len(args.compare_seeds_learned), Qc),
+        "posterior_check_plain_n": int(pn.min()),
         "posterior_check_ess_median": float(np.median(ess_c)),
+        "posterior_check_ess_min": float(ess_c.min()),
+        "posterior_worst_mean_over_tol_per_series": [round(float(x), 3) for x in worst_mu],
+        "posterior_worst_sd_over_tol_per_series": [round(float(x), 3) for x in worst_sd],
         "posterior_mean_within_5pct": float(ok_mu.mean()),
         "posterior_sd_within_5pct": float(ok_sd.mean()),
         "posterior_both_within_5pct_series": int(np.sum(ok_mu.all(1) & ok_sd.all(1))),
@@ -306,6 +333,8 @@ def main():
     ap.add_argument("--lam", type=float, default=0.5)
     ap.add_argument("--inflate", type=float, default=8.0)
     ap.add_argument("--compare-quota", type=int, default=4096)
+    ap.add_argument("--compare-seeds-plain", type=int, nargs="+", default=[2, 3, 4])
+    ap.add_argument("--compare-seeds-learned", type=int, nargs="+", default=[2, 3, 4, 5])
     ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")
     ap.add_argument("--no-smc", action="store_true")
     ap.add_argument("--smc-particles", type=int, default=4096)
