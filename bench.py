@@ -379,14 +379,21 @@ def main():
     first0 = args.pilot  # main-run indices follow the pilot prefix
     runs = [PL.PlainABC(ser, 1, e, N, series=c, band_w=args.band) for c, (ser, e) in
             enumerate(zip(sers, eps))]
+    # stream A simulates back to back; stream B compacts each country's
+    # distances as soon as its launch ends (HBM-bound, it overlaps the next
+    # launch); stream C makes the float64 band decision and the moments
     sA = torch.cuda.current_stream()
     sB = torch.cuda.Stream()
+    sC = torch.cuda.Stream()
     days = torch.zeros(1, dtype=torch.int64, device="cuda")
+    compacted = [None] * len(runs)  # last compaction of each country's distance buffer
 
     def step(s, keep, ev):
         first = first0 + s * N
         for c, r in enumerate(runs):
             e_hi = r.eps * (1 + r.band_w)
+            if compacted[c] is not None:
+                sA.wait_event(compacted[c])  # the buffer is free once compacted
             if ev is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e0.record(sA)
@@ -396,12 +403,16 @@ def main():
                 e1 = torch.cuda.Event(enable_timing=True)
                 e1.record(sA)
                 ev.append((e0, e1, c))
-            idx, th, d, _, cnt = abc.accept_compact(r.dist, e_hi, r.cap, first=first, seed=r.seed,
-                                                    series=c)
-            done = torch.cuda.Event()
-            done.record(sA)
+            simulated = torch.cuda.Event()
+            simulated.record(sA)
             with torch.cuda.stream(sB):
-                sB.wait_event(done)
+                sB.wait_event(simulated)
+                idx, th, d, _, cnt = abc.accept_compact(r.dist, e_hi, r.cap, first=first,
+                                                        seed=r.seed, series=c)
+                compacted[c] = torch.cuda.Event()
+                compacted[c].record(sB)
+            with torch.cuda.stream(sC):
+                sC.wait_event(compacted[c])
                 abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
                 mean, cov = abc.posterior_moments(th, n_dev=cnt)
             keep.append((c, idx, th, cnt, mean, cov))
