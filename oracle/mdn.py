@@ -212,9 +212,13 @@ def truncated_logq(out_row, theta, lo, hi, inflate=1.0):
 
 def defensive_logq(out_row, theta, lo, hi, lam, inflate=1.0):
     """log of the defensive proposal density at theta (original units):
-    (1 - lam) * truncated mixture (component sds times `inflate`) + lam * prior."""
+    (1 - lam) * truncated mixture (component sds times `inflate`) + lam * prior;
+    the prior alone when every component is dropped."""
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
-    lq_mix = truncated_logq(out_row, theta, lo, hi, inflate)
     lq_prior = -np.log(hi - lo).sum()
+    if not np.any(np.all(truncated_masses(out_row, lo, hi, inflate) >= 1e-30, axis=1)):
+        # no component has mass in the box: the proposal is the prior
+        return np.full(np.asarray(theta).reshape(-1, 8).shape[0], lq_prior)
+    lq_mix = truncated_logq(out_row, theta, lo, hi, inflate)
     return np.logaddexp(np.log1p(-lam) + lq_mix, np.log(lam) + lq_prior) if lam > 0 else lq_mix

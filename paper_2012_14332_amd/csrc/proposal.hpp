@@ -34,7 +34,8 @@ struct ProposalBox {
 // keeps the upper-tail masses Q(alpha), Q(beta); kind 2 (beta <= 0) keeps
 // Q(-beta), Q(-alpha), so no mass is formed as a difference of numbers near
 // one. logz_k = sum_j log Z_kj (Z = truncated mass); a component with a mass
-// below 1e-30 in some dimension is dropped (weight 0).
+// below 1e-30 in some dimension is dropped (weight 0); if every component is
+// dropped, the proposal is the prior itself (weight 1).
 struct MixTable {
     float p1[MIX_K * MIX_D], p2[MIX_K * MIX_D];
     int32_t kind[MIX_K * MIX_D];
@@ -42,6 +43,7 @@ struct MixTable {
     float logw[MIX_K];   // log of the renormalised component weights (-inf: dropped)
     float cum[MIX_K];    // running sums of the renormalised weights
     float logz[MIX_K];
+    int32_t empty;       // every component dropped: the proposal is the prior
 };
 
 __device__ __forceinline__ float q_upper(float x) { return 0.5f * erfcf(x * 0.70710678118654752440f); }
@@ -103,6 +105,7 @@ __device__ inline void mix_table_finish(const float* o, MixTable& t)
         t.cum[k] = acc;
         t.logw[k] = w[k] > 0.0f ? logf(w[k] / tot) : -INFINITY;
     }
+    t.empty = tot > 0.0f ? 0 : 1;
 }
 
 // The whole table of one row in one thread.
@@ -150,6 +153,11 @@ __device__ inline float proposal_draw(const MixTable& t, const ProposalBox& p, K
     float logvol = 0.0f;
     for (int j = 0; j < 8; ++j) logvol += logf(p.hi[j] - p.lo[j]);
     const float u_sel = (float)(w0.x >> 8) * 0x1p-24f;
+    if (t.empty) {  // no component has mass in the box: the proposal is the prior
+        for (int j = 0; j < 8; ++j)
+            th[j] = fmaf(p.hi[j] - p.lo[j], (float)(ww[j] >> 8) * 0x1p-24f, p.lo[j]);
+        return 1.0f;
+    }
     if (u_sel < p.lambda) {
         for (int j = 0; j < 8; ++j)
             th[j] = fmaf(p.hi[j] - p.lo[j], (float)(ww[j] >> 8) * 0x1p-24f, p.lo[j]);

@@ -157,4 +157,12 @@ def test_sampler_weights_and_importance_identity(A):
     # lambda = 1 is the prior itself: every weight is exactly 1
     _, w1 = net.sample(mix, 1000, seed=4, lam=1.0)
     assert torch.all(w1 == 1.0)
+    # a mixture with no mass in the box falls back to the prior (weights 1)
+    far = np.zeros(136, dtype=np.float32)
+    far[8:8 + 64] = 60.0
+    far[8 + 64:] = -5.0
+    the, we = net.sample(torch.from_numpy(far).cuda(), 2000, seed=4, lam=0.2)
+    assert torch.all(we == 1.0)
+    the = the.cpu().numpy()
+    assert np.all(the >= lo) and np.all(the <= hi)
     net.close()

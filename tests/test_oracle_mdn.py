@@ -159,3 +159,13 @@ def test_truncated_proposal_without_truncation_is_the_mixture():
     got = mdn.truncated_logq(out, th, lo, hi, 1.0)
     ref = mdn.mixture_logpdf(np.repeat(out[None], 20, 0), t) - np.log(s).sum()
     np.testing.assert_allclose(got, ref, rtol=1e-12)
+
+
+def test_proposal_with_no_mass_in_the_box_is_the_prior():
+    out = np.zeros(mdn.N_OUT)
+    out[mdn.K:mdn.K + mdn.K * mdn.D] = 60.0     # every mean far above the box
+    out[mdn.K + mdn.K * mdn.D:] = -5.0          # narrow components
+    Z = mdn.truncated_masses(out, LO, HI, 1.0)
+    assert np.all(Z < 1e-30)
+    th = LO + (HI - LO) * np.random.default_rng(3).random((5, 8))
+    np.testing.assert_allclose(mdn.defensive_logq(out, th, LO, HI, 0.3), -np.log(HI - LO).sum())
