@@ -234,6 +234,11 @@ __global__ __launch_bounds__(256) void k_smc_propose(ProposeArgs a)
     if (a.anc) a.anc[k] = j;
 }
 
+__global__ void k_smc_zero_u64(unsigned long long* p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
 // Number of rows of theta [m][8] inside the closed box (added to *count).
 __global__ __launch_bounds__(256) void k_smc_count_box(const float* theta, int64_t m, abc_prior box,
                                                        unsigned long long* count)
@@ -487,7 +492,7 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
                              "is not positive definite", gen);
         eps = h.eps;
     }
-    ABC_HIP(hipMemsetAsync(dbox, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_smc_zero_u64, dim3(1), dim3(64), 0, s, dbox);
 
     const float e_hi = cfg->band_w > 0.0f ? (float)((double)eps * (1.0 + (double)cfg->band_w)) : eps;
     int got = 0;

@@ -1,0 +1,102 @@
+"""Parity at the benchmark's full sizes and launch configuration, on sampled
+outputs the FP64 oracle computes one by one.
+
+Three countries at 1e7 prior samples each (indices 1e5 .. 1e5 + 1e7 - 1, the
+benchmark's range, default launch shape, early exit at eps (1 + w), float64
+band decision): for 1500 random indices per country plus every accepted one,
+the oracle's distance is computed; the accept decision must be the oracle's
+outside the tie band |d - eps| < 1e-5 eps, early-exited samples must have an
+oracle distance above eps, and completed float32 distances near eps must be
+within the stated float32 accuracy. The 64-series batched run (quota 1000,
+rounds of 2^22) is checked the same way on its first-quota rows and on a
+sample of the rows it rejected in each series' consumed prefix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2012_14332_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+TIE = 1e-5
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_14332_amd import abc, pipeline as P
+
+    abc.lib()
+    abc.set_launch_config(0, 0, 0)
+    abc.set_refill_min(0)
+    return abc, P
+
+
+def _oracle_d(m, obs, seed, idx, series):
+    return np.array([oracle.distances(m, obs, seed, 1, first=int(i), series=series)[0] for i in idx])
+
+
+@pytest.mark.parametrize("c", [0, 1, 2])
+def test_three_countries_full_size(env, c):
+    abc, P = env
+    s = W.three_countries()[c]
+    m = oracle.make_model(s.P, s.T)
+    obs = oracle.observe(m, s.theta_true, s.obs_seed)
+    ser = P.observed_series(s)
+    eps = P.pilot_eps(ser, 1, n=100_000, q=1e-4, series=c)
+    N, first, w = 10_000_000, 100_000, 0.02
+    run = P.PlainABC(ser, 1, eps, N, series=c, band_w=w)
+    res = run.run(first)
+    acc = res.idx[:res.n()].cpu().numpy()
+    d32 = run.dist.cpu().numpy()  # float32 distances after early exit (band rows unchanged here)
+    rng = np.random.default_rng(100 + c)
+    smp = np.sort(rng.choice(N, size=1500, replace=False)) + first
+    idx = np.unique(np.concatenate([smp, acc]))
+    ref = _oracle_d(m, obs, 1, idx, c)
+    want = idx[ref <= eps]
+    tie = idx[np.abs(ref - eps) < TIE * eps]
+    # accepted set: the oracle's on every checked index, outside the tie band
+    got = set(acc.tolist())
+    wrong = [int(i) for i in idx if ((i in got) != (i in set(want.tolist()))) and i not in set(tie.tolist())]
+    assert not wrong, wrong[:10]
+    # early exit only where the oracle distance is above eps
+    d = d32[idx - first].astype(np.float64)
+    ex = np.isinf(d)
+    assert np.all(ref[ex] > eps)
+    # completed float32 distances: accuracy near eps and overall
+    fin = ~ex
+    rel = np.abs(d[fin] - ref[fin]) / ref[fin]
+    near = ref[fin] <= 2 * eps
+    assert np.median(rel) < 1e-5
+    assert rel[near].max() < 1e-2, rel[near].max()
+    print("country %d: %d accepted, %d checked, max rel err near eps %.2e, %d exited of %d sampled"
+          % (c, acc.size, idx.size, rel[near].max() if near.any() else 0.0, ex[np.isin(idx, smp)].sum(),
+             smp.size))
+
+
+def test_batched_64_series_full_size(env):
+    abc, P = env
+    ss = W.uneven_series(64, 5)
+    sers = [P.observed_series(s) for s in ss]
+    eps = [P.pilot_eps(ser, 2, n=100_000, q=1e-4, series=j) for j, ser in enumerate(sers)]
+    Q = 1000
+    o = abc.batch_run(sers, eps, 2, Q, round_size=1 << 22, cand_capacity=4 * Q)
+    rng = np.random.default_rng(7)
+    for j in range(0, 64, 3):  # every third series
+        s = ss[j]
+        m = oracle.make_model(s.P, s.T)
+        obs = oracle.observe(m, s.theta_true, s.obs_seed, series=j)
+        kept = o["idx"][j].cpu().numpy()
+        used = int(o["used"][j].item())
+        # the first-quota rows: oracle distance within eps (tie band aside)
+        chk = rng.choice(kept, size=40, replace=False)
+        ref = _oracle_d(m, obs, 2, chk, j)
+        assert np.all(ref <= eps[j] * (1 + TIE)), (j, ref.max() / eps[j])
+        # rows before the last kept index that were not kept: the oracle rejects them
+        last = int(kept.max())
+        pool = np.setdiff1d(rng.choice(last + 1, size=min(last + 1, 400), replace=False), kept)[:60]
+        ref_r = _oracle_d(m, obs, 2, pool, j)
+        assert np.all(ref_r > eps[j] * (1 - TIE)), (j, ref_r.min() / eps[j])
+        assert last < used
