@@ -131,6 +131,11 @@ def batched_leg(args):
         "rounds": st["rounds"],
         "graph_replays": st["graph_replays"],
         "rounds_ms": st["rounds_ms"],
+        # algorithmic VALU rate of the round kernels over the replays' wall time
+        # (host waits between replays included, so a lower bound on the kernel's)
+        "valu_frac_rounds_lower_bound": VALU_PER_SAMPLE_DAY * st["sample_days"] /
+                                        (st["rounds_ms"] * 1e-3) / (VALU_PEAK_TOPS * 1e12),
+        "refill_min": tune.get("refill"),
         "rechecked_fp64": st["rechecked"],
         "launch_shape": [st["spl"], st["block"], st["grid"]],
         "lds_bytes": st["lds_bytes"],
@@ -309,6 +314,46 @@ def smc_leg(args):
         "rejection_s_for_N": need * rej_s / n_rej,
         "simulation_gain": need / sims if sims else None,
         "wall_gain": (need * rej_s / n_rej) / smc_s,
+    }
+
+
+def paper_style_leg(args):
+    """Like-for-like with the paper's per-run figures (Sec. 4: T = 49, raw-count
+    distance, full trajectories, no early exit): simulator throughput of the
+    single synthetic country in trajectories/s and simulated days/s, next to
+    the paper's 2x Mk1 IPU, V100 and 2-socket Xeon numbers (other hardware,
+    real data; context only)."""
+    import torch
+
+    from paper_2012_14332_amd import abc
+    from paper_2012_14332_amd import pipeline as PL
+    from paper_2012_14332_amd import workloads as W
+
+    s = W.single_country()
+    ser = PL.observed_series(s)
+    n = 10_000_000
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    run = lambda f: abc.simulate_distance(ser, n, 1, first=f, flags=abc.ABC_DIST_RAW, out=out)
+    run(0)
+    torch.cuda.synchronize()
+    reps = 5
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        run((r + 1) * n)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    traj = n / sec
+    paper = {"2x_Mk1_IPU": 4.25e7, "V100": 5.68e6, "2x_Xeon_Gold_6248": 1.38e6}
+    return {
+        "workload": "%s, raw-count distance, all %d days simulated (no early exit), %d samples per "
+                    "launch, %d launches" % (s.name, s.T, n, reps),
+        "trajectories_per_s": traj,
+        "sim_days_per_s": traj * s.T,
+        "paper_trajectories_per_s": paper,
+        "ratio_to_paper": {k: traj / v for k, v in paper.items()},
     }
 
 
@@ -500,6 +545,7 @@ def main():
         out["batched"].pop("_used", None)
     if not args.no_smc:
         out["smc"] = smc_leg(args)
+    out["paper_style"] = paper_style_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
     print(json.dumps(out))

@@ -23,6 +23,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -84,6 +85,7 @@ struct BatchArgs {
     float nc;               // -2 ln(2) s^2 of the Box-Muller radius
     float scale;
     int32_t refill_min;     // refill a wave's idle lanes once at least this many are idle
+    const int32_t* order;   // [m] series in planning order (longest horizon first)
     const float* mix;       // null: prior draws; else [m][136] proposal rows (learned proposal)
     const MixTable* tables; // [m] truncated-mixture tables of the rows
     ProposalBox prop;
@@ -141,11 +143,14 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
 {
     __shared__ int wave_cnt[BT_MAX_SERIES / 64];
     __shared__ int chunk_wave[BT_MAX_SERIES / 64];
-    const int s = threadIdx.x;
-    const int lane = s & 63, wave = s >> 6;
+    // thread t plans series order[t]: chunks are laid out longest horizon
+    // first, so every wave ends its share of a round on short trajectories
+    const int tid = threadIdx.x;
+    const int s = tid < a.m ? a.order[tid] : tid;
+    const int lane = tid & 63, wave = tid >> 6;
     bool active = false;
     int64_t next = 0;
-    if (s < a.m) {
+    if (tid < a.m) {
         next = a.state[s].next;
         active = a.state[s].certain < a.quota && next < a.max_samples;
     }
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
         t->chunk0[rank] = c0;
         a.state[s].next = next + n_s;
     }
-    if (s == 0) {
+    if (tid == 0) {
         t->n_active = n_active;
         t->total_chunks = ctot;
         t->chunk0[n_active] = ctot;
@@ -699,7 +704,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     while (npow_cap < cand_cap) npow_cap <<= 1;
 
     // device buffers (freed on return)
-    DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days, b_mixtab;
+    DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days, b_mixtab, b_order;
     ABC_HIP(hipMalloc(&b_desc.p, sizeof(SeriesDesc) * m));
     ABC_HIP(hipMalloc(&b_state.p, sizeof(SeriesState) * m));
     ABC_HIP(hipMalloc(&b_table.p, sizeof(RoundTable)));
@@ -734,6 +739,11 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
 
     ABC_HIP(hipMemcpyAsync(b_desc.p, desc.data(), sizeof(SeriesDesc) * m, hipMemcpyHostToDevice, s));
     ABC_HIP(hipMemcpyAsync(b_ptrs.p, obs_ptr.data(), sizeof(const int32_t*) * m, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> order(m);
+    for (int q = 0; q < m; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return series[x].T > series[y].T; });
+    ABC_HIP(hipMalloc(&b_order.p, sizeof(int32_t) * m));
+    ABC_HIP(hipMemcpyAsync(b_order.p, order.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
     ABC_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope with this call
 
     BatchArgs a{};
@@ -747,6 +757,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     a.domain = domain;
     for (int k = 0; k < 8; ++k) { a.lo[k] = lo[k]; a.width[k] = width[k]; }
     a.desc = reinterpret_cast<const SeriesDesc*>(b_desc.p);
+    a.order = reinterpret_cast<const int32_t*>(b_order.p);
     a.state = reinterpret_cast<SeriesState*>(b_state.p);
     a.table = reinterpret_cast<RoundTable*>(b_table.p);
     a.obs_table = reinterpret_cast<const float*>(b_obs.p);
