@@ -84,15 +84,18 @@ def test_precision_study(env):
         # full scale: FP32 variants (with the band) against the FP64 device path
         big = {}
         chunk = 1 << 25
-        for name, flags in (("fp32_naive", 0), ("fp32_kahan", abc.ABC_KAHAN), ("fp64", abc.ABC_FP64)):
+        for name, flags in (("fp32_naive", 0), ("fp32_kahan", abc.ABC_KAHAN), ("fp64", abc.ABC_FP64),
+                            ("fp32_naive_no_band", -1)):
             idx_all, th_all = [], []
             t0 = torch.cuda.Event(enable_timing=True)
             t1 = torch.cuda.Event(enable_timing=True)
             t0.record()
             for f0 in range(first, first + per_country, chunk):
                 n = min(chunk, first + per_country - f0)
-                if flags == abc.ABC_FP64:
-                    dist = abc.simulate_distance(ser, n, 1, first=f0, series=c, flags=flags,
+                if flags == abc.ABC_FP64 or flags == -1:
+                    # float64 throughout, or float32 throughout (no float64 band decision)
+                    fl = abc.ABC_FP64 if flags == abc.ABC_FP64 else 0
+                    dist = abc.simulate_distance(ser, n, 1, first=f0, series=c, flags=fl,
                                                  eps_exit=eps)
                     idx, th, _, _, cnt = abc.accept_compact(dist, eps, 1 << 16, first=f0, seed=1,
                                                             series=c)
@@ -127,5 +130,9 @@ def test_precision_study(env):
             assert diff.size <= 2, diff.size
             assert np.all(np.abs(b["mean"] - ref64["mean"]) <= 1e-3 * sd)
         rep["fp64"]["scale"] = {"accepted": int(ref64["idx"].size), "ms": ref64["ms"]}
+        nb = big["fp32_naive_no_band"]
+        rep["fp32_naive"]["scale"]["accept_set_differences_vs_fp64_without_band"] = int(
+            np.setxor1d(nb["idx"], ref64["idx"]).size)
+        assert rep["fp32_naive"]["scale"]["accept_set_differences_vs_fp64_without_band"] <= 20
         report["countries"][s.name] = rep
     print("PRECISION_REPORT " + json.dumps(report))
