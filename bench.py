@@ -25,8 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "accepted ABC samples/s at fixed ε (sim-days/s, VALU %); plain vs learned proposal"
 # VALU instructions of one simulated day in the float32 kernel, counted from
-# its gfx950 assembly (16 v_mad_u64_u32, 22 transcendental, 111 other).
-VALU_PER_SAMPLE_DAY = 149
+# its gfx950 assembly (16 v_mad_u64_u32, 22 transcendental, 119 other; 8 of
+# them look up the lower bound on the days still to come).
+VALU_PER_SAMPLE_DAY = 157
 # FP32 operations of one simulated day (FMA = 2, transcendental = 1).
 FP32_FLOP_PER_SAMPLE_DAY = 72
 # Peak VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s.

@@ -63,6 +63,8 @@ typedef int32_t abc_status;
 #define ABC_DIST_RAW 0x8u      /* Euclidean distance on raw counts (default: log1p counts) */
 #define ABC_SUPPORT 0x10u      /* supplied theta: rows outside the closed prior box have prior
                                   density zero and get distance +INF without simulation */
+#define ABC_NO_BOUND 0x20u     /* float32 early exit on the running sum alone: no lower bound
+                                  on the days still to come from the cumulative R and D */
 
 #define ABC_T_MAX 1024         /* longest horizon a series may have */
 
@@ -130,8 +132,13 @@ ABC_API abc_status abc_sample_prior(const abc_prior* prior, const abc_stream* st
  *           reports dist +INF.
  *   eps_exit  early-exit bound: a sample stops as soon as its running squared
  *           distance exceeds eps_exit^2 (with a margin that can never flip an
- *           accept decision at eps <= eps_exit) and reports +INF. Pass +INF to
- *           simulate every day.
+ *           accept decision at eps <= eps_exit) and reports +INF. For the
+ *           float32 log1p distance the running sum is first raised by a lower
+ *           bound on the days still to come (recovered and dead counts never
+ *           fall, so a count already above a later observation must still pay
+ *           for it), kept below what float32 rounding could undo; ABC_NO_BOUND
+ *           turns that off. Either way +INF means the float32 distance would
+ *           have ended above eps_exit. Pass +INF to simulate every day.
  *   dist    device float32 [n]: the distance, or +INF after an early exit.
  *   dist64  device float64 [n] or NULL: the same value before rounding to
  *           float32 (with ABC_FP64 the full double result).

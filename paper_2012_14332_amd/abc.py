@@ -21,6 +21,7 @@ ABC_KAHAN = 0x2
 ABC_NOISE_LITERAL = 0x4
 ABC_DIST_RAW = 0x8
 ABC_SUPPORT = 0x10
+ABC_NO_BOUND = 0x20
 T_MAX = 1024
 
 PRIOR_LO = (0.0,) * 8

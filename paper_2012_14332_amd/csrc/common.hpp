@@ -70,7 +70,8 @@ inline abc_status check_model(const abc_model* m)
 {
     ABC_REQUIRE(m != nullptr, "model is NULL");
     ABC_REQUIRE(isfinite(m->noise_scale) && m->noise_scale >= 0.0f, "noise_scale must be finite and >= 0");
-    ABC_REQUIRE((m->flags & ~(ABC_FP64 | ABC_KAHAN | ABC_NOISE_LITERAL | ABC_DIST_RAW | ABC_SUPPORT)) == 0u,
+    ABC_REQUIRE((m->flags & ~(ABC_FP64 | ABC_KAHAN | ABC_NOISE_LITERAL | ABC_DIST_RAW | ABC_SUPPORT |
+                               ABC_NO_BOUND)) == 0u,
                 "unknown model flags 0x%x", m->flags);
     return ABC_OK;
 }

@@ -40,6 +40,8 @@ struct SimArgs {
     unsigned long long* days;  // nullable: += sample-days executed
     int32_t* traj;       // record mode: [n][T+1][6]
     int32_t refill_min;  // refill a wave's idle lanes once at least this many are idle
+    int32_t lb_ntb;      // future-days bound table: time blocks (0 = no bound)
+    int32_t lb_sh;       // days per time block = 2^lb_sh
 };
 
 __device__ __forceinline__ void load_or_draw_theta(const SimArgs& a, bool prior, int64_t k,
@@ -105,6 +107,56 @@ __device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, uint32_t 
     out.pad = (!PRIOR && a.box && outside_box(a, thv)) ? 1 : 0;  // 1: prior density zero
 }
 
+// ---------------------------------------------------------------------------
+// Lower bound on the squared distance still to come (log1p distance only).
+//
+// Recovered R and dead D are cumulative: the model only ever adds to them, so
+// after day t every later simulated count X_s >= X_t. Where X_t already lies
+// above a later observation O_s, day s contributes at least
+// (log2(1+X_t) - log2(1+O_s))^2 whatever happens in between. Summed over the
+// days after t this gives F_t(a) = sum_{s>t} max(0, a - b_s)^2 with
+// a = log2(1+X_t), b_s = log2(1+O_s); a sample whose running sum plus
+// F_t(a_R) + F_t(a_D) already passes the exit bound cannot finish below it.
+// F_t(a) grows with a and shrinks with t, so the table stores it at grid
+// points a = q/2 (looked up with q rounded down) and, for each block of 2^sh
+// days, at the block's last day: every lookup is a lower bound of the exact
+// value. Entries are reduced by the float32 rounding the day loop can commit
+// (a per-term error below 2^-17 in log2 units and the running-sum rounding),
+// so an exit taken on the bound is one the plain running sum would also have
+// reached by day T: distances that are reported never change, and +INF still
+// means the float32 distance ends above the exit bound.
+// ---------------------------------------------------------------------------
+constexpr int LB_Q = 64;          // grid a = 0, 0.5, ..., 31.5 (log2(1 + X) <= 31)
+constexpr int LB_MAX_BLOCKS = 96; // time blocks per table (48 KB for R and D)
+
+// Column col = c * LB_Q + q of the table: grid point q of table c (0 = R,
+// 1 = D). bval holds b_s for R then D in float64, staged by the caller.
+__device__ void build_future_bound(const double* bval, int T, int sh, int ntb, double exit2,
+                                   int col_id, float* tab)
+{
+    const int c = col_id / LB_Q;
+    const int q = col_id % LB_Q;
+    const double g = 0.5 * q;
+    const double* b = bval + c * T;
+    float* col = tab + c * ntb * LB_Q + q;
+    const double e = 0x1p-17;                         // float32 error of one log2 term
+    const double sum_err = 2.0 * T * 0x1p-24 * exit2; // running-sum rounding below the bound
+    double F = 0.0;                                   // sum over days after t
+    for (int t = T; t >= 0; --t) {
+        const int tb = t >> sh;
+        const int tend = min(((tb + 1) << sh) - 1, T);
+        if (t == tend) {
+            double v = F - 2.0 * e * sqrt((double)T * F) - sum_err;
+            v *= 1.0 - 0x1p-20;
+            col[tb * LB_Q] = v > 0.0 ? (float)v : 0.0f;
+        }
+        if (t >= 1) {
+            const double x = g - b[t - 1];
+            if (x > 0.0) F += x * x;
+        }
+    }
+}
+
 struct Lane {
     State s;
     RatesF r;
@@ -122,7 +174,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     extern __shared__ float lds_f[];
     const int T = a.T;
     const int obs_words = (3 * T + 3) & ~3;
-    Slot* ring_all = reinterpret_cast<Slot*>(lds_f + obs_words);
+    const int ntb = DIST == 0 ? a.lb_ntb : 0;
+    float* tab = lds_f + obs_words;  // [2][ntb][LB_Q] future-days bound
+    Slot* ring_all = reinterpret_cast<Slot*>(lds_f + obs_words + 2 * LB_Q * ntb);
 
     // observed series: log2(1 + O) for the log1p distance (accumulated in
     // log2 units), or the count itself for the raw distance
@@ -132,6 +186,15 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
             lds_f[q] = (float)(log1p((double)O) * 1.44269504088896340736);
         else
             lds_f[q] = __int_as_float(O);
+    }
+    if (DIST == 0 && ntb > 0) {
+        // b_s of R and D in float64, staged where the ring will live
+        double* bval = reinterpret_cast<double*>(ring_all);
+        for (int q = threadIdx.x; q < 2 * T; q += blockDim.x)
+            bval[q] = log1p((double)a.obs[T + q]) * 1.44269504088896340736;
+        __syncthreads();
+        for (int col = threadIdx.x; col < 2 * LB_Q; col += blockDim.x)
+            build_future_bound(bval, T, a.lb_sh, ntb, (double)a.exit_f32, col, tab);
     }
     __syncthreads();
 
@@ -232,13 +295,16 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
             normals_f32(w, nc, z);
             day_step_f32<NOISE>(l.s, l.r, invP, z);
             const int32_t X[3] = {l.s.A, l.s.R, l.s.D};
+            float lx[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float d;
-                if (DIST == 0)
-                    d = log2p1_count_f32(X[c]) - lds_f[c * T + t - 1];
-                else
+                if (DIST == 0) {
+                    lx[c] = log2p1_count_f32(X[c]);
+                    d = lx[c] - lds_f[c * T + t - 1];
+                } else {
                     d = (float)(X[c] - __float_as_int(lds_f[c * T + t - 1]));
+                }
                 if (KAHAN) {
                     const float y = fmaf(d, d, -l.comp);
                     const float tt = l.acc + y;
@@ -248,7 +314,15 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
                     l.acc = fmaf(d, d, l.acc);
                 }
             }
-            const bool exited = l.acc > a.exit_f32;
+            float lb = 0.0f;
+            if (DIST == 0 && ntb > 0) {
+                // grid index rounded down, below the float32 error of lx
+                const float* row = tab + ((t >> a.lb_sh) * LB_Q);
+                const int qr = (int)fmaf(lx[1], 2.0f, -0x1p-14f);
+                const int qd = (int)fmaf(lx[2], 2.0f, -0x1p-14f);
+                lb = row[qr] + row[ntb * LB_Q + qd];
+            }
+            const bool exited = l.acc + lb > a.exit_f32;
             if (exited || t == T) {
                 const float dd = exited ? INFINITY : finish_distance_f32(l.acc, dscale);
                 a.dist[l.k] = dd;
@@ -554,9 +628,14 @@ static unsigned refill_grid(int64_t n, int block, int blocks_per_cu)
     return (unsigned)(g > 0 ? g : 1);
 }
 
-static size_t refill_lds_bytes(int T, int block)
+// observed series | future-days bound table | ring (which first holds the
+// float64 b_s staged for the table, hence at least 2 T doubles with a table)
+static size_t refill_lds_bytes(int T, int block, int lb_ntb)
 {
-    return sizeof(float) * (size_t)((3 * T + 3) & ~3) + sizeof(Slot) * 64 * (size_t)(block / 64);
+    const size_t ring = sizeof(Slot) * 64 * (size_t)(block / 64);
+    const size_t stage = lb_ntb > 0 ? sizeof(double) * 2 * (size_t)T : 0;
+    return sizeof(float) * (size_t)((3 * T + 3) & ~3) + sizeof(float) * 2 * LB_Q * (size_t)lb_ntb +
+           (ring > stage ? ring : stage);
 }
 
 static size_t max_lds_per_block()
@@ -576,7 +655,7 @@ template <int NOISE, int DIST, bool KAHAN, int SPL>
 static void launch_f32_spl(const SimArgs& a, bool prior, hipStream_t s)
 {
     const int block = g_launch.block;
-    const size_t lds = refill_lds_bytes(a.T, block);
+    const size_t lds = refill_lds_bytes(a.T, block, a.lb_ntb);
     const dim3 g(refill_grid(a.n, block, g_launch.blocks_per_cu)), b(block);
     if (prior)
         hipLaunchKernelGGL((k_simulate_f32<NOISE, DIST, KAHAN, true, SPL>), g, b, lds, s, a);
@@ -687,7 +766,16 @@ extern "C" abc_status abc_simulate_distance(const abc_series* ser, const abc_mod
         else launch_f64<1, 1>(a, use_prior, lds, s);
         return check_launch("k_simulate_f64");
     }
-    const size_t lds = refill_lds_bytes(a.T, g_launch.block);
+    // future-days bound for the log1p distance when there is an exit bound;
+    // time blocks of 2^sh days keep the table within LB_MAX_BLOCKS rows
+    if (distm == 0 && !isinf(eps_exit) && !(model->flags & ABC_NO_BOUND)) {
+        int sh = 0;
+        while ((a.T >> sh) + 1 > LB_MAX_BLOCKS) ++sh;
+        a.lb_sh = sh;
+        a.lb_ntb = (a.T >> sh) + 1;
+        if (refill_lds_bytes(a.T, g_launch.block, a.lb_ntb) > max_lds_per_block()) a.lb_ntb = 0;
+    }
+    const size_t lds = refill_lds_bytes(a.T, g_launch.block, a.lb_ntb);
     if (lds > max_lds_per_block())
         return set_error(ABC_EUNSUPPORTED, "T = %d with workgroup size %d needs %zu B of LDS (> %zu)",
                          a.T, g_launch.block, lds, max_lds_per_block());

@@ -127,3 +127,43 @@ def test_fp32_modes_track_oracle(A, flags, kw):
     rel = np.abs(d.cpu().numpy() - ref) / np.maximum(ref, 1e-30)
     assert np.median(rel) < 1e-4, np.median(rel)
     assert np.quantile(rel, 0.99) < 1e-2, np.quantile(rel, 0.99)
+
+
+def _days(A, ser, n, **kw):
+    days = torch.zeros(1, dtype=torch.int64, device="cuda")
+    d = A.simulate_distance(ser, n, 3, days=days, **kw).cpu().numpy()
+    return d, int(days.item())
+
+
+@pytest.mark.parametrize("which", ["country-T72", "country-T100", "T1024"])
+def test_future_bound_only_masks_rejections(A, which):
+    """The lower bound on the days still to come (R and D never fall) may
+    exit a sample earlier than the running sum alone, never later, and only
+    where the float32 distance run to day T ends above the exit bound."""
+    if which == "T1024":
+        P, T, th, seed = 1_000_000_000, 1024, W.THETA_NZ, 7
+    else:
+        s = W.three_countries()[1 if which == "country-T72" else 2]
+        P, T, th, seed = s.P, s.T, s.theta_true, s.obs_seed
+    obs = oracle.observe(oracle.make_model(P, T), th, seed)
+    ser = A.DeviceSeries(P, T, torch.from_numpy(obs))
+    n = 100_003 if T <= 100 else 20_011
+    A.set_launch_config(0, 0, 0)
+    full = _run(A, ser, n=n)
+    for q in (1e-3, 0.05):
+        eps = float(np.quantile(full, q))
+        d_b, days_b = _days(A, ser, n, eps_exit=eps)
+        d_n, days_n = _days(A, ser, n, eps_exit=eps, flags=A.ABC_NO_BOUND)
+        inf_b, inf_n = np.isinf(d_b), np.isinf(d_n)
+        np.testing.assert_array_equal(d_b[~inf_b], full[~inf_b])
+        assert np.all(inf_b[inf_n])                  # never exits later
+        assert np.all(full[inf_b] > eps)             # +INF keeps its meaning
+        np.testing.assert_array_equal(np.nonzero(d_b <= eps)[0], np.nonzero(full <= eps)[0])
+        assert days_b <= days_n
+        print("%s q=%g: sample-days %d -> %d (%.1f%% fewer)"
+              % (which, q, days_n, days_b, 100.0 * (1 - days_b / days_n)))
+        # the bound is part of the launch-independent result
+        for shape in [(1, 64, 1), (4, 256, 3)]:
+            A.set_launch_config(*shape)
+            np.testing.assert_array_equal(_run(A, ser, n=n, eps_exit=eps), d_b, err_msg=str(shape))
+        A.set_launch_config(0, 0, 0)

@@ -64,6 +64,28 @@ def test_invariants(P):
     assert np.all(tr[:, 0, 2] == 100)
 
 
+def test_future_days_lower_bound_holds():
+    """R and D never fall, so after day t each later day s contributes at
+    least max(0, log1p X_t - log1p O_s)^2 per cumulative count: the lower
+    bound the float32 kernel adds to its running sum before the early-exit
+    test. Checked on oracle trajectories against a series of another theta."""
+    P, T = 3.3e8, 100
+    m = oracle.make_model(P, T)
+    obs = oracle.observe(m, NZ, 4)
+    th = oracle.prior(400, seed=12)
+    tr = oracle.record(m, th, seed=13)
+    X = np.log1p(tr[:, 1:, 3:5].astype(np.float64))          # R, D on days 1..T
+    O = np.log1p(obs[1:3].T.astype(np.float64))               # [T, 2]
+    term = ((X - O[None]) ** 2).sum(-1)                       # [n, T]
+    rest = np.cumsum(term[:, ::-1], 1)[:, ::-1]               # sum over s >= t
+    hit = 0
+    for t in range(T - 1):
+        lb = (np.maximum(0.0, X[:, t:t + 1, :] - O[None, t + 1:, :]) ** 2).sum((1, 2))
+        assert np.all(lb <= rest[:, t + 1] * (1 + 1e-12) + 1e-12)
+        hit += int(np.count_nonzero(lb > 0))
+    assert hit > 0
+
+
 def _with(th, **kw):
     names = ["alpha0", "alpha", "n", "beta", "gamma", "delta", "eta", "kappa"]
     t = np.array(th, np.float32).copy()
