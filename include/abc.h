@@ -179,6 +179,10 @@ ABC_API abc_status abc_simulate_record(const abc_series* ser, const abc_model* m
  * set) nothing is changed. rechecked (device int32, nullable) receives the
  * number of rows simulated in float64. ser, model, st as for
  * abc_simulate_distance (the ABC_FP64 and ABC_KAHAN flags are ignored).
+ * eps = +INF keeps every row (nothing lies inside an infinite band); at
+ * eps = 0 the band has no width, so an exact-match decision needs rows from
+ * an ABC_FP64 pass. Errors: ABC_EINVAL (eps < 0 or NaN, band_w outside [0, 1),
+ * NULL pointers, T too long for the float64 row kernel's LDS).
  */
 ABC_API abc_status abc_recheck_band(const abc_series* ser, const abc_model* model,
                                     const abc_stream* st, float eps, float band_w,

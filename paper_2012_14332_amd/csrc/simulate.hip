@@ -858,7 +858,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     if ((rc = check_series(ser, true))) return rc;
     if ((rc = check_model(model))) return rc;
     if ((rc = check_stream_sel(st))) return rc;
-    ABC_REQUIRE(isfinite(eps) && eps >= 0.0f, "eps must be finite and >= 0");
+    ABC_REQUIRE(!isnan(eps) && eps >= 0.0f, "eps must be >= 0 (or +INF)");
     ABC_REQUIRE(isfinite(band_w) && band_w >= 0.0f && band_w < 1.0f, "band_w must be in [0, 1)");
     ABC_REQUIRE(capacity >= 0, "capacity < 0");
     ABC_REQUIRE(count != nullptr, "count is NULL");
