@@ -28,6 +28,13 @@ METRIC = "accepted ABC samples/s at fixed ε (sim-days/s, VALU %); plain vs lear
 # its gfx950 assembly (16 v_mad_u64_u32, 22 transcendental, 119 other; 8 of
 # them look up the lower bound on the days still to come).
 VALU_PER_SAMPLE_DAY = 157
+# The same day step in the batched round kernel, which has no bound lookup.
+BATCH_VALU_PER_SAMPLE_DAY = 149
+# VALU instructions of the once-per-sample steps in both kernels: the prior
+# draw (two Philox calls, uniforms, theta), the initial state and the
+# per-sample part of the day counters, counted in the block that fills a
+# wave's ring (132 instructions, of which 12 register moves are not counted).
+VALU_PER_SAMPLE = 120
 # FP32 operations of one simulated day (FMA = 2, transcendental = 1).
 FP32_FLOP_PER_SAMPLE_DAY = 72
 # Peak VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s.
@@ -134,7 +141,8 @@ def batched_leg(args):
         "rounds_ms": st["rounds_ms"],
         # algorithmic VALU rate of the round kernels over the replays' wall time
         # (host waits between replays included, so a lower bound on the kernel's)
-        "valu_frac_rounds_lower_bound": VALU_PER_SAMPLE_DAY * st["sample_days"] /
+        "valu_frac_rounds_lower_bound": (BATCH_VALU_PER_SAMPLE_DAY * st["sample_days"] +
+                                         VALU_PER_SAMPLE * used) /
                                         (st["rounds_ms"] * 1e-3) / (VALU_PEAK_TOPS * 1e12),
         "refill_min": tune.get("refill"),
         "rechecked_fp64": st["rechecked"],
@@ -485,7 +493,9 @@ def main():
     launches = len(sim_ms)
     avg_ms = float(np.mean(sim_ms))
     days_per_launch = eff_days / launches
-    achieved = VALU_PER_SAMPLE_DAY * days_per_launch / (avg_ms * 1e-3) / 1e12
+    samples_per_launch = N
+    achieved = (VALU_PER_SAMPLE_DAY * days_per_launch + VALU_PER_SAMPLE * samples_per_launch) / \
+        (avg_ms * 1e-3) / 1e12
     flops = FP32_FLOP_PER_SAMPLE_DAY * days_per_launch / (avg_ms * 1e-3) / 1e12
     traffic = traffic_per_launch()
     per_country = {}
@@ -535,6 +545,8 @@ def main():
             "traffic": traffic,
             "ops_per_sample_day": VALU_PER_SAMPLE_DAY,
             "sample_days_per_launch": days_per_launch,
+            "ops_per_sample": VALU_PER_SAMPLE,
+            "samples_per_launch": samples_per_launch,
         },
         "per_country": per_country,
     }

@@ -121,7 +121,10 @@ __device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, uint32_t 
 // points a = q/2 (looked up with q rounded down) and, for each block of 2^sh
 // days, at the block's last day: every lookup is a lower bound of the exact
 // value. Entries are reduced by the float32 rounding the day loop can commit
-// (a per-term error below 2^-17 in log2 units and the running-sum rounding),
+// (a per-term error taken as 2^-15 in log2 units, 16 ulp of the largest log2
+// count, where the hardware log2, the count's float conversion, the rounded
+// observation and the subtraction together stay within a few ulp; and the
+// running-sum rounding),
 // so an exit taken on the bound is one the plain running sum would also have
 // reached by day T: distances that are reported never change, and +INF still
 // means the float32 distance ends above the exit bound.
@@ -139,7 +142,7 @@ __device__ void build_future_bound(const double* bval, int T, int sh, int ntb, d
     const double g = 0.5 * q;
     const double* b = bval + c * T;
     float* col = tab + c * ntb * LB_Q + q;
-    const double e = 0x1p-17;                         // float32 error of one log2 term
+    const double e = 0x1p-15;                         // float32 error of one log2 term
     const double sum_err = 2.0 * T * 0x1p-24 * exit2; // running-sum rounding below the bound
     double F = 0.0;                                   // sum over days after t
     for (int t = T; t >= 0; --t) {
@@ -318,8 +321,8 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
             if (DIST == 0 && ntb > 0) {
                 // grid index rounded down, below the float32 error of lx
                 const float* row = tab + ((t >> a.lb_sh) * LB_Q);
-                const int qr = (int)fmaf(lx[1], 2.0f, -0x1p-14f);
-                const int qd = (int)fmaf(lx[2], 2.0f, -0x1p-14f);
+                const int qr = (int)fmaf(lx[1], 2.0f, -0x1p-12f);
+                const int qd = (int)fmaf(lx[2], 2.0f, -0x1p-12f);
                 lb = row[qr] + row[ntb * LB_Q + qd];
             }
             const bool exited = l.acc + lb > a.exit_f32;

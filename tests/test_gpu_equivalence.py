@@ -162,6 +162,13 @@ def test_future_bound_only_masks_rejections(A, which):
         assert days_b <= days_n
         print("%s q=%g: sample-days %d -> %d (%.1f%% fewer)"
               % (which, q, days_n, days_b, 100.0 * (1 - days_b / days_n)))
+        # compensated sums take the same bound
+        if which == "country-T72":
+            fullk = _run(A, ser, n=n, flags=A.ABC_KAHAN)
+            d_k = _run(A, ser, n=n, eps_exit=eps, flags=A.ABC_KAHAN)
+            inf_k = np.isinf(d_k)
+            np.testing.assert_array_equal(d_k[~inf_k], fullk[~inf_k])
+            assert np.all(fullk[inf_k] > eps)
         # the bound is part of the launch-independent result
         for shape in [(1, 64, 1), (4, 256, 3)]:
             A.set_launch_config(*shape)
