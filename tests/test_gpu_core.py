@@ -117,6 +117,30 @@ def test_record_fp32_invariants_and_early_days(A):
     assert same1.mean() > 0.995, same1.mean()
 
 
+@pytest.mark.parametrize("P,T", [(1_000_000_000, 100), (60_000_000, 49)])
+def test_float32_distance_terms_within_the_bound_margin(A, P, T):
+    """The float32 kernel's distance arithmetic on its own integer trajectory:
+    against the exact log2 terms of the recorded float32 trajectory, the
+    squared sum stays within what a per-term error of 2^-17 allows (the
+    future-days bound budgets 2^-15 per term), at counts up to ~1e9."""
+    n, seed = 20_000, 12
+    obs = oracle.observe(oracle.make_model(P, T), W.THETA_USA, 24)
+    ser = _series(A, P, T, obs)
+    th = A.sample_prior(n, seed=seed)
+    traj = A.simulate_record(ser, th, seed=seed).cpu().numpy().astype(np.float64)
+    d32 = A.simulate_distance(ser, n, seed, theta=th).cpu().numpy().astype(np.float64)
+    L2 = math.log(2.0)
+    u = (np.log1p(traj[:, 1:, 2:5]) - np.log1p(obs.T.astype(np.float64))[None]) / L2
+    acc64 = (u ** 2).sum((1, 2))
+    acc32 = (d32 / L2) ** 2
+    e = 2.0 ** -17
+    allow = 2 * e * np.abs(u).sum((1, 2)) + 3 * T * e * e + (3 * T + 8) * 2.0 ** -24 * acc64
+    worst = np.max(np.abs(acc32 - acc64) / allow)
+    print("P=%g T=%d: worst |acc32 - acc64| / allowance = %.3f, max count %d"
+          % (P, T, worst, int(traj[:, :, 2:5].max())))
+    assert worst <= 1.0
+
+
 def _obs_for(s):
     return oracle.observe(oracle.make_model(s.P, s.T), s.theta_true, s.obs_seed)
 
