@@ -136,9 +136,13 @@ def test_float32_distance_terms_within_the_bound_margin(A, P, T):
     e = 2.0 ** -17
     allow = 2 * e * np.abs(u).sum((1, 2)) + 3 * T * e * e + (3 * T + 8) * 2.0 ** -24 * acc64
     worst = np.max(np.abs(acc32 - acc64) / allow)
-    print("P=%g T=%d: worst |acc32 - acc64| / allowance = %.3f, max count %d"
-          % (P, T, worst, int(traj[:, :, 2:5].max())))
+    # the float32 distance against the exact distance of the same trajectory
+    rel = np.abs(d32 - np.sqrt(acc64) * L2) / (np.sqrt(acc64) * L2)
+    print("P=%g T=%d: worst |acc32 - acc64| / allowance = %.3f, max count %d, "
+          "distance rel. err. median %.1e max %.1e"
+          % (P, T, worst, int(traj[:, :, 2:5].max()), np.median(rel), rel.max()))
     assert worst <= 1.0
+    assert rel.max() <= 1e-5
 
 
 def _obs_for(s):
