@@ -366,6 +366,65 @@ def paper_style_leg(args):
     }
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def hbm_leg(args):
+    """Bandwidth of the two HBM-bound passes, each on inputs larger than the
+    256 MB last-level cache, timed with HIP events on the launch stream:
+    accept-compaction of 4e8 float32 distances at an acceptance of 1e-4
+    (theta of the accepted rows re-drawn from their counters), and the float64
+    posterior moments of 1e8 theta rows, unweighted and weighted. The sizes
+    keep each call several hundred microseconds long, well above the host's
+    per-call launch cost, so back-to-back calls keep the GPU busy.
+    Algorithmic bytes: 4 B per distance read plus 44 B per accepted row
+    written (index, theta, distance); 32 B per theta row (+ 4 B weight)."""
+    import torch
+
+    from paper_2012_14332_amd import abc
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    n_c, q = 400_000_000, 1e-4
+    dist = torch.rand(n_c, generator=g, device="cuda", dtype=torch.float32)
+    eps = q                      # uniform distances: a fraction q falls at or below q
+    cap = 1 << 16
+    n_m = 100_000_000
+    theta = torch.rand((n_m, 8), generator=g, device="cuda", dtype=torch.float32)
+    w = torch.rand(n_m, generator=g, device="cuda", dtype=torch.float32)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    ms_c, res = timed(lambda: abc.accept_compact(dist, eps, cap, seed=3))
+    acc = int(res[4].item())
+    bytes_c = 4.0 * n_c + 44.0 * min(acc, cap)
+    ms_m, _ = timed(lambda: abc.posterior_moments(theta))
+    ms_w, _ = timed(lambda: abc.posterior_moments(theta, weight=w))
+    bytes_m, bytes_w = 32.0 * n_m, 36.0 * n_m
+
+    def rec(ms, b, **kw):
+        gbs = b / (ms * 1e-3) / 1e9
+        return dict(kw, ms=ms, algorithmic_bytes=b, GB_per_s=gbs, frac_of_hbm_peak=gbs / HBM_PEAK_GBS)
+
+    return {
+        "compact": rec(ms_c, bytes_c, n=n_c, accepted=acc),
+        "moments": rec(ms_m, bytes_m, rows=n_m),
+        "moments_weighted": rec(ms_w, bytes_w, rows=n_m),
+        "peak_GB_per_s": HBM_PEAK_GBS,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +450,7 @@ def main():
     ap.add_argument("--compare-seeds-learned", type=int, nargs="+", default=[2, 3, 4, 5])
     ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")
     ap.add_argument("--no-smc", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the compaction/moments bandwidth leg")
     ap.add_argument("--smc-particles", type=int, default=4096)
     ap.add_argument("--smc-generations", type=int, default=16)
     ap.add_argument("--smc-alpha", type=float, default=0.5)
@@ -559,6 +619,8 @@ def main():
     if not args.no_smc:
         out["smc"] = smc_leg(args)
     out["paper_style"] = paper_style_leg(args)
+    if not args.no_hbm:
+        out["hbm_passes"] = hbm_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
     print(json.dumps(out))

@@ -214,15 +214,18 @@ ABC_API abc_status abc_accept_compact(const float* dist, const float* theta, con
 /*
  * Posterior mean and covariance of accepted theta in float64 (the summaries
  * the paper reports as posterior averages, Table "t:trajectories").
- *   theta   device float32 [n_max][8]; the first n rows are used, where n =
- *           min(*n_dev, n_max) is read on the device (n_dev: device int64,
- *           e.g. the out_count of abc_accept_compact). n_dev may be NULL: n = n_max.
+ *   theta   device float32 [n_max][8], 16-byte aligned; the first n rows are
+ *           used, where n = min(*n_dev, n_max) is read on the device (n_dev:
+ *           device int64, e.g. the out_count of abc_accept_compact). n_dev may
+ *           be NULL: n = n_max.
  *   weight  device float32 [n_max] or NULL (all ones).
  *   mean    device float64 [8]: sum w theta / V1.
  *   cov     device float64 [8][8]: sum w (theta-mean)(theta-mean)^T / (V1 - V2/V1),
  *           V1 = sum w, V2 = sum w^2 (the unbiased n-1 form when w = 1).
  * n = 0 gives NaN mean and covariance; n = 1 a NaN covariance. The summation
- * order depends only on n_max, never on timing.
+ * order depends only on n (fixed contiguous row ranges), never on timing or
+ * on the device. Errors: ABC_EINVAL (n_max < 0, NULL or misaligned theta,
+ * NULL mean/cov).
  */
 ABC_API abc_status abc_posterior_moments(const float* theta, const float* weight, const int64_t* n_dev,
                                  int64_t n_max, double* mean, double* cov, void* stream);

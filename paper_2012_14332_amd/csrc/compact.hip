@@ -2,14 +2,19 @@
 // Sec. 3.2), and its C-ABI entry point abc_accept_compact.
 //
 // Single pass over the distances with a decoupled look-back scan: every
-// workgroup takes the next tile of 4096 samples from an atomic ticket (so a
+// workgroup takes the next tile of 65536 samples from an atomic ticket (so a
 // tile only ever waits on tiles that are already running), counts its
-// accepted samples with wavefront ballots, publishes that aggregate, then
-// one wavefront looks back over up to 64 predecessor tiles at a time to
-// obtain the exclusive prefix. Output order is sample-index order, so the
-// result does not depend on scheduling. HBM traffic: 4 B per sample read,
-// plus 32-48 B per accepted row (theta re-drawn from its counter when it was
-// never materialised).
+// accepted samples, publishes that aggregate, then one wavefront looks back
+// over up to 64 predecessor tiles at a time to obtain the exclusive prefix.
+// Each wavefront owns 4096 consecutive samples of the tile and reads them as
+// 16 coalesced float4 loads per lane (1 KB per load instruction), keeping a
+// 4-bit accept mask per load; ranks inside a load are only formed for the
+// rare loads that hold an accepted sample. Output order is sample-index
+// order, so the result does not depend on scheduling. HBM traffic: 4 B per
+// sample read, plus 32-48 B per accepted row (theta re-drawn from its counter
+// when it was never materialised). Large tiles keep the ticket counter and
+// the look-back -- device-scope atomics on few addresses -- off the critical
+// path.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -18,9 +23,10 @@
 
 namespace abc {
 
-constexpr int CT_BLOCK = 256;
-constexpr int CT_ITEMS = 16;  // consecutive samples per thread
-constexpr int CT_TILE = CT_BLOCK * CT_ITEMS;
+constexpr int CT_BLOCK = 1024;                   // 16 wavefronts
+constexpr int CT_STEPS = 16;                     // float4 loads per lane
+constexpr int CT_WAVE_SPAN = 64 * 4 * CT_STEPS;  // 4096 samples per wavefront
+constexpr int CT_TILE = (CT_BLOCK / 64) * CT_WAVE_SPAN;
 
 constexpr uint64_t ST_AGG = 1;     // status word: (value << 2) | flag
 constexpr uint64_t ST_PREFIX = 2;
@@ -76,6 +82,25 @@ __device__ __forceinline__ int wave_incl_scan_i32(int v, int lane)
     return v;
 }
 
+// One accepted sample k of the tile goes to output row r.
+__device__ __forceinline__ void emit_row(const CompactArgs& a, int64_t k, int64_t r)
+{
+    if (r >= a.capacity) return;
+    const uint64_t i = a.first + (uint64_t)k;
+    a.out_idx[r] = (int64_t)i;
+    float th[8];
+    if (a.theta) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) th[j] = a.theta[8 * k + j];
+    } else {
+        prior_draw(a.key, i, a.series, a.domain, a.lo, a.width, th);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a.out_theta[8 * r + j] = th[j];
+    if (a.out_dist) a.out_dist[r] = a.dist[k];
+    if (a.out_w) a.out_w[r] = a.weight[k];
+}
+
 __global__ __launch_bounds__(CT_BLOCK) void k_compact(CompactArgs a)
 {
     __shared__ unsigned int tile_sh;
@@ -88,29 +113,31 @@ __global__ __launch_bounds__(CT_BLOCK) void k_compact(CompactArgs a)
     if (tid == 0) tile_sh = atomicAdd(a.ticket, 1u);
     __syncthreads();
     const int64_t tile = tile_sh;
-    const int64_t base = tile * CT_TILE + (int64_t)tid * CT_ITEMS;
+    const int64_t wbase = tile * CT_TILE + (int64_t)wave * CT_WAVE_SPAN;
 
-    // flags of this thread's 16 consecutive samples
-    uint32_t mask = 0;
-    if (base + CT_ITEMS <= a.n) {
-        const float4* p = reinterpret_cast<const float4*>(a.dist + base);
+    // accept masks: bit 4 q + c for sample wbase + 256 q + 4 lane + c
+    uint64_t bits = 0;
+    if (wbase + CT_WAVE_SPAN <= a.n) {
+        const float4* p = reinterpret_cast<const float4*>(a.dist + wbase) + lane;
+        float4 v[CT_STEPS];
 #pragma unroll
-        for (int q = 0; q < CT_ITEMS / 4; ++q) {
-            const float4 v = p[q];
-            mask |= (uint32_t)(v.x <= a.eps) << (4 * q + 0);
-            mask |= (uint32_t)(v.y <= a.eps) << (4 * q + 1);
-            mask |= (uint32_t)(v.z <= a.eps) << (4 * q + 2);
-            mask |= (uint32_t)(v.w <= a.eps) << (4 * q + 3);
+        for (int q = 0; q < CT_STEPS; ++q) v[q] = p[64 * q];
+#pragma unroll
+        for (int q = 0; q < CT_STEPS; ++q) {
+            const uint64_t m = (uint64_t)(v[q].x <= a.eps) | ((uint64_t)(v[q].y <= a.eps) << 1) |
+                               ((uint64_t)(v[q].z <= a.eps) << 2) | ((uint64_t)(v[q].w <= a.eps) << 3);
+            bits |= m << (4 * q);
         }
     } else {
-        for (int q = 0; q < CT_ITEMS; ++q)
-            if (base + q < a.n && a.dist[base + q] <= a.eps) mask |= 1u << q;
+        for (int q = 0; q < CT_STEPS; ++q)
+            for (int c = 0; c < 4; ++c) {
+                const int64_t k = wbase + 256 * q + 4 * lane + c;
+                if (k < a.n && a.dist[k] <= a.eps) bits |= 1ull << (4 * q + c);
+            }
     }
-    const int cnt = __popc(mask);
-
-    // block-wide exclusive scan of the per-thread counts
-    const int incl = wave_incl_scan_i32(cnt, lane);
-    if (lane == 63) wave_tot[wave] = incl;
+    const int cnt = __popcll(bits);
+    const int wsum = __builtin_amdgcn_readlane(wave_incl_scan_i32(cnt, lane), 63);
+    if (lane == 0) wave_tot[wave] = wsum;
     __syncthreads();
     int wave_off = 0, block_tot = 0;
 #pragma unroll
@@ -118,7 +145,6 @@ __global__ __launch_bounds__(CT_BLOCK) void k_compact(CompactArgs a)
         if (q < wave) wave_off += wave_tot[q];
         block_tot += wave_tot[q];
     }
-    const int thread_excl = wave_off + incl - cnt;
 
     // publish the aggregate, then look back for the exclusive prefix
     if (wave == 0) {
@@ -160,29 +186,21 @@ __global__ __launch_bounds__(CT_BLOCK) void k_compact(CompactArgs a)
         }
     }
     __syncthreads();
-    if (mask == 0u) return;
+    if (wsum == 0) return;
 
-    int64_t r = excl_sh + thread_excl;
-    while (mask) {
-        const int q = __ffs(mask) - 1;
-        mask &= mask - 1u;
-        if (r < a.capacity) {
-            const int64_t k = base + q;
-            const uint64_t i = a.first + (uint64_t)k;
-            a.out_idx[r] = (int64_t)i;
-            float th[8];
-            if (a.theta) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) th[j] = a.theta[8 * k + j];
-            } else {
-                prior_draw(a.key, i, a.series, a.domain, a.lo, a.width, th);
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a.out_theta[8 * r + j] = th[j];
-            if (a.out_dist) a.out_dist[r] = a.dist[k];
-            if (a.out_w) a.out_w[r] = a.weight[k];
+    // rows in sample order: load by load, lanes in order, components in order
+    int64_t r0 = excl_sh + wave_off;
+    for (int q = 0; q < CT_STEPS; ++q) {
+        const uint32_t m = (uint32_t)(bits >> (4 * q)) & 15u;
+        if (__ballot(m != 0u) == 0ull) continue;
+        const int c = __popc(m);
+        const int incl = wave_incl_scan_i32(c, lane);
+        int64_t r = r0 + (incl - c);
+        for (uint32_t mm = m; mm != 0u; mm &= mm - 1u) {
+            emit_row(a, wbase + 256 * q + 4 * lane + (__ffs(mm) - 1), r);
+            ++r;
         }
-        ++r;
+        r0 += __builtin_amdgcn_readlane(incl, 63);
     }
 }
 

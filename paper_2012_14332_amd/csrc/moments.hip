@@ -2,12 +2,16 @@
 // parameter averages of Table "t:trajectories", extended to the covariance
 // and to importance weights), and its C-ABI entry point abc_posterior_moments.
 //
-// Deterministic: the rows are cut into fixed chunks of 2048; each chunk's
-// sums (V1, V2, S1 = sum w (theta - c), S2 = sum w (theta - c)(theta - c)^T,
-// 46 doubles) are reduced in a fixed shuffle/LDS tree, and one final
-// workgroup adds the chunk sums in chunk order. The shift c is the first row,
-// which keeps the centred sums free of cancellation. Then
+// Deterministic: the n rows are cut into G = min(768, ceil(n / 2048))
+// contiguous ranges, a function of n alone. Workgroup b sums its range (each
+// thread every 256th row, in row order; theta read as two float4 per row)
+// into V1, V2, S1 = sum w (theta - c), S2 = sum w (theta - c)(theta - c)^T
+// (46 doubles), reduces them in a fixed shuffle/LDS tree and writes one
+// partial; one final workgroup adds the G partials in eight ordered slices
+// and then the slices in order. The shift
+// c is the first row, which keeps the centred sums free of cancellation. Then
 //   mean = c + S1 / V1,  cov = (S2 - S1 S1^T / V1) / (V1 - V2 / V1).
+// Two launches whatever n is, and the partial pass streams theta once.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -17,16 +21,23 @@
 namespace abc {
 
 constexpr int MOM_BLOCK = 256;
-constexpr int MOM_CHUNK = 2048;
+constexpr int MOM_GROUPS = 768;     // most row ranges (workgroups of the partial pass)
+constexpr int MOM_MIN_ROWS = 2048;  // fewest rows per range
 constexpr int MOM_NSUM = 2 + 8 + 36;
+
+// number of row ranges for n rows (depends on n only)
+__host__ __device__ inline int64_t mom_groups(int64_t n)
+{
+    const int64_t g = (n + MOM_MIN_ROWS - 1) / MOM_MIN_ROWS;
+    return g < MOM_GROUPS ? g : MOM_GROUPS;
+}
 
 struct MomArgs {
     const float* theta;
     const float* weight;
     const int64_t* n_dev;
     int64_t n_max;
-    int64_t nchunks;
-    double* partial;  // [nchunks][MOM_NSUM]
+    double* partial;  // [mom_groups(n_max)][MOM_NSUM]
     double* mean;
     double* cov;
 };
@@ -50,58 +61,85 @@ __global__ __launch_bounds__(MOM_BLOCK) void k_moments_partial(MomArgs a)
 {
     __shared__ double red[MOM_BLOCK / 64][MOM_NSUM];
     const int64_t n = rows_used(a);
-    const int64_t used_chunks = (n + MOM_CHUNK - 1) / MOM_CHUNK;
+    const int64_t G = mom_groups(n);
+    if ((int64_t)blockIdx.x >= G) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t R = (n + G - 1) / G;
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int64_t r1 = r0 + R < n ? r0 + R : n;
+    const float4* th4 = reinterpret_cast<const float4*>(a.theta);
     double c[8];
-    if (n > 0) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) c[j] = (double)a.theta[j];
+    {
+        const float4 u = th4[0], v = th4[1];
+        c[0] = u.x; c[1] = u.y; c[2] = u.z; c[3] = u.w;
+        c[4] = v.x; c[5] = v.y; c[6] = v.z; c[7] = v.w;
     }
-    for (int64_t ch = blockIdx.x; ch < used_chunks; ch += gridDim.x) {
-        double s[MOM_NSUM];
+    double s[MOM_NSUM];
 #pragma unroll
-        for (int q = 0; q < MOM_NSUM; ++q) s[q] = 0.0;
-        for (int r = threadIdx.x; r < MOM_CHUNK; r += MOM_BLOCK) {
-            const int64_t row = ch * MOM_CHUNK + r;
-            if (row >= n) break;
-            const double w = a.weight ? (double)a.weight[row] : 1.0;
-            double x[8];
+    for (int q = 0; q < MOM_NSUM; ++q) s[q] = 0.0;
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += MOM_BLOCK) {
+        const double w = a.weight ? (double)a.weight[row] : 1.0;
+        const float4 u = th4[2 * row], v = th4[2 * row + 1];
+        const double x[8] = {(double)u.x - c[0], (double)u.y - c[1], (double)u.z - c[2],
+                             (double)u.w - c[3], (double)v.x - c[4], (double)v.y - c[5],
+                             (double)v.z - c[6], (double)v.w - c[7]};
+        s[0] += w;
+        s[1] += w * w;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) x[j] = (double)a.theta[8 * row + j] - c[j];
-            s[0] += w;
-            s[1] += w * w;
+        for (int j = 0; j < 8; ++j) s[2 + j] += w * x[j];
+        int q = 10;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s[2 + j] += w * x[j];
-            int q = 10;
+        for (int j = 0; j < 8; ++j)
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
+            for (int l = j; l < 8; ++l) s[q++] += w * x[j] * x[l];
+    }
 #pragma unroll
-                for (int l = j; l < 8; ++l) s[q++] += w * x[j] * x[l];
-        }
+    for (int q = 0; q < MOM_NSUM; ++q) {
+        const double v = wave_sum_f64(s[q]);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < MOM_NSUM) {
+        double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < MOM_NSUM; ++q) {
-            const double v = wave_sum_f64(s[q]);
-            if (lane == 0) red[wave][q] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < MOM_NSUM) {
-            double v = 0.0;
-#pragma unroll
-            for (int w = 0; w < MOM_BLOCK / 64; ++w) v += red[w][threadIdx.x];
-            a.partial[ch * MOM_NSUM + threadIdx.x] = v;
-        }
-        __syncthreads();
+        for (int w = 0; w < MOM_BLOCK / 64; ++w) v += red[w][threadIdx.x];
+        a.partial[(int64_t)blockIdx.x * MOM_NSUM + threadIdx.x] = v;
     }
 }
 
-__global__ __launch_bounds__(64) void k_moments_final(MomArgs a)
+constexpr int MOM_FINAL_SPLIT = 8;  // the final pass sums the partials in 8 ordered slices
+
+__global__ __launch_bounds__(64 * MOM_FINAL_SPLIT) void k_moments_final(MomArgs a)
 {
+    __shared__ double part[MOM_FINAL_SPLIT][MOM_NSUM];
     __shared__ double tot[MOM_NSUM];
     const int64_t n = rows_used(a);
-    const int64_t used_chunks = (n + MOM_CHUNK - 1) / MOM_CHUNK;
+    const int64_t G = mom_groups(n);
+    const int j = threadIdx.x & 63;   // which of the 46 sums
+    const int g = threadIdx.x >> 6;   // which slice of the partials
+    if (j < MOM_NSUM) {
+        // slice g = partials [g L, (g + 1) L) in range order, loads batched
+        // ahead of the ordered adds
+        const int64_t L = (G + MOM_FINAL_SPLIT - 1) / MOM_FINAL_SPLIT;
+        const int64_t b0 = g * L, b1 = b0 + L < G ? b0 + L : G;
+        const double* p = a.partial + j;
+        double v = 0.0;
+        int64_t b = b0;
+        for (; b + 16 <= b1; b += 16) {
+            double t[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) t[k] = p[(b + k) * MOM_NSUM];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v += t[k];
+        }
+        for (; b < b1; ++b) v += p[b * MOM_NSUM];
+        part[g][j] = v;
+    }
+    __syncthreads();
     if (threadIdx.x < MOM_NSUM) {
         double v = 0.0;
-        for (int64_t ch = 0; ch < used_chunks; ++ch) v += a.partial[ch * MOM_NSUM + threadIdx.x];
+#pragma unroll
+        for (int q = 0; q < MOM_FINAL_SPLIT; ++q) v += part[q][threadIdx.x];
         tot[threadIdx.x] = v;
     }
     __syncthreads();
@@ -135,27 +173,27 @@ extern "C" abc_status abc_posterior_moments(const float* theta, const float* wei
     ABC_REQUIRE(n_max >= 0, "n_max < 0");
     ABC_REQUIRE(mean != nullptr && cov != nullptr, "mean/cov NULL");
     ABC_REQUIRE(n_max == 0 || theta != nullptr, "theta is NULL");
+    ABC_REQUIRE((reinterpret_cast<uintptr_t>(theta) & 15u) == 0, "theta must be 16-byte aligned");
     const hipStream_t s = as_stream(stream);
     MomArgs a{};
     a.theta = theta;
     a.weight = weight;
     a.n_dev = n_dev;
     a.n_max = n_max;
-    a.nchunks = (n_max + MOM_CHUNK - 1) / MOM_CHUNK;
     a.mean = mean;
     a.cov = cov;
+    const int64_t groups = mom_groups(n_max);  // enough for any device count <= n_max
     void* scratch = nullptr;
-    const size_t bytes = sizeof(double) * MOM_NSUM * (size_t)(a.nchunks > 0 ? a.nchunks : 1);
+    const size_t bytes = sizeof(double) * MOM_NSUM * (size_t)(groups > 0 ? groups : 1);
     ABC_HIP(hipMallocAsync(&scratch, bytes, s));
     a.partial = reinterpret_cast<double*>(scratch);
     abc_status rc = ABC_OK;
-    if (a.nchunks > 0) {
-        const unsigned grid = (unsigned)(a.nchunks < 1024 ? a.nchunks : 1024);
-        hipLaunchKernelGGL(k_moments_partial, dim3(grid), dim3(MOM_BLOCK), 0, s, a);
+    if (groups > 0) {
+        hipLaunchKernelGGL(k_moments_partial, dim3((unsigned)groups), dim3(MOM_BLOCK), 0, s, a);
         rc = check_launch("k_moments_partial");
     }
     if (rc == ABC_OK) {
-        hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64 * MOM_FINAL_SPLIT), 0, s, a);
         rc = check_launch("k_moments_final");
     }
     hipError_t e = hipFreeAsync(scratch, s);

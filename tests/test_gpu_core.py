@@ -202,7 +202,8 @@ def test_distance_fp32_accuracy_statement(A):
     assert all(abs(ref[i] - kth) <= 1e-3 * kth for i in diff), sorted(diff)
 
 
-@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 1_000_003])
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 32767, 32768, 32769, 65536 + 4096 * 3 + 17,
+                               1_000_003])
 def test_compact_matches_brute_force(A, n):
     rng = np.random.default_rng(n)
     dist = rng.exponential(size=n).astype(np.float32)
@@ -239,7 +240,7 @@ def test_compact_overflow_and_prior_redraw(A):
     np.testing.assert_array_equal(th.cpu().numpy(), ref_th)
 
 
-@pytest.mark.parametrize("n", [1, 2, 1000, 2048 * 3 + 5, 1_000_000])
+@pytest.mark.parametrize("n", [1, 2, 1000, 2048 * 3 + 5, 2048 * 1024 + 1, 3_000_017])
 def test_moments_match_oracle(A, n):
     rng = np.random.default_rng(n)
     th = (rng.random((n, 8)) * np.array(W.PRIOR_HI)).astype(np.float32)
