@@ -94,10 +94,13 @@ struct BatchArgs {
 
 // theta of sample i of series s (desc d): the prior draw, or the learned
 // proposal's draw with its importance weight
+// (MIX: the learned proposal is in use; a compile-time switch so that the
+// prior-only round kernel does not carry the proposal's code and registers)
+template <bool MIX = true>
 __device__ __forceinline__ float batch_theta(const BatchArgs& a, int s, const SeriesDesc& d, uint64_t i,
                                              float th[8])
 {
-    if (a.mix) return proposal_draw(a.tables[s], a.prop, a.key, i, d.series_id, a.prop_domain, th);
+    if (MIX && a.mix) return proposal_draw(a.tables[s], a.prop, a.key, i, d.series_id, a.prop_domain, th);
     prior_draw(a.key, i, d.series_id, a.domain, a.lo, a.width, th);
     return 1.0f;
 }
@@ -241,7 +244,7 @@ struct BLane {
     bool active;
 };
 
-template <int SPL>
+template <int SPL, bool MIX>
 __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
 {
     extern __shared__ float lds_b[];
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
             const SeriesDesc& d = desc_sh[s];
             const int64_t i = tab_sh.first[r] + local;
             float th[8];
-            (void)batch_theta(a, s, d, (uint64_t)i, th);
+            (void)batch_theta<MIX>(a, s, d, (uint64_t)i, th);
             const Theta tt = theta_from(th);
             const RatesF rr = rates_f32(tt);
             const State s0 = init_state(tt.ka, d.P, d.A0, d.R0, d.D0);
@@ -607,7 +610,10 @@ struct DevBuf {
 template <int SPL>
 void launch_round(const BatchArgs& a, unsigned grid, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch_round<SPL>), dim3(grid), dim3(block), lds, s, a);
+    if (a.mix)
+        hipLaunchKernelGGL((k_batch_round<SPL, true>), dim3(grid), dim3(block), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_batch_round<SPL, false>), dim3(grid), dim3(block), lds, s, a);
 }
 
 }  // namespace
