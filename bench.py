@@ -165,7 +165,7 @@ def learned_leg(args, batched):
     import numpy as np
     import torch
 
-    from paper_2012_14332_amd import abc
+    from paper_2012_14332_amd import abc, autotune
     from paper_2012_14332_amd import pipeline as PL
     from paper_2012_14332_amd import workloads as W
 
@@ -181,6 +181,11 @@ def learned_leg(args, batched):
     Q = args.quota
     kw = dict(round_size=1 << 22, rounds_per_graph=4, cand_capacity=4 * Q, mix=mix, lam=args.lam,
               inflate=args.inflate)
+    # the proposal's round kernel has its own register budget: tune its shape
+    # too, and give the plain kernels their shape back afterwards
+    prev_shape, prev_refill = abc.get_launch_config(), abc.get_refill_min()
+    tune = autotune.tune_batch(sers, eps, seed=2, quota=Q, round_size=1 << 22, use_cache=False,
+                               mix=mix, lam=args.lam, inflate=args.inflate)
     abc.batch_run(sers, eps, 2, Q, **kw)  # warm-up (graph capture, code paths)
     walls = []
     for rep in range(args.batch_reps):
@@ -232,6 +237,8 @@ def learned_leg(args, batched):
     worst_sd = (np.abs(lsd - psd) / (0.05 * psd)).max(1)
     gains = [(Q / u) / (Q / pu) for u, pu in zip(used, batched["_used"])]
     net.close()
+    abc.set_launch_config(*prev_shape)
+    abc.set_refill_min(prev_refill)
     return {
         "workload": "1e6 training pairs (T ~ U[30,200], P log-uniform [1e5,1e9], theta from the "
                     "prior), 20 epochs Adam lr 1e-3 batch 4096 (BF16 MFMA, FP32 accumulation); "
@@ -243,6 +250,9 @@ def learned_leg(args, batched):
         "data_ms": data_ms,
         "loss_first_last": [float(log[:10].mean()), float(log[-10:].mean())],
         "path": "batched persistent kernel with per-series proposal rows (abc_batch_run_weighted)",
+        "launch_shape": tune["shape"],
+        "refill_min": tune["refill"],
+        "autotune_top": tune["table"][:5],
         "accepted_per_s": acc / wall,
         "ess_per_s": ess / wall,
         "plain_accepted_per_s": batched["accepted_per_s"],
@@ -334,13 +344,16 @@ def paper_style_leg(args):
     real data; context only)."""
     import torch
 
-    from paper_2012_14332_amd import abc
+    from paper_2012_14332_amd import abc, autotune
     from paper_2012_14332_amd import pipeline as PL
     from paper_2012_14332_amd import workloads as W
 
     s = W.single_country()
     ser = PL.observed_series(s)
     n = 10_000_000
+    # full trajectories favour another shape than early exit does: tune it
+    prev_shape, prev_refill = abc.get_launch_config(), abc.get_refill_min()
+    tune = autotune.tune_plain(ser, math.inf, flags=abc.ABC_DIST_RAW, use_cache=False)
     out = torch.empty(n, dtype=torch.float32, device="cuda")
     run = lambda f: abc.simulate_distance(ser, n, 1, first=f, flags=abc.ABC_DIST_RAW, out=out)
     run(0)
@@ -355,12 +368,15 @@ def paper_style_leg(args):
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) * 1e-3 / reps
     traj = n / sec
+    abc.set_launch_config(*prev_shape)
+    abc.set_refill_min(prev_refill)
     paper = {"2x_Mk1_IPU": 4.25e7, "V100": 5.68e6, "2x_Xeon_Gold_6248": 1.38e6}
     return {
         "workload": "%s, raw-count distance, all %d days simulated (no early exit), %d samples per "
                     "launch, %d launches" % (s.name, s.T, n, reps),
         "trajectories_per_s": traj,
         "sim_days_per_s": traj * s.T,
+        "launch_shape": tune["shape"],
         "paper_trajectories_per_s": paper,
         "ratio_to_paper": {k: traj / v for k, v in paper.items()},
     }
@@ -611,10 +627,15 @@ def main():
         "per_country": per_country,
     }
     if not args.no_batched:
+        # the batched legs tune their own shapes; the float32 simulate kernel
+        # of the later legs gets the main step's shape back
+        main_shape, main_refill = abc.get_launch_config(), abc.get_refill_min()
         out["batched"] = batched_leg(args)
         if not args.no_learned:
             out["learned"] = learned_leg(args, out["batched"])
         out["batched"].pop("_eps", None)
+        abc.set_launch_config(*main_shape)
+        abc.set_refill_min(main_refill)
         out["batched"].pop("_used", None)
     if not args.no_smc:
         out["smc"] = smc_leg(args)

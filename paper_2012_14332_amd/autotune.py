@@ -80,16 +80,18 @@ def _time(fn, reps: int) -> float:
 
 
 def tune_plain(ser: abc.DeviceSeries, eps_exit: float, n: int = 4_000_000, seed: int = 1,
-               reps: int = 3, use_cache: bool = True) -> Dict:
-    """Fastest shape of the plain kernel on n samples of `ser` with early exit at eps_exit."""
-    key = "%s|plain|T%d" % (device_key(), t_bucket(ser.T))
+               reps: int = 3, use_cache: bool = True, flags: int = 0) -> Dict:
+    """Fastest shape of the plain kernel on n samples of `ser` with early exit at
+    eps_exit (model flags `flags`)."""
+    key = "%s|plain|T%d|f%d|%s" % (device_key(), t_bucket(ser.T), flags,
+                                   "exit" if math.isfinite(eps_exit) else "full")
     if use_cache:
         rec = _load().get(key)
         if rec and "refill" in rec:
             _apply(rec)
             return rec
     out = torch.empty(n, dtype=torch.float32, device="cuda")
-    run = lambda: abc.simulate_distance(ser, n, seed, eps_exit=eps_exit, out=out)
+    run = lambda: abc.simulate_distance(ser, n, seed, eps_exit=eps_exit, flags=flags, out=out)
     table = []
     for sh in shapes(SPL_PLAIN):
         abc.set_launch_config(*sh)
@@ -115,9 +117,12 @@ def _apply(rec: Dict):
 
 
 def tune_batch(sers, eps, seed: int = 1, quota: int = 1000, round_size: int = 1 << 22,
-               rounds: int = 4, use_cache: bool = True) -> Dict:
-    """Fastest shape of the batched kernel over `rounds` rounds of the real batch."""
-    key = "%s|batch|T%d|m%d" % (device_key(), t_bucket(max(s.T for s in sers)), len(sers))
+               rounds: int = 4, use_cache: bool = True, **run_kw) -> Dict:
+    """Fastest shape of the batched kernel over `rounds` rounds of the real batch.
+    run_kw goes to abc.batch_run (mix, lam, inflate: the learned proposal's
+    round kernel, which is tuned and cached separately)."""
+    key = "%s|batch|T%d|m%d%s" % (device_key(), t_bucket(max(s.T for s in sers)), len(sers),
+                                  "|mix" if run_kw.get("mix") is not None else "")
     if use_cache:
         rec = _load().get(key)
         if rec and "refill" in rec:
@@ -129,7 +134,7 @@ def tune_batch(sers, eps, seed: int = 1, quota: int = 1000, round_size: int = 1 
         for _ in range(2):
             o = abc.batch_run(sers, eps, seed, quota, round_size=round_size,
                               max_samples=rounds * round_size // len(sers), rounds_per_graph=1,
-                              cand_capacity=4096, check=False)
+                              cand_capacity=4096, check=False, **run_kw)
             if o["status"] not in (0, -5):
                 return math.inf
             st = o["stats"]
