@@ -2,7 +2,7 @@
 // Sec. 3.2), and its C-ABI entry point abc_accept_compact.
 //
 // Single pass over the distances with a decoupled look-back scan: every
-// workgroup takes the next tile of 65536 samples from an atomic ticket (so a
+// workgroup takes the next tile of 16384 or 65536 samples from an atomic ticket (so a
 // tile only ever waits on tiles that are already running), counts its
 // accepted samples, publishes that aggregate, then one wavefront looks back
 // over up to 64 predecessor tiles at a time to obtain the exclusive prefix.
@@ -23,10 +23,14 @@
 
 namespace abc {
 
-constexpr int CT_BLOCK = 1024;                   // 16 wavefronts
 constexpr int CT_STEPS = 16;                     // float4 loads per lane
 constexpr int CT_WAVE_SPAN = 64 * 4 * CT_STEPS;  // 4096 samples per wavefront
-constexpr int CT_TILE = (CT_BLOCK / 64) * CT_WAVE_SPAN;
+// Wavefronts per workgroup (tile = WAVES x 4096 samples): 16 for large inputs,
+// where fewer tickets and look-backs pay; 4 below CT_BIG_N, where small
+// workgroups also fit beside a resident simulate launch on another stream.
+constexpr int CT_WAVES_BIG = 16;
+constexpr int CT_WAVES_SMALL = 4;
+constexpr int64_t CT_BIG_N = (int64_t)1 << 25;
 
 constexpr uint64_t ST_AGG = 1;     // status word: (value << 2) | flag
 constexpr uint64_t ST_PREFIX = 2;
@@ -101,10 +105,12 @@ __device__ __forceinline__ void emit_row(const CompactArgs& a, int64_t k, int64_
     if (a.out_w) a.out_w[r] = a.weight[k];
 }
 
-__global__ __launch_bounds__(CT_BLOCK) void k_compact(CompactArgs a)
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
 {
+    constexpr int CT_TILE = WAVES * CT_WAVE_SPAN;
     __shared__ unsigned int tile_sh;
-    __shared__ int wave_tot[CT_BLOCK / 64];
+    __shared__ int wave_tot[WAVES];
     __shared__ int64_t excl_sh;
 
     const int tid = threadIdx.x;
@@ -141,7 +147,7 @@ __global__ __launch_bounds__(CT_BLOCK) void k_compact(CompactArgs a)
     __syncthreads();
     int wave_off = 0, block_tot = 0;
 #pragma unroll
-    for (int q = 0; q < CT_BLOCK / 64; ++q) {
+    for (int q = 0; q < WAVES; ++q) {
         if (q < wave) wave_off += wave_tot[q];
         block_tot += wave_tot[q];
     }
@@ -235,7 +241,9 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
         }
     }
     const hipStream_t s = as_stream(stream);
-    const int64_t num_tiles = (n + CT_TILE - 1) / CT_TILE;
+    const int waves = n >= CT_BIG_N ? CT_WAVES_BIG : CT_WAVES_SMALL;
+    const int64_t tile = (int64_t)waves * CT_WAVE_SPAN;
+    const int64_t num_tiles = (n + tile - 1) / tile;
     // scratch: one status word per tile + the ticket, stream-ordered
     void* scratch = nullptr;
     const size_t bytes = sizeof(unsigned long long) * (size_t)(num_tiles + 1);
@@ -260,7 +268,12 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
                        a.status, num_tiles, a.ticket, out_count);
     abc_status rc = check_launch("k_compact_init");
     if (rc == ABC_OK && num_tiles > 0) {
-        hipLaunchKernelGGL(k_compact, dim3((unsigned)num_tiles), dim3(CT_BLOCK), 0, s, a);
+        if (waves == CT_WAVES_BIG)
+            hipLaunchKernelGGL((k_compact<CT_WAVES_BIG>), dim3((unsigned)num_tiles),
+                               dim3(64 * CT_WAVES_BIG), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_compact<CT_WAVES_SMALL>), dim3((unsigned)num_tiles),
+                               dim3(64 * CT_WAVES_SMALL), 0, s, a);
         rc = check_launch("k_compact");
     }
     hipError_t e = hipFreeAsync(scratch, s);

@@ -202,8 +202,8 @@ def test_distance_fp32_accuracy_statement(A):
     assert all(abs(ref[i] - kth) <= 1e-3 * kth for i in diff), sorted(diff)
 
 
-@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 32767, 32768, 32769, 65536 + 4096 * 3 + 17,
-                               1_000_003])
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 16383, 16384, 16385, 65536 + 4096 * 3 + 17,
+                               1_000_003, (1 << 25) + 4096 * 5 + 3])
 def test_compact_matches_brute_force(A, n):
     rng = np.random.default_rng(n)
     dist = rng.exponential(size=n).astype(np.float32)
