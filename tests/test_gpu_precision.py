@@ -136,3 +136,32 @@ def test_precision_study(env):
         assert rep["fp32_naive"]["scale"]["accept_set_differences_vs_fp64_without_band"] <= 20
         report["countries"][s.name] = rep
     print("PRECISION_REPORT " + json.dumps(report))
+
+
+def test_same_path_and_flipped_path_errors(env):
+    """The float32 state path against the oracle's float64 integer path, sample
+    by sample: where every daily count agrees ("same path"), the float32
+    distance is within 1e-5 relative of the oracle's; where a float32 hazard
+    moved a floored count ("flipped path"), the error is reported separately
+    (those are the samples the float64 band decision exists for)."""
+    abc, P = env
+    n = 20_000
+    out = {}
+    for c, s in enumerate(W.three_countries()):
+        m = oracle.make_model(s.P, s.T)
+        obs = oracle.observe(m, s.theta_true, s.obs_seed)
+        ser = abc.DeviceSeries(s.P, s.T, torch.from_numpy(obs))
+        th = abc.sample_prior(n, seed=13, series=c)
+        tr32 = abc.simulate_record(ser, th, seed=13, series=c).cpu().numpy().astype(np.int64)
+        tr64 = oracle.record(m, th.cpu().numpy(), seed=13, series=c)
+        same = np.all(tr32 == tr64, axis=(1, 2))
+        d32 = abc.simulate_distance(ser, n, 13, theta=th, series=c).cpu().numpy().astype(np.float64)
+        ref = oracle.distances(m, obs, seed=13, n=n, series=c, theta=th.cpu().numpy())
+        rel = np.abs(d32 - ref) / ref
+        out[s.name] = {"same_path": int(same.sum()), "flipped_path": int((~same).sum()),
+                       "same_max_rel": float(rel[same].max()),
+                       "flipped_max_rel": float(rel[~same].max()) if (~same).any() else 0.0,
+                       "flipped_median_rel": float(np.median(rel[~same])) if (~same).any() else 0.0}
+        assert same.sum() > 0
+        assert rel[same].max() <= 1e-5, out[s.name]
+    print(json.dumps(out, indent=1))
