@@ -132,30 +132,61 @@ __device__ __forceinline__ void fill_slot(const SimArgs& a, int64_t k, uint32_t 
 constexpr int LB_Q = 64;          // grid a = 0, 0.5, ..., 31.5 (log2(1 + X) <= 31)
 constexpr int LB_MAX_BLOCKS = 96; // time blocks per table (48 KB for R and D)
 
-// Column col = c * LB_Q + q of the table: grid point q of table c (0 = R,
-// 1 = D). bval holds b_s for R then D in float64, staged by the caller.
-__device__ void build_future_bound(const double* bval, int T, int sh, int ntb, double exit2,
-                                   int col_id, float* tab)
+constexpr int LB_MAX_SEG = 8;      // day segments per column while building
+
+// Builds the [2][ntb][LB_Q] table; called by every thread of the workgroup
+// (it synchronises). Column (c, q) is grid point q of table c (0 = R, 1 = D);
+// the days are cut into S = blockDim / 128 segments (at most 8) so that S
+// threads share a column: each sums its segment, the segment sums give every
+// thread the sum over the days after its segment, and each thread then walks
+// its own days backwards storing the rows whose block ends there. stage holds
+// b_s for R then D in float64 (2 T values, staged by the caller) followed by
+// room for the [LB_MAX_SEG][2 LB_Q] segment sums.
+__device__ void build_future_bound(double* stage, int T, int sh, int ntb, double exit2, float* tab)
 {
-    const int c = col_id / LB_Q;
-    const int q = col_id % LB_Q;
-    const double g = 0.5 * q;
-    const double* b = bval + c * T;
-    float* col = tab + c * ntb * LB_Q + q;
+    const double* bval = stage;
+    double* segsum = stage + 2 * T;
+    int S = (int)blockDim.x / (2 * LB_Q);
+    S = S < 1 ? 1 : (S > LB_MAX_SEG ? LB_MAX_SEG : S);
+    const int L = (T + S - 1) / S;
     const double e = 0x1p-15;                         // float32 error of one log2 term
     const double sum_err = 2.0 * T * 0x1p-24 * exit2; // running-sum rounding below the bound
-    double F = 0.0;                                   // sum over days after t
-    for (int t = T; t >= 0; --t) {
-        const int tb = t >> sh;
-        const int tend = min(((tb + 1) << sh) - 1, T);
-        if (t == tend) {
-            double v = F - 2.0 * e * sqrt((double)T * F) - sum_err;
-            v *= 1.0 - 0x1p-20;
-            col[tb * LB_Q] = v > 0.0 ? (float)v : 0.0f;
-        }
-        if (t >= 1) {
+    // phase 1: the sum of each segment
+    for (int id = threadIdx.x; id < 2 * LB_Q * S; id += blockDim.x) {
+        const int col = id % (2 * LB_Q), seg = id / (2 * LB_Q);
+        const double g = 0.5 * (col % LB_Q);
+        const double* b = bval + (col / LB_Q) * T;
+        const int d0 = seg * L + 1, d1 = min((seg + 1) * L, T);
+        double F = 0.0;
+        for (int t = d1; t >= d0; --t) {
             const double x = g - b[t - 1];
             if (x > 0.0) F += x * x;
+        }
+        segsum[seg * 2 * LB_Q + col] = F;
+    }
+    __syncthreads();
+    // phase 2 and 3: each segment's rows, from the sum over the later days
+    for (int id = threadIdx.x; id < 2 * LB_Q * S; id += blockDim.x) {
+        const int col = id % (2 * LB_Q), seg = id / (2 * LB_Q);
+        const int c = col / LB_Q;
+        const double g = 0.5 * (col % LB_Q);
+        const double* b = bval + c * T;
+        float* out = tab + c * ntb * LB_Q + (col % LB_Q);
+        double F = 0.0;                                // sum over the days after t
+        for (int k = S - 1; k > seg; --k) F += segsum[k * 2 * LB_Q + col];
+        const int d0 = seg * L + 1, d1 = min((seg + 1) * L, T);
+        const int tlo = seg == 0 ? 0 : d0;
+        for (int t = d1; t >= tlo; --t) {
+            const int tb = t >> sh;
+            if (t == min(((tb + 1) << sh) - 1, T)) {
+                double v = F - 2.0 * e * sqrt((double)T * F) - sum_err;
+                v *= 1.0 - 0x1p-20;
+                out[tb * LB_Q] = v > 0.0 ? (float)v : 0.0f;
+            }
+            if (t >= 1) {
+                const double x = g - b[t - 1];
+                if (x > 0.0) F += x * x;
+            }
         }
     }
 }
@@ -192,12 +223,11 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     }
     if (DIST == 0 && ntb > 0) {
         // b_s of R and D in float64, staged where the ring will live
-        double* bval = reinterpret_cast<double*>(ring_all);
+        double* stage = reinterpret_cast<double*>(ring_all);
         for (int q = threadIdx.x; q < 2 * T; q += blockDim.x)
-            bval[q] = log1p((double)a.obs[T + q]) * 1.44269504088896340736;
+            stage[q] = log1p((double)a.obs[T + q]) * 1.44269504088896340736;
         __syncthreads();
-        for (int col = threadIdx.x; col < 2 * LB_Q; col += blockDim.x)
-            build_future_bound(bval, T, a.lb_sh, ntb, (double)a.exit_f32, col, tab);
+        build_future_bound(stage, T, a.lb_sh, ntb, (double)a.exit_f32, tab);
     }
     __syncthreads();
 
@@ -632,11 +662,12 @@ static unsigned refill_grid(int64_t n, int block, int blocks_per_cu)
 }
 
 // observed series | future-days bound table | ring (which first holds the
-// float64 b_s staged for the table, hence at least 2 T doubles with a table)
+// float64 b_s and the segment sums staged for the table)
 static size_t refill_lds_bytes(int T, int block, int lb_ntb)
 {
     const size_t ring = sizeof(Slot) * 64 * (size_t)(block / 64);
-    const size_t stage = lb_ntb > 0 ? sizeof(double) * 2 * (size_t)T : 0;
+    const size_t stage =
+        lb_ntb > 0 ? sizeof(double) * (2 * (size_t)T + (size_t)LB_MAX_SEG * 2 * LB_Q) : 0;
     return sizeof(float) * (size_t)((3 * T + 3) & ~3) + sizeof(float) * 2 * LB_Q * (size_t)lb_ntb +
            (ring > stage ? ring : stage);
 }

@@ -160,6 +160,8 @@ def test_future_bound_only_masks_rejections(A, which):
         assert np.all(full[inf_b] > eps)             # +INF keeps its meaning
         np.testing.assert_array_equal(np.nonzero(d_b <= eps)[0], np.nonzero(full <= eps)[0])
         assert days_b <= days_n
+        if which == "country-T72" and q == 1e-3:
+            assert days_b <= 0.8 * days_n   # the low-death country: the bound must bite
         print("%s q=%g: sample-days %d -> %d (%.1f%% fewer)"
               % (which, q, days_n, days_b, 100.0 * (1 - days_b / days_n)))
         # compensated sums take the same bound
