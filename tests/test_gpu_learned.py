@@ -1,7 +1,7 @@
 """What the learned proposal gains: on the same series and eps it must accept
 a larger fraction of simulated samples than prior sampling, and its
-importance-weighted posterior must agree with plain ABC's (the judge) within
-Monte Carlo error. With the defensive weight lambda = 1 the proposal is the
+importance-weighted posterior must agree with plain ABC's (the reference it
+is checked against) within Monte Carlo error. With the defensive weight lambda = 1 the proposal is the
 prior, every weight is 1, and the result is plain ABC again."""
 import math
 
