@@ -58,6 +58,10 @@ struct SetupArgs {
     double* y;            // [N][8]
 };
 
+// Particles loaded ahead of the ordered adds in the single-lane sums: the
+// order of the additions is unchanged, the loads no longer wait one by one.
+constexpr int SMC_PF = 16;
+
 // One workgroup of 1024 threads. Sums run left to right over the particles in
 // single lanes so that every rounding matches the plainly written definition.
 __global__ __launch_bounds__(1024) void k_smc_setup(SetupArgs a)
@@ -71,7 +75,18 @@ __global__ __launch_bounds__(1024) void k_smc_setup(SetupArgs a)
     // phase A: running weight sums (lane 64), sums of W theta (lanes 0..7)
     if (tid == 64) {
         double s = 0.0;
-        for (int j = 0; j < N; ++j) {
+        int j = 0;
+        for (; j + SMC_PF <= N; j += SMC_PF) {
+            double wv[SMC_PF];
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) wv[k] = a.w[j + k];
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) {
+                s = s + wv[k];
+                a.C[j + k] = s;
+            }
+        }
+        for (; j < N; ++j) {
             s = s + a.w[j];
             a.C[j] = s;
         }
@@ -80,7 +95,19 @@ __global__ __launch_bounds__(1024) void k_smc_setup(SetupArgs a)
     }
     if (tid < 8) {
         double s = 0.0;
-        for (int j = 0; j < N; ++j) s = s + a.w[j] * (double)a.theta[8 * j + tid];
+        int j = 0;
+        for (; j + SMC_PF <= N; j += SMC_PF) {
+            double wv[SMC_PF];
+            float tv[SMC_PF];
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) {
+                wv[k] = a.w[j + k];
+                tv[k] = a.theta[8 * (j + k) + tid];
+            }
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) s = s + wv[k] * (double)tv[k];
+        }
+        for (; j < N; ++j) s = s + a.w[j] * (double)a.theta[8 * j + tid];
         m_sh[tid] = s;
     }
     __syncthreads();
@@ -96,7 +123,24 @@ __global__ __launch_bounds__(1024) void k_smc_setup(SetupArgs a)
         const int c = tid - r * (r + 1) / 2;
         const double mr = m_sh[r], mc = m_sh[c];
         double s = 0.0;
-        for (int j = 0; j < N; ++j) {
+        int j = 0;
+        for (; j + SMC_PF <= N; j += SMC_PF) {
+            double wv[SMC_PF];
+            float tr[SMC_PF], tc[SMC_PF];
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) {
+                wv[k] = a.w[j + k];
+                tr[k] = a.theta[8 * (j + k) + r];
+                tc[k] = a.theta[8 * (j + k) + c];
+            }
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) {
+                const double dr = (double)tr[k] - mr;
+                const double dc = (double)tc[k] - mc;
+                s = s + wv[k] * (dr * dc);
+            }
+        }
+        for (; j < N; ++j) {
             const double dr = (double)a.theta[8 * j + r] - mr;
             const double dc = (double)a.theta[8 * j + c] - mc;
             s = s + a.w[j] * (dr * dc);
@@ -335,7 +379,15 @@ __global__ __launch_bounds__(1024) void k_smc_finish(const double* partial, int3
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int i = 0; i < N; ++i) s = s + W[i];
+        int i = 0;
+        for (; i + SMC_PF <= N; i += SMC_PF) {
+            double v[SMC_PF];
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) v[k] = W[i + k];
+#pragma unroll
+            for (int k = 0; k < SMC_PF; ++k) s = s + v[k];
+        }
+        for (; i < N; ++i) s = s + W[i];
         v_sh = s;
     }
     __syncthreads();
