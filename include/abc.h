@@ -293,7 +293,7 @@ typedef struct {
  * otherwise ABC_EUNSUPPORTED asks to split the batch. max_samples bounds the
  * samples per series; ABC_EOVERFLOW if some series then still lacks its quota
  * or produced more candidates (d <= eps (1 + band_w)) than cand_capacity rows
- * (0 = 4 quota, at most 16384, and the finalisation sorts them in LDS: about
+ * (0 = max(4 quota, 256), at most 16384, and the finalisation sorts them in LDS: about
  * 12 B per row must fit, so 8192 rows at most on gfx950); each round caps a series' share by its
  * candidate rate so far to stay within half the free capacity. Launch shape: abc_set_launch_config
  * (spl 1, 2 or 4). Blocks the calling host thread until done; the caller's

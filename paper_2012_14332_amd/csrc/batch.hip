@@ -182,10 +182,10 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
             int64_t lim = room > 0 ? room * next / (2 * (cand + 1)) : 0;
             if (lim < 64) lim = 64;
             if (n_s > lim) n_s = lim;
-        } else if (n_s > 2 * (int64_t)a.cand_cap) {
-            // first round: no rate seen yet; at most twice the capacity, safe
-            // for any acceptance rate up to one half
-            n_s = 2 * (int64_t)a.cand_cap;
+        } else if (n_s > (int64_t)a.cand_cap) {
+            // first round: no rate seen yet; at most the capacity, which no
+            // acceptance rate can overflow (one candidate per sample at most)
+            n_s = (int64_t)a.cand_cap;
         }
     }
     const int chunks = (int)((n_s + 63) / 64);
@@ -692,20 +692,23 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         return set_error(ABC_EUNSUPPORTED,
                          "batch needs %zu B of LDS per workgroup (> %d): split the series into groups",
                          lds + static_lds, max_lds);
+    // default candidate rows: 4 quota, and never fewer than 256 so that a
+    // small quota does not leave a one-chunk share able to overflow the list
+    const int cand_default = 4 * quota > 256 ? 4 * quota : 256;
     {
         int np = 1;
-        while (np < (cand_capacity ? cand_capacity : 4 * quota)) np <<= 1;
+        while (np < (cand_capacity ? cand_capacity : cand_default)) np <<= 1;
         const size_t lds_final = sizeof(int64_t) * np + sizeof(float) * (np + 1) +
                                  sizeof(double) * 3 * (size_t)maxT + 16;
         if (lds_final > (size_t)max_lds)
             return set_error(ABC_EINVAL, "cand_capacity %d needs %zu B of LDS to sort (> %d)",
-                             cand_capacity ? cand_capacity : 4 * quota, lds_final, max_lds);
+                             cand_capacity ? cand_capacity : cand_default, lds_final, max_lds);
     }
     const int per_cu = (int)(163840 / (lds + static_lds));
     const unsigned grid = (unsigned)num_cu * (unsigned)(per_cu < bpc ? (per_cu > 0 ? per_cu : 1) : bpc);
     ABC_REQUIRE(cand_capacity == 0 || (cand_capacity >= quota && cand_capacity <= 16384),
-                "cand_capacity must be 0 (4 quota) or in [quota, 16384]");
-    const int cand_cap = cand_capacity ? cand_capacity : 4 * quota;
+                "cand_capacity must be 0 (max(4 quota, 256)) or in [quota, 16384]");
+    const int cand_cap = cand_capacity ? cand_capacity : cand_default;
     int npow_cap = 1;
     while (npow_cap < cand_cap) npow_cap <<= 1;
 

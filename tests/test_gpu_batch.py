@@ -113,3 +113,70 @@ def test_batch_limits(env):
     o = abc.batch_run(sers, [e * 3 for e in eps], 9, 20, round_size=1 << 18, cand_capacity=20,
                       check=False)
     assert o["status"] == -5
+
+
+def _agree_first(d, eps, got, want):
+    if not np.array_equal(got, want):
+        diff = set(got.tolist()) ^ set(want.tolist())
+        assert all(abs(d[i] - eps) < TIE * eps for i in diff if i < len(d)), diff
+
+
+def test_batch_extremes(env):
+    """Series at the limits in one batch: T = 1, T = 200 at P = 1e9, the
+    smallest population (P = A0: no room for I0), quota 1, and a tolerance
+    above every distance (the first Q indices are the answer)."""
+    abc, P = env
+    specs = [(1_000_000, 1, W.THETA_NZ), (1_000_000_000, 200, W.THETA_USA), (100, 40, W.THETA_ITALY),
+             (50_000_000, 60, W.THETA_ITALY)]
+    sers, obs_l = [], []
+    for j, (Pp, T, th) in enumerate(specs):
+        obs = oracle.observe(oracle.make_model(Pp, T), th, 31, series=j)
+        obs_l.append(obs)
+        sers.append(abc.DeviceSeries(Pp, T, torch.from_numpy(obs)))
+    eps = []
+    refs = []
+    for j, (Pp, T, _) in enumerate(specs):
+        d = oracle.distances(oracle.make_model(Pp, T), obs_l[j], seed=9, n=40_000, series=j)
+        refs.append(d)
+        u = np.unique(d)
+        k = max(1, int(np.searchsorted(u, np.quantile(d, 2e-3))))
+        eps.append(float(0.5 * (u[k - 1] + u[k])))
+    eps[3] = 1e30                                  # every sample of series 3 is accepted
+    for quota in (1, 25):
+        out = abc.batch_run(sers, eps, 9, quota, round_size=1 << 14)
+        cnt, used, idx = (out[k].cpu().numpy() for k in ("count", "used", "idx"))
+        assert np.all(cnt == quota), cnt
+        for j, (Pp, T, _) in enumerate(specs):
+            d = refs[j]
+            if used[j] > d.size:
+                d = oracle.distances(oracle.make_model(Pp, T), obs_l[j], seed=9, n=int(used[j]),
+                                     series=j)
+            _agree_first(d, eps[j], idx[j], oracle.first_accepted(d, eps[j], quota))
+        np.testing.assert_array_equal(idx[3], np.arange(quota))
+
+
+def test_batch_single_series_equals_plain_path(env):
+    abc, P = env
+    s = W.uneven_series(64, 5)[7]
+    ser = P.observed_series(s)
+    eps = P.pilot_eps(ser, 9, n=20000, q=5e-3, series=0)
+    out = abc.batch_run([ser], [eps], 9, 60, round_size=1 << 15)
+    used = int(out["used"][0].item())
+    run = P.PlainABC(ser, 9, eps, used, series=0, capacity=1 << 14)
+    res = run.run(0)
+    plain = res.idx[:res.n()].cpu().numpy()[:60]
+    np.testing.assert_array_equal(out["idx"][0].cpu().numpy(), plain)
+
+
+def test_batch_series_count_limit(env):
+    """256 series (the most one batch takes; short ones, since every series'
+    observations sit in LDS at once) and 257 rejected."""
+    abc, P = env
+    obs = oracle.observe(oracle.make_model(1_000_000, 20), W.THETA_ITALY, 32)
+    ser = abc.DeviceSeries(1_000_000, 20, torch.from_numpy(obs))
+    eps = P.pilot_eps(ser, 9, n=20000, q=2e-2, series=0)
+    m = 256
+    out = abc.batch_run([ser] * m, [eps] * m, 9, 3, round_size=1 << 16, series_ids=list(range(m)))
+    assert np.all(out["count"].cpu().numpy() == 3)
+    with pytest.raises(abc.AbcError):
+        abc.batch_run([ser] * (m + 1), [eps] * (m + 1), 9, 3, series_ids=list(range(m + 1)))
