@@ -98,6 +98,19 @@ def test_generations_match_oracle_stepwise(env, N, alpha, chunk0):
         _compare(out, gens[t], "gen%d" % t)
 
 
+@pytest.mark.parametrize("N,alpha", [(12, 1.0), (16, 0.1)])
+def test_small_populations_and_extreme_quantiles(env, N, alpha):
+    """Few particles (the covariance of 8 parameters needs at least 9) and
+    the extreme tolerance quantiles: alpha = 1 keeps the previous generation's
+    largest distance, alpha = 0.1 its second smallest of 16."""
+    abc, s, m, obs, eps0, ser = env
+    gens = osmc.smc_abc(m, obs, seed=8, N=N, generations=3, alpha=alpha, eps0=eps0)
+    cfg = abc.smc_config(N, eps0, alpha=alpha, chunk0=1 << 12, chunk_max=1 << 16)
+    for t in range(1, len(gens)):
+        out = abc.smc_generation(ser, cfg, 8, t, _upload(gens[t - 1]), want_ancestors=True)
+        _compare(out, gens[t], "gen%d" % t)
+
+
 def test_full_run_matches_oracle(env):
     abc, s, m, obs, eps0, ser = env
     gens = osmc.smc_abc(m, obs, seed=8, N=200, generations=5, alpha=0.5, eps0=eps0)
