@@ -63,7 +63,14 @@ class PlainResult:
     rechecked: Optional[torch.Tensor] = None
 
     def n(self) -> int:
-        return int(self.count.item())
+        """Accepted rows. An overflowed candidate list (more candidates than
+        the pass's capacity) has no float64 band decision and only part of the
+        rows, so it raises instead of returning a partial answer."""
+        c = int(self.count.item())
+        if c > self.idx.shape[0]:
+            raise abc.AbcError("%d candidates exceed the capacity %d: run again with a larger "
+                               "capacity" % (c, self.idx.shape[0]))
+        return c
 
 
 class PlainABC:

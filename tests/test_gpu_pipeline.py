@@ -74,3 +74,15 @@ def test_plain_pass_country_T100_offset(P):
 def test_plain_pass_uneven_series(P):
     for s in W.uneven_series(64, 5)[:4]:
         _check(P, s, 200_000, 5e-3, 0.02)
+
+
+def test_overflowed_pass_raises_instead_of_answering(P):
+    from paper_2012_14332_amd import abc
+
+    s = W.three_countries()[0]
+    ser = P.observed_series(s)
+    res = P.PlainABC(ser, 11, 1e30, 100_000, capacity=1000).run(0)
+    with pytest.raises(abc.AbcError):
+        res.n()
+    ok = P.PlainABC(ser, 11, 1e30, 100_000, capacity=100_000).run(0)
+    assert ok.n() == 100_000
