@@ -298,13 +298,43 @@ __global__ void k_sum_splits(const float* part, int splits, int64_t mn, float* o
     out[e] = s;
 }
 
-// column sums of x [rows][cols] -> out[cols] (one thread per column, in row order)
-__global__ void k_colsum(const float* x, int rows, int cols, float* out)
+// column sums of x [rows][cols] -> out[cols], in two fixed-order levels:
+// workgroup (column tile, row block) sums CS_ROWS rows of 64 columns, four
+// row groups per column (rows r0 + g, r0 + g + 4, ... in order, loaded 16
+// ahead) added in group order; then each column adds its row blocks in order.
+constexpr int CS_ROWS = 256;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float* x, int rows, int cols, float* part)
+{
+    __shared__ float red[4][64];
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + l;
+    const int r0 = blockIdx.y * CS_ROWS;
+    const int r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
+    float s = 0.0f;
+    if (c < cols) {
+        int r = r0 + g;
+        for (; r + 4 * 15 < r1; r += 64) {
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = x[(int64_t)(r + 4 * k) * cols + c];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s += v[k];
+        }
+        for (; r < r1; r += 4) s += x[(int64_t)r * cols + c];
+    }
+    red[g][l] = s;
+    __syncthreads();
+    if (g == 0 && c < cols)
+        part[(int64_t)blockIdx.y * cols + c] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+}
+
+__global__ void k_colsum_fin(const float* part, int blocks, int cols, float* out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += x[(int64_t)r * cols + c];
+    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * cols + c];
     out[c] = s;
 }
 
@@ -351,63 +381,64 @@ __global__ void k_gather(GatherArgs a)
 __global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float* T, int n,
                                                   float* dout, bf16* dout_b, float* loss_acc)
 {
+    // one wavefront per row; lane = k NN_D + j holds component k, dimension j
+    static_assert(NN_K * NN_D == 64, "one lane per (component, dimension)");
     __shared__ float red[4];
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = blockIdx.x * 4 + wv;
     float nll = 0.0f;
-    if (r < n) {
+    if (r < n) {  // uniform over the wavefront
         const float* o = out + (int64_t)r * NN_OUT;
-        const float* t = T + (int64_t)r * NN_D;
         float* g = dout + (int64_t)r * NN_OUT;
         bf16* gb = dout_b + (int64_t)r * NN_OUT;
+        const int k = lane / NN_D, j = lane % NN_D;
+        // log-softmax of the mixture logits (every lane, same values)
         float lmax = -INFINITY;
-        for (int k = 0; k < NN_K; ++k) lmax = fmaxf(lmax, o[k]);
+#pragma unroll
+        for (int q = 0; q < NN_K; ++q) lmax = fmaxf(lmax, o[q]);
         float se = 0.0f;
-        for (int k = 0; k < NN_K; ++k) se += expf(o[k] - lmax);
+#pragma unroll
+        for (int q = 0; q < NN_K; ++q) se += expf(o[q] - lmax);
         const float lse_logits = lmax + logf(se);
-        float L[NN_K];
-        float Lmax = -INFINITY;
-        for (int k = 0; k < NN_K; ++k) {
-            float c = o[k] - lse_logits - 0.5f * NN_D * 1.83787706640934548356f;
-            for (int j = 0; j < NN_D; ++j) {
-                const float mu = o[NN_K + k * NN_D + j];
-                const float ls = fminf(fmaxf(o[NN_K + NN_K * NN_D + k * NN_D + j], LOGSIG_LO), LOGSIG_HI);
-                const float u = (t[j] - mu) * expf(-ls);
-                c += -0.5f * u * u - ls;
-            }
-            L[k] = c;
-            Lmax = fmaxf(Lmax, c);
-        }
-        float sr = 0.0f;
-        for (int k = 0; k < NN_K; ++k) sr += expf(L[k] - Lmax);
+        // this lane's Gaussian factor
+        const float mu = o[NN_K + lane];
+        const float raw = o[NN_K + NN_K * NN_D + lane];
+        const float ls = fminf(fmaxf(raw, LOGSIG_LO), LOGSIG_HI);
+        const float si = expf(-ls);
+        const float u = (T[(int64_t)r * NN_D + j] - mu) * si;
+        float term = -0.5f * u * u - ls;
+        term += __shfl_xor(term, 1, 64);
+        term += __shfl_xor(term, 2, 64);
+        term += __shfl_xor(term, 4, 64);
+        const float logit = o[k];
+        const float Lk = logit - lse_logits - 0.5f * NN_D * 1.83787706640934548356f + term;
+        // log-sum-exp over the components (the 8 lane groups)
+        float Lmax = Lk;
+        Lmax = fmaxf(Lmax, __shfl_xor(Lmax, 8, 64));
+        Lmax = fmaxf(Lmax, __shfl_xor(Lmax, 16, 64));
+        Lmax = fmaxf(Lmax, __shfl_xor(Lmax, 32, 64));
+        float sr = expf(Lk - Lmax);
+        sr += __shfl_xor(sr, 8, 64);
+        sr += __shfl_xor(sr, 16, 64);
+        sr += __shfl_xor(sr, 32, 64);
         const float lse = Lmax + logf(sr);
         nll = -lse;
         const float inv_n = 1.0f / (float)n;
-        for (int k = 0; k < NN_K; ++k) {
-            const float resp = expf(L[k] - lse);
-            const float pik = expf(o[k] - lse_logits);
-            const float gk = (pik - resp) * inv_n;
+        const float resp = expf(Lk - lse);
+        const float gmu = -resp * u * si * inv_n;
+        const float gls = (raw > LOGSIG_LO && raw < LOGSIG_HI) ? -resp * (u * u - 1.0f) * inv_n : 0.0f;
+        g[NN_K + lane] = gmu;
+        gb[NN_K + lane] = f2bf(gmu);
+        g[NN_K + NN_K * NN_D + lane] = gls;
+        gb[NN_K + NN_K * NN_D + lane] = f2bf(gls);
+        if (j == 0) {
+            const float gk = (expf(logit - lse_logits) - resp) * inv_n;
             g[k] = gk;
             gb[k] = f2bf(gk);
-            for (int j = 0; j < NN_D; ++j) {
-                const float mu = o[NN_K + k * NN_D + j];
-                const float raw = o[NN_K + NN_K * NN_D + k * NN_D + j];
-                const float ls = fminf(fmaxf(raw, LOGSIG_LO), LOGSIG_HI);
-                const float si = expf(-ls);
-                const float u = (t[j] - mu) * si;
-                const float gmu = -resp * u * si * inv_n;
-                const float gls = (raw > LOGSIG_LO && raw < LOGSIG_HI) ? -resp * (u * u - 1.0f) * inv_n : 0.0f;
-                g[NN_K + k * NN_D + j] = gmu;
-                gb[NN_K + k * NN_D + j] = f2bf(gmu);
-                g[NN_K + NN_K * NN_D + k * NN_D + j] = gls;
-                gb[NN_K + NN_K * NN_D + k * NN_D + j] = f2bf(gls);
-            }
         }
     }
-    // block sum of the NLL, one atomic per workgroup
-    float v = nll;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    // block sum of the NLL (the same in every lane of a row), one atomic per workgroup
+    if (lane == 0) red[wv] = nll;
     __syncthreads();
     if (threadIdx.x == 0 && loss_acc) atomicAdd(loss_acc, (red[0] + red[1] + red[2] + red[3]) / (float)n);
 }
@@ -554,7 +585,7 @@ struct abc_mdn {
     int ws = 0;  // workspace rows
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dOUTb = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
     float *T = nullptr, *Z1 = nullptr, *Z2 = nullptr, *OUT = nullptr, *dOUT = nullptr,
-          *dZ2 = nullptr, *dZ1 = nullptr, *part = nullptr;
+          *dZ2 = nullptr, *dZ1 = nullptr, *part = nullptr, *cs_part = nullptr;
     int64_t* perm = nullptr;
 };
 
@@ -563,11 +594,11 @@ namespace {
 void free_ws(abc_mdn* n)
 {
     void* ptrs[] = {n->X, n->H1, n->H2, n->dOUTb, n->dZ2b, n->dZ1b, n->T, n->Z1, n->Z2,
-                    n->OUT, n->dOUT, n->dZ2, n->dZ1, n->part};
+                    n->OUT, n->dOUT, n->dZ2, n->dZ1, n->part, n->cs_part};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     n->X = n->H1 = n->H2 = n->dOUTb = n->dZ2b = n->dZ1b = nullptr;
-    n->T = n->Z1 = n->Z2 = n->OUT = n->dOUT = n->dZ2 = n->dZ1 = n->part = nullptr;
+    n->T = n->Z1 = n->Z2 = n->OUT = n->dOUT = n->dZ2 = n->dZ1 = n->part = n->cs_part = nullptr;
     n->ws = 0;
 }
 
@@ -592,6 +623,7 @@ abc_status ensure_ws(abc_mdn* n, int rows)
     ALLOC(n->dZ1, r * NN_H * sizeof(float));
     ALLOC(n->dZ1b, r * NN_H * sizeof(bf16));
     ALLOC(n->part, (size_t)splits * NN_H * NN_H * sizeof(float));
+    ALLOC(n->cs_part, (size_t)((rows + CS_ROWS - 1) / CS_ROWS) * NN_H * sizeof(float));
 #undef ALLOC
     n->ws = rows;
     return ABC_OK;
@@ -636,10 +668,19 @@ void forward(abc_mdn* net, int n, hipStream_t s)
     gemm<false, false, EPI_STORE>(g, 0, s);
 }
 
+void colsum(const float* x, int rows, int cols, float* out, float* part, hipStream_t s)
+{
+    const int blocks = (rows + CS_ROWS - 1) / CS_ROWS;
+    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, blocks), dim3(256), 0, s, x, rows, cols,
+                       part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((cols + 255) / 256), dim3(256), 0, s, part, blocks, cols,
+                       out);
+}
+
 // loss + gradient of the mean NLL into net->g (forward must have run)
 void backward(abc_mdn* net, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mdn_loss, dim3((n + 255) / 256), dim3(256), 0, s, net->OUT, net->T, n,
+    hipLaunchKernelGGL(k_mdn_loss, dim3((n + 3) / 4), dim3(256), 0, s, net->OUT, net->T, n,
                        net->dOUT, net->dOUTb, net->loss_acc);
     const int kps = k_per_split_for(n), used = splits_for(n);
     // dW3 = H2^T dOUT, db3 = colsum(dOUT)
@@ -650,7 +691,7 @@ void backward(abc_mdn* net, int n, hipStream_t s)
     gemm<true, false, EPI_STORE>(g, kps, s);
     hipLaunchKernelGGL(k_sum_splits, dim3((NN_H * NN_OUT + 255) / 256), dim3(256), 0, s, net->part,
                        used, (int64_t)NN_H * NN_OUT, net->g + OFF_W3);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(NN_OUT), 0, s, net->dOUT, n, NN_OUT, net->g + OFF_B3);
+    colsum(net->dOUT, n, NN_OUT, net->g + OFF_B3, net->cs_part, s);
     // dZ2 = (dOUT W3^T) gelu'(Z2)
     g = GemmArgs{};
     g.M = n; g.N = NN_H; g.K = NN_OUT;
@@ -665,7 +706,7 @@ void backward(abc_mdn* net, int n, hipStream_t s)
     gemm<true, false, EPI_STORE>(g, kps, s);
     hipLaunchKernelGGL(k_sum_splits, dim3((NN_H * NN_H + 255) / 256), dim3(256), 0, s, net->part,
                        used, (int64_t)NN_H * NN_H, net->g + OFF_W2);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(NN_H), 0, s, net->dZ2, n, NN_H, net->g + OFF_B2);
+    colsum(net->dZ2, n, NN_H, net->g + OFF_B2, net->cs_part, s);
     // dZ1 = (dZ2 W2^T) gelu'(Z1)
     g = GemmArgs{};
     g.M = n; g.N = NN_H; g.K = NN_H;
@@ -680,7 +721,7 @@ void backward(abc_mdn* net, int n, hipStream_t s)
     gemm<true, false, EPI_STORE>(g, kps, s);
     hipLaunchKernelGGL(k_sum_splits, dim3((NN_IN * NN_H + 255) / 256), dim3(256), 0, s, net->part,
                        used, (int64_t)NN_IN * NN_H, net->g + OFF_W1);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(NN_H), 0, s, net->dZ1, n, NN_H, net->g + OFF_B1);
+    colsum(net->dZ1, n, NN_H, net->g + OFF_B1, net->cs_part, s);
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
