@@ -201,7 +201,10 @@ struct GemmArgs {
     const float* Zin;
 };
 
-template <bool TA, bool TB, int EPI>
+// VEC: every operand row, column count and K range is a multiple of 8
+// elements and 16-byte aligned, so each thread stages one 8-element vector of
+// A and one of B per K step (one global load each) instead of eight scalars.
+template <bool TA, bool TB, int EPI, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 {
     __shared__ __align__(16) bf16 As[G_BM][G_LD];
@@ -219,6 +222,44 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = kbeg; k0 < kend; k0 += G_BK) {
+        if constexpr (VEC) {
+            typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+            const us8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+            // A: 64 x 32 as 256 vectors of 8
+            if (!TA) {
+                const int mm = tid >> 2, kv = (tid & 3) * 8;
+                const int gm = m0 + mm, gk = k0 + kv;
+                us8 v = zero;
+                if (gm < g.M && gk < kend)
+                    v = *reinterpret_cast<const us8*>(g.A + (int64_t)gm * g.lda + gk);
+                *reinterpret_cast<us8*>(&As[mm][kv]) = v;
+            } else {
+                const int kk = tid >> 3, mv = (tid & 7) * 8;
+                const int gm = m0 + mv, gk = k0 + kk;
+                us8 v = zero;
+                if (gm < g.M && gk < kend)
+                    v = *reinterpret_cast<const us8*>(g.A + (int64_t)gk * g.lda + gm);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) As[mv + q][kk] = v[q];
+            }
+            // B: 32 x 64 as 256 vectors of 8, stored [n][k]
+            if (TB) {
+                const int nn = tid >> 2, kv = (tid & 3) * 8;
+                const int gn = n0 + nn, gk = k0 + kv;
+                us8 v = zero;
+                if (gn < g.N && gk < kend)
+                    v = *reinterpret_cast<const us8*>(g.B + (int64_t)gn * g.ldb + gk);
+                *reinterpret_cast<us8*>(&Bs[nn][kv]) = v;
+            } else {
+                const int kk = tid >> 3, nv = (tid & 7) * 8;
+                const int gn = n0 + nv, gk = k0 + kk;
+                us8 v = zero;
+                if (gn < g.N && gk < kend)
+                    v = *reinterpret_cast<const us8*>(g.B + (int64_t)gk * g.ldb + gn);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Bs[nv + q][kk] = v[q];
+            }
+        } else {
         // stage A: 64 x 32
         for (int e = tid; e < G_BM * G_BK; e += 256) {
             int mm, kk;
@@ -238,6 +279,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
             bf16 v = 0;
             if (gn < g.N && gk < kend) v = TB ? g.B[(int64_t)gn * g.ldb + gk] : g.B[(int64_t)gk * g.ldb + gn];
             Bs[nn][kk] = v;
+        }
         }
         __syncthreads();
 #pragma unroll
@@ -293,8 +335,17 @@ __global__ void k_sum_splits(const float* part, int splits, int64_t mn, float* o
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= mn) return;
+    // in split order, loads issued 8 ahead of the adds
     float s = 0.0f;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * mn + e];
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(z + q) * mn + e];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; z < splits; ++z) s += part[(int64_t)z * mn + e];
     out[e] = s;
 }
 
@@ -334,7 +385,15 @@ __global__ void k_colsum_fin(const float* part, int blocks, int cols, float* out
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.0f;
-    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * cols + c];
+    int b = 0;
+    for (; b + 8 <= blocks; b += 8) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(b + q) * cols + c];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; b < blocks; ++b) s += part[(int64_t)b * cols + c];
     out[c] = s;
 }
 
@@ -564,7 +623,14 @@ static void gemm(const GemmArgs& g0, int kps, hipStream_t s)
     const int splits = (g.K + g.k_per_split - 1) / g.k_per_split;
     g.split_stride = (int64_t)g.M * g.N;
     const dim3 grid((g.N + G_BN - 1) / G_BN, (g.M + G_BM - 1) / G_BM, splits);
-    hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    const bool vec = g.M % 8 == 0 && g.N % 8 == 0 && g.K % 8 == 0 && g.lda % 8 == 0 &&
+                     g.ldb % 8 == 0 && g.k_per_split % 8 == 0 &&
+                     (reinterpret_cast<uintptr_t>(g.A) & 15u) == 0 &&
+                     (reinterpret_cast<uintptr_t>(g.B) & 15u) == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI, true>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI, false>), grid, dim3(256), 0, s, g);
 }
 
 }  // namespace abc
