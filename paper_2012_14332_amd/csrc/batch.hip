@@ -639,6 +639,8 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     ABC_REQUIRE(rounds_per_graph >= 1 && rounds_per_graph <= 64, "rounds_per_graph in [1, 64]");
     ABC_REQUIRE(out_idx && out_theta && out_dist && out_count && out_used && out_mean && out_cov,
                 "NULL output pointer");
+    ABC_REQUIRE(cand_capacity == 0 || (cand_capacity >= quota && cand_capacity <= 16384),
+                "cand_capacity must be 0 (max(4 quota, 256)) or in [quota, 16384]");
     float lo[8], width[8];
     if ((rc = prior_lo_width(prior, lo, width))) return rc;
     for (int k = 0; k < 8; ++k) ABC_REQUIRE(prior->lo[k] >= 0.0f, "prior lo[%d] < 0", k);
@@ -706,8 +708,6 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     }
     const int per_cu = (int)(163840 / (lds + static_lds));
     const unsigned grid = (unsigned)num_cu * (unsigned)(per_cu < bpc ? (per_cu > 0 ? per_cu : 1) : bpc);
-    ABC_REQUIRE(cand_capacity == 0 || (cand_capacity >= quota && cand_capacity <= 16384),
-                "cand_capacity must be 0 (max(4 quota, 256)) or in [quota, 16384]");
     const int cand_cap = cand_capacity ? cand_capacity : cand_default;
     int npow_cap = 1;
     while (npow_cap < cand_cap) npow_cap <<= 1;

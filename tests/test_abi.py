@@ -133,3 +133,45 @@ def test_host_validation_of_the_newer_entry_points(built):
         assert L.abc_batch_run_weighted(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 10, 4096,
                                         100, 0.02, 1, 0, ctypes.byref(prop), fake, fake, fake, fake,
                                         fake, fake, fake, fake, ctypes.byref(bst), None) == -1
+
+
+def test_host_validation_of_limits_and_special_values(built):
+    """The documented limits (T <= ABC_T_MAX, n <= 2^36), NaN or negative
+    tolerances, misaligned buffers and capacity options are rejected on the
+    host; eps = +INF is accepted where it means "no bound" or "accept all"."""
+    from paper_2012_14332_amd import abc
+
+    L = abc.lib()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    odd = ctypes.c_void_p(0x1004)       # not 16-byte aligned
+    pr = abc.make_prior()
+    st = abc.make_stream(1, 1, 0)
+    md = abc._Model(1.0, 0)
+    sim = lambda ser, n, e, dist=fake: L.abc_simulate_distance(
+        ctypes.byref(ser), ctypes.byref(md), ctypes.byref(st), None, ctypes.byref(pr), 0, n, e, dist,
+        None, None, None)
+    ser = abc._Series(1000000, 100, 0, 0, 1025, 0x1000)        # T beyond ABC_T_MAX
+    assert sim(ser, 10, float("inf")) == -1 and b"T = 1025" in L.abc_last_error()
+    ser = abc._Series(1000000, 100, 0, 0, 50, 0x1000)
+    assert sim(ser, (1 << 36) + 1, float("inf")) == -1          # n beyond 2^36
+    assert sim(ser, 10, float("nan")) == -1                     # NaN exit bound
+    assert sim(ser, 10, -1.0) == -1                             # negative exit bound
+    assert sim(ser, 0, float("inf"), None) == 0                 # n = 0: nothing to do
+    # compaction: NaN tolerance; +INF is "accept every sample"
+    cnt = fake
+    assert L.abc_accept_compact(fake, None, None, ctypes.byref(pr), ctypes.byref(st), 10, 0,
+                                float("nan"), 0, None, None, None, None, cnt, None) == -1
+    # band decision: NaN or negative eps, band width outside [0, 1)
+    for e, w in ((float("nan"), 0.02), (-1.0, 0.02), (1.0, 1.0), (1.0, -0.1)):
+        assert L.abc_recheck_band(ctypes.byref(ser), ctypes.byref(md), ctypes.byref(st), e, w, 10,
+                                  fake, fake, fake, None, fake, None, None) == -1
+    # moments: theta must be 16-byte aligned, n_max >= 0
+    assert L.abc_posterior_moments(odd, None, None, 10, fake, fake, None) == -1
+    assert L.abc_posterior_moments(fake, None, None, -1, fake, fake, None) == -1
+    # batched: candidate capacity below the quota or above 16384
+    bs = (abc._BatchSeries * 1)(abc._BatchSeries(1000000, 100, 0, 0, 10, 0x1000, 1.0, 0))
+    bst = abc._BatchStats()
+    for cap in (99, 16385):
+        assert L.abc_batch_run(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 100, 4096, 1000,
+                               0.02, 1, cap, fake, fake, fake, fake, fake, fake, fake,
+                               ctypes.byref(bst), None) == -1
