@@ -278,57 +278,71 @@ __device__ inline double simulate_one_f64(const float thv[8], uint64_t i, Key ke
     return sqrt(acc);
 }
 
-// One trajectory in float64 run by a whole wavefront (64 threads, one
-// wavefront per workgroup): the lanes draw the normals of all days in
-// parallel, lane 0 walks the state through the days, the lanes form the
-// squared distance terms in parallel, and lane 0 adds them in day order
-// (the order of simulate_one_f64, so the result is the same double).
-// Scratch: zs [5 T] doubles, xs [3 T] int32 in LDS. Returns the distance on
-// lane 0 (other lanes return 0).
+// Up to ROWS_PER_WAVE_MAX float64 trajectories run by one wavefront (one
+// wavefront per workgroup): the lanes draw the normals of every (row, day)
+// pair in parallel, lane r walks row r through the days, the lanes form the
+// squared distance terms in parallel, and lane r adds its row's terms in day
+// order (the order of simulate_one_f64, so each result is the same double).
+// A float64 instruction occupies the SIMD for the same cycles whatever its
+// lane mask, so rows walked side by side in lanes cost no more than one.
+// Rows r < nr: theta rth[8 r .. 8 r + 7] and sample index rix[r], in LDS.
+// Scratch in LDS: zs [nr][5 T] doubles, xs [nr][3 T] int32. Returns row r's
+// distance on lane r < nr (other lanes return 0).
+constexpr int ROWS_PER_WAVE_MAX = 8;
+
 template <int NOISE, int DIST>
-__device__ double simulate_row_f64_wave(const float thv[8], uint64_t i, Key key, uint32_t series,
-                                        uint32_t domain, int32_t P, int32_t A0, int32_t R0,
-                                        int32_t D0, int T, double scale, const double* lobs,
-                                        double* zs, int32_t* xs)
+__device__ double simulate_rows_f64_wave(int nr, const float* rth, const uint64_t* rix, Key key,
+                                         uint32_t series, uint32_t domain, int32_t P, int32_t A0,
+                                         int32_t R0, int32_t D0, int T, double scale,
+                                         const double* lobs, double* zs, int32_t* xs)
 {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
-    for (int t = 1 + lane; t <= T; t += 64) {
-        const uint4 w = stream_words(key, i, series, ctr_word3((uint32_t)t, domain, 0));
+    const int ZT = 5 * T, XT = 3 * T;
+    for (int p = lane; p < nr * T; p += 64) {
+        const int r = p / T, t = p - r * T + 1;
+        const uint4 w = stream_words(key, rix[r], series, ctr_word3((uint32_t)t, domain, 0));
         double z[5];
         normals_f64(w, z);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) zs[5 * (t - 1) + k] = z[k];
+        for (int k = 0; k < 5; ++k) zs[r * ZT + 5 * (t - 1) + k] = z[k];
     }
     __syncthreads();
-    if (lane == 0) {
+    if (lane < nr) {
+        float thv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) thv[k] = rth[8 * lane + k];
         const Theta th = theta_from(thv);
         State s = init_state(th.ka, P, A0, R0, D0);
         const double Pd = (double)P;
+        const double* zr = zs + lane * ZT;
+        int32_t* xr = xs + lane * XT;
         for (int t = 1; t <= T; ++t) {
             double z[5];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) z[k] = zs[5 * (t - 1) + k];
+            for (int k = 0; k < 5; ++k) z[k] = zr[5 * (t - 1) + k];
             day_step_f64<NOISE>(s, th, Pd, scale, z);
-            xs[3 * (t - 1) + 0] = s.A;
-            xs[3 * (t - 1) + 1] = s.R;
-            xs[3 * (t - 1) + 2] = s.D;
+            xr[3 * (t - 1) + 0] = s.A;
+            xr[3 * (t - 1) + 1] = s.R;
+            xr[3 * (t - 1) + 2] = s.D;
         }
     }
     __syncthreads();
-    for (int q = lane; q < 3 * T; q += 64) {
+    for (int p = lane; p < nr * XT; p += 64) {
+        const int r = p / XT, q = p - r * XT;
         const int t = q / 3, c = q - 3 * t;
         double d;
         if (DIST == 0)
-            d = log1p((double)xs[q]) - lobs[c * T + t];
+            d = log1p((double)xs[r * XT + q]) - lobs[c * T + t];
         else
-            d = (double)xs[q] - lobs[c * T + t];
-        zs[q] = d * d;
+            d = (double)xs[r * XT + q] - lobs[c * T + t];
+        zs[r * ZT + q] = d * d;
     }
     __syncthreads();
     double acc = 0.0;
-    if (lane == 0) {
-        for (int q = 0; q < 3 * T; ++q) acc += zs[q];
+    if (lane < nr) {
+        const double* tr = zs + lane * ZT;
+        for (int q = 0; q < XT; ++q) acc += tr[q];
         acc = sqrt(acc);
     }
     return acc;

@@ -419,48 +419,85 @@ struct RecheckArgs {
     int64_t* count;
     uint8_t* keep;   // scratch [capacity]
     int32_t* rechecked;  // nullable: number of rows simulated in float64
+    int32_t rows_max;    // rows per wavefront the LDS was sized for
 };
 
-// Pass 1: one wavefront per in-band candidate row (simulate_row_f64_wave);
-// rows outside the band only get their keep flag. Workgroups that meet no
-// in-band row never stage the observed series. Spreading the rows over many
-// wavefronts keeps the time any one SIMD spends on them short: this kernel
-// runs beside the next float32 launch, which it should not hold up.
+// LDS of the float64 row kernels, for up to R rows per wavefront:
+// obs [3 T] f64 | zs [R][5 T] f64 | rix [R] u64 | rq [R] i64 | xs [R][3 T] i32 | rth [R][8] f32
+struct RowLds {
+    double* lobs;
+    double* zs;
+    uint64_t* rix;
+    int64_t* rq;
+    int32_t* xs;
+    float* rth;
+};
+
+__device__ __forceinline__ RowLds row_lds(double* base, int T, int R)
+{
+    RowLds l;
+    l.lobs = base;
+    l.zs = base + 3 * T;
+    l.rix = reinterpret_cast<uint64_t*>(l.zs + (size_t)5 * T * R);
+    l.rq = reinterpret_cast<int64_t*>(l.rix + R);
+    l.xs = reinterpret_cast<int32_t*>(l.rq + R);
+    l.rth = reinterpret_cast<float*>(l.xs + (size_t)3 * T * R);
+    return l;
+}
+
+// Pass 1: each wavefront takes R consecutive candidates at a time, R just
+// enough for the grid to cover the candidate count (at most rows_max); the
+// in-band ones among them are simulated side by side in float64
+// (simulate_rows_f64_wave), the others only get their keep flag. Workgroups
+// that meet no in-band row never stage the observed series. Spreading the
+// rows over many wavefronts keeps the time any one SIMD spends on them short:
+// this kernel runs beside the next float32 launch, which it should not hold up.
 template <int NOISE, int DIST>
 __global__ __launch_bounds__(64) void k_recheck_flags(RecheckArgs r)
 {
-    extern __shared__ double lds_r[];  // obs [3 T] | z [5 T] | counts [3 T] int32
+    extern __shared__ double lds_r[];
     const SimArgs& a = r.sim;
     const int64_t count = *r.count;
     if (count > r.capacity) return;  // overflowed candidate set: left for the caller to rerun
     const int T = a.T;
-    double* lobs = lds_r;
-    double* zs = lds_r + 3 * T;
-    int32_t* xs = reinterpret_cast<int32_t*>(zs + 5 * T);
+    const RowLds l = row_lds(lds_r, T, r.rows_max);
+    const int64_t per = (count + gridDim.x - 1) / gridDim.x;
+    const int R = (int)(per < 1 ? 1 : (per > r.rows_max ? r.rows_max : per));
+    const int lane = threadIdx.x;
     bool staged = false;
-    for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
-        const float d = r.dist[q];
-        if (!(d > r.band_lo && d <= r.band_hi)) {
-            if (threadIdx.x == 0) r.keep[q] = d <= r.eps ? 1 : 0;
-            continue;
+    for (int64_t q0 = (int64_t)blockIdx.x * R; q0 < count; q0 += (int64_t)gridDim.x * R) {
+        const int64_t q = q0 + lane;
+        bool inb = false;
+        if (lane < R && q < count) {
+            const float d = r.dist[q];
+            inb = d > r.band_lo && d <= r.band_hi;
+            if (!inb) r.keep[q] = d <= r.eps ? 1 : 0;
         }
+        const uint64_t m = __ballot(inb);
+        const int nr = __popcll(m);
+        if (nr == 0) continue;
         if (!staged) {
-            stage_obs_f64<DIST>(a.obs, T, lobs);
-            __syncthreads();
+            stage_obs_f64<DIST>(a.obs, T, l.lobs);
             staged = true;
         }
-        float thv[8];
+        if (inb) {
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            l.rq[rank] = q;
+            l.rix[rank] = (uint64_t)r.idx[q];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) thv[j] = r.theta[8 * q + j];
-        const double d64 = simulate_row_f64_wave<NOISE, DIST>(
-            thv, (uint64_t)r.idx[q], a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
-            (double)a.scale, lobs, zs, xs);
-        if (threadIdx.x == 0) {
-            r.keep[q] = d64 <= (double)r.eps ? 1 : 0;
-            r.dist[q] = (float)d64;
-            if (r.rechecked) atomicAdd(r.rechecked, 1);
+            for (int j = 0; j < 8; ++j) l.rth[8 * rank + j] = r.theta[8 * q + j];
         }
-        __syncthreads();  // the scratch is reused by the next row
+        __syncthreads();
+        const double d64 = simulate_rows_f64_wave<NOISE, DIST>(
+            nr, l.rth, l.rix, a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
+            (double)a.scale, l.lobs, l.zs, l.xs);
+        if (lane < nr) {
+            const int64_t qq = l.rq[lane];
+            r.keep[qq] = d64 <= (double)r.eps ? 1 : 0;
+            r.dist[qq] = (float)d64;
+        }
+        if (lane == 0 && r.rechecked) atomicAdd(r.rechecked, nr);
+        __syncthreads();  // the scratch is reused by the next rows
     }
 }
 
@@ -517,32 +554,36 @@ __global__ void k_zero_i32(int32_t* p)
 }
 
 
-// float64 distances of listed rows (sample idx[q], theta[q]), one lane each.
+// float64 distances of listed rows (sample idx[q], theta[q]), rows_per_wave
+// consecutive rows at a time per wavefront, walked side by side in lanes.
 struct RowsArgs {
     SimArgs sim;
     const int64_t* idx;
     double* dist64;
+    int32_t rows_per_wave;
 };
 
 template <int NOISE, int DIST>
 __global__ __launch_bounds__(64) void k_rows_f64(RowsArgs r)
 {
-    extern __shared__ double lds_w[];  // obs [3 T] | z [5 T] | counts [3 T] int32
+    extern __shared__ double lds_w[];
     const SimArgs& a = r.sim;
-    const int T = a.T;
-    double* lobs = lds_w;
-    double* zs = lds_w + 3 * T;
-    int32_t* xs = reinterpret_cast<int32_t*>(zs + 5 * T);
-    stage_obs_f64<DIST>(a.obs, T, lobs);
-    __syncthreads();
-    for (int64_t q = blockIdx.x; q < a.n; q += gridDim.x) {
-        float thv[8];
+    const int T = a.T, R = r.rows_per_wave;
+    const RowLds l = row_lds(lds_w, T, R);
+    stage_obs_f64<DIST>(a.obs, T, l.lobs);
+    const int lane = threadIdx.x;
+    for (int64_t q0 = (int64_t)blockIdx.x * R; q0 < a.n; q0 += (int64_t)gridDim.x * R) {
+        const int nr = (int)(a.n - q0 < R ? a.n - q0 : R);
+        if (lane < nr) {
+            l.rix[lane] = (uint64_t)r.idx[q0 + lane];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) thv[j] = a.theta[8 * q + j];
-        const double d64 = simulate_row_f64_wave<NOISE, DIST>(
-            thv, (uint64_t)r.idx[q], a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
-            (double)a.scale, lobs, zs, xs);
-        if (threadIdx.x == 0) r.dist64[q] = d64;
+            for (int j = 0; j < 8; ++j) l.rth[8 * lane + j] = a.theta[8 * (q0 + lane) + j];
+        }
+        __syncthreads();
+        const double d64 = simulate_rows_f64_wave<NOISE, DIST>(
+            nr, l.rth, l.rix, a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
+            (double)a.scale, l.lobs, l.zs, l.xs);
+        if (lane < nr) r.dist64[q0 + lane] = d64;
         __syncthreads();
     }
 }
@@ -620,11 +661,23 @@ static abc_status fill_series(SimArgs& a, const abc_series* ser, const abc_model
     return ABC_OK;
 }
 
-// float64 row kernels: one wavefront per row, rows strided over the grid
+// float64 row kernels: one wavefront per workgroup, up to R rows side by side
+// per wavefront, rows strided over the grid
 constexpr int64_t ROW_WAVE_GRID = 2048;
-static size_t row_wave_lds_bytes(int T)
+constexpr int64_t ROW_WAVE_TARGET = 1024;  // wavefronts that spread rows over all SIMDs
+constexpr size_t ROW_LDS_BUDGET = 20480;   // LDS per row workgroup beyond one row's
+static size_t row_wave_lds_bytes(int T, int R)
 {
-    return (sizeof(double) * 8 + sizeof(int32_t) * 3) * (size_t)T;
+    return sizeof(double) * 3 * (size_t)T +
+           (size_t)R * (sizeof(double) * 5 * (size_t)T + sizeof(uint64_t) + sizeof(int64_t) +
+                        sizeof(int32_t) * 3 * (size_t)T + sizeof(float) * 8);
+}
+// Most rows per wavefront within the LDS budget (at least 1).
+static int row_wave_rows_max(int T)
+{
+    int R = ROWS_PER_WAVE_MAX;
+    while (R > 1 && row_wave_lds_bytes(T, R) > ROW_LDS_BUDGET) --R;
+    return R;
 }
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + SIM_BLOCK - 1) / SIM_BLOCK); }
@@ -898,7 +951,8 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     ABC_REQUIRE(count != nullptr, "count is NULL");
     if (capacity == 0) return ABC_OK;
     ABC_REQUIRE(idx && theta && dist, "idx/theta/dist NULL");
-    const size_t lds = row_wave_lds_bytes(ser->T);
+    const int rows_max = row_wave_rows_max(ser->T);
+    const size_t lds = row_wave_lds_bytes(ser->T, rows_max);
     ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 recheck");
     const hipStream_t s = as_stream(stream);
     RecheckArgs r{};
@@ -913,6 +967,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     r.weight = weight;
     r.count = count;
     r.rechecked = rechecked;
+    r.rows_max = rows_max;
     void* scratch = nullptr;
     ABC_HIP(hipMallocAsync(&scratch, (size_t)capacity, s));
     r.keep = reinterpret_cast<uint8_t*>(scratch);
@@ -946,17 +1001,22 @@ extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_mod
     ABC_REQUIRE(n >= 0, "n < 0");
     if (n == 0) return ABC_OK;
     ABC_REQUIRE(idx && theta && dist64, "idx/theta/dist64 NULL");
-    const size_t lds = row_wave_lds_bytes(ser->T);
+    const int64_t want = (n + ROW_WAVE_TARGET - 1) / ROW_WAVE_TARGET;
+    const int rmax = row_wave_rows_max(ser->T);
+    const int rows = (int)(want < rmax ? want : rmax);
+    const size_t lds = row_wave_lds_bytes(ser->T, rows);
     ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 path");
     RowsArgs r{};
     fill_series(r.sim, ser, model, st, 0, n);
     r.sim.theta = theta;
     r.idx = idx;
     r.dist64 = dist64;
+    r.rows_per_wave = rows;
     const hipStream_t s = as_stream(stream);
     const int noise = (model->flags & ABC_NOISE_LITERAL) ? 1 : 0;
     const int distm = (model->flags & ABC_DIST_RAW) ? 1 : 0;
-    const dim3 g((unsigned)(n < ROW_WAVE_GRID ? n : ROW_WAVE_GRID)), b(64);
+    const int64_t waves = (n + rows - 1) / rows;
+    const dim3 g((unsigned)(waves < ROW_WAVE_GRID ? waves : ROW_WAVE_GRID)), b(64);
     if (noise == 0 && distm == 0) hipLaunchKernelGGL((k_rows_f64<0, 0>), g, b, lds, s, r);
     else if (noise == 0) hipLaunchKernelGGL((k_rows_f64<0, 1>), g, b, lds, s, r);
     else if (distm == 0) hipLaunchKernelGGL((k_rows_f64<1, 0>), g, b, lds, s, r);

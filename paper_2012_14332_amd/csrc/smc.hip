@@ -8,8 +8,8 @@
 //   k_smc_setup     one workgroup: weighted mean and covariance of generation
 //                   t-1 (left-to-right float64 sums), Sigma = 2 cov, its
 //                   Cholesky factor L, running weight sums C_j, whitened
-//                   particles y_j = L^-1 theta_j, and eps_t from an LDS sort of
-//                   the previous distances.
+//                   particles y_j = L^-1 theta_j, and eps_t, the kth smallest
+//                   previous distance, by radix selection.
 //   k_smc_propose   one lane per candidate: ancestor by binary search of
 //                   u C_{N-1} in C, theta* = theta_anc + L z (float64, rounded
 //                   to float32).
@@ -58,160 +58,274 @@ struct SetupArgs {
     double* y;            // [N][8]
 };
 
-// Particles loaded ahead of the ordered adds in the single-lane sums: the
-// order of the additions is unchanged, the loads no longer wait one by one.
+// The single-lane ordered sums read the particles from LDS: all threads copy
+// a chunk of SMC_CHUNK particles (weights, then theta) into the distance
+// array before it holds the distances, and the summing lanes load SMC_PF
+// values ahead of their adds. The order of the additions is that of the
+// plainly written definition.
 constexpr int SMC_PF = 16;
+constexpr int SMC_CHUNK = 1024;  // 8 KiB of weights + 32 KiB of theta
 
-// One workgroup of 1024 threads. Sums run left to right over the particles in
-// single lanes so that every rounding matches the plainly written definition.
-__global__ __launch_bounds__(1024) void k_smc_setup(SetupArgs a)
+__device__ __forceinline__ void smc_stage_chunk(const SetupArgs& a, int c0, int m, double* sw,
+                                                float* sth)
+{
+    // one particle per thread: all nine loads are in flight before any store
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const float* src = a.theta + (int64_t)8 * (c0 + j);
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = src[k];
+        const double wj = a.w[c0 + j];
+        sw[j] = wj;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sth[8 * j + k] = v[k];
+    }
+}
+
+// Keys whose unsigned order is the order of the (non-NaN) doubles.
+__device__ __forceinline__ uint64_t order_key(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+__device__ __forceinline__ double key_value(uint64_t k)
+{
+    const uint64_t b = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+constexpr int SMC_SETUP_THREADS = 1024;
+constexpr int SMC_SEL_PER = SMC_MAX_N / SMC_SETUP_THREADS;
+
+// One workgroup of SMC_SETUP_THREADS threads. Sums run left to right over the
+// particles in single lanes so that every rounding matches the plainly written
+// definition.
+__global__ __launch_bounds__(SMC_SETUP_THREADS) void k_smc_setup(SetupArgs a)
 {
 #pragma clang fp contract(off)
     __shared__ double sd[SMC_MAX_N];
     __shared__ double m_sh[8];
     __shared__ double v_sh;
+    __shared__ double sig_sh[64];
+    __shared__ unsigned long long sel_prefix;
+    __shared__ unsigned int sel_rank;
+    __shared__ double l_sh[64];
+    __shared__ int status_sh;
+    static_assert(SMC_CHUNK * 6 <= SMC_MAX_N, "staging chunk exceeds the distance array");
+    double* sw = sd;
+    float* sth = reinterpret_cast<float*>(sd + SMC_CHUNK);
+    double* sC = sd + 5 * SMC_CHUNK;  // running sums of the chunk, stored coalesced
     const int tid = threadIdx.x;
     const int N = a.N;
     // phase A: running weight sums (lane 64), sums of W theta (lanes 0..7)
-    if (tid == 64) {
-        double s = 0.0;
-        int j = 0;
-        for (; j + SMC_PF <= N; j += SMC_PF) {
-            double wv[SMC_PF];
+    double sc = 0.0, sm = 0.0;
+    for (int c0 = 0; c0 < N; c0 += SMC_CHUNK) {
+        const int m = min(SMC_CHUNK, N - c0);
+        smc_stage_chunk(a, c0, m, sw, sth);
+        __syncthreads();
+        if (tid == 64) {
+            int j = 0;
+            for (; j + SMC_PF <= m; j += SMC_PF) {
+                double wv[SMC_PF];
 #pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) wv[k] = a.w[j + k];
+                for (int k = 0; k < SMC_PF; ++k) wv[k] = sw[j + k];
 #pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) {
-                s = s + wv[k];
-                a.C[j + k] = s;
+                for (int k = 0; k < SMC_PF; ++k) {
+                    sc = sc + wv[k];
+                    sC[j + k] = sc;
+                }
+            }
+            for (; j < m; ++j) {
+                sc = sc + sw[j];
+                sC[j] = sc;
             }
         }
-        for (; j < N; ++j) {
-            s = s + a.w[j];
-            a.C[j] = s;
+        if (tid < 8) {
+            int j = 0;
+            for (; j + SMC_PF <= m; j += SMC_PF) {
+                double wv[SMC_PF];
+                float tv[SMC_PF];
+#pragma unroll
+                for (int k = 0; k < SMC_PF; ++k) {
+                    wv[k] = sw[j + k];
+                    tv[k] = sth[8 * (j + k) + tid];
+                }
+#pragma unroll
+                for (int k = 0; k < SMC_PF; ++k) sm = sm + wv[k] * (double)tv[k];
+            }
+            for (; j < m; ++j) sm = sm + sw[j] * (double)sth[8 * j + tid];
         }
-        v_sh = s;
-        a.st->total = s;
+        __syncthreads();
+        for (int j = tid; j < m; j += blockDim.x) a.C[c0 + j] = sC[j];
     }
-    if (tid < 8) {
-        double s = 0.0;
-        int j = 0;
-        for (; j + SMC_PF <= N; j += SMC_PF) {
-            double wv[SMC_PF];
-            float tv[SMC_PF];
-#pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) {
-                wv[k] = a.w[j + k];
-                tv[k] = a.theta[8 * (j + k) + tid];
-            }
-#pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) s = s + wv[k] * (double)tv[k];
-        }
-        for (; j < N; ++j) s = s + a.w[j] * (double)a.theta[8 * j + tid];
-        m_sh[tid] = s;
+    if (tid == 64) {
+        v_sh = sc;
+        a.st->total = sc;
     }
     __syncthreads();
     if (tid < 8) {
-        m_sh[tid] = m_sh[tid] / v_sh;
+        m_sh[tid] = sm / v_sh;
         a.st->mean[tid] = m_sh[tid];
     }
     __syncthreads();
     // phase B: covariance entries (a >= b), one lane each
+    int r = 0, c = 0;
+    double mr = 0.0, mc = 0.0, sv = 0.0;
     if (tid < 36) {
-        int r = 0;
         while ((r + 1) * (r + 2) / 2 <= tid) ++r;
-        const int c = tid - r * (r + 1) / 2;
-        const double mr = m_sh[r], mc = m_sh[c];
-        double s = 0.0;
-        int j = 0;
-        for (; j + SMC_PF <= N; j += SMC_PF) {
-            double wv[SMC_PF];
-            float tr[SMC_PF], tc[SMC_PF];
-#pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) {
-                wv[k] = a.w[j + k];
-                tr[k] = a.theta[8 * (j + k) + r];
-                tc[k] = a.theta[8 * (j + k) + c];
-            }
-#pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) {
-                const double dr = (double)tr[k] - mr;
-                const double dc = (double)tc[k] - mc;
-                s = s + wv[k] * (dr * dc);
-            }
-        }
-        for (; j < N; ++j) {
-            const double dr = (double)a.theta[8 * j + r] - mr;
-            const double dc = (double)a.theta[8 * j + c] - mc;
-            s = s + a.w[j] * (dr * dc);
-        }
-        const double sg = 2.0 * (s / v_sh);
-        a.st->sigma[8 * r + c] = sg;
-        a.st->sigma[8 * c + r] = sg;
+        c = tid - r * (r + 1) / 2;
+        mr = m_sh[r];
+        mc = m_sh[c];
     }
-    // previous distances into LDS, padded with +inf to a power of two
-    int npow = 1;
-    while (npow < N) npow <<= 1;
-    for (int j = tid; j < npow; j += blockDim.x) sd[j] = j < N ? a.dist[j] : (double)INFINITY;
-    __syncthreads();
-    // phase C: Cholesky-Banachiewicz, row by row (lane 0)
-    if (tid == 0) {
-        double L[64];
-        int bad = 0;
-        for (int i = 0; i < 64; ++i) L[i] = 0.0;
-        for (int i = 0; i < 8 && !bad; ++i)
-            for (int j = 0; j <= i; ++j) {
-                double s = a.st->sigma[8 * i + j];
-                for (int k = 0; k < j; ++k) s = s - L[8 * i + k] * L[8 * j + k];
-                if (i == j) {
-                    if (!(s > 0.0)) {
-                        bad = 1;
-                        break;
-                    }
-                    L[8 * i + i] = sqrt(s);
-                } else {
-                    L[8 * i + j] = s / L[8 * j + j];
+    for (int c0 = 0; c0 < N; c0 += SMC_CHUNK) {
+        const int m = min(SMC_CHUNK, N - c0);
+        smc_stage_chunk(a, c0, m, sw, sth);
+        __syncthreads();
+        if (tid < 36) {
+            int j = 0;
+            for (; j + SMC_PF <= m; j += SMC_PF) {
+                double wv[SMC_PF];
+                float tr[SMC_PF], tc[SMC_PF];
+#pragma unroll
+                for (int k = 0; k < SMC_PF; ++k) {
+                    wv[k] = sw[j + k];
+                    tr[k] = sth[8 * (j + k) + r];
+                    tc[k] = sth[8 * (j + k) + c];
+                }
+#pragma unroll
+                for (int k = 0; k < SMC_PF; ++k) {
+                    const double dr = (double)tr[k] - mr;
+                    const double dc = (double)tc[k] - mc;
+                    sv = sv + wv[k] * (dr * dc);
                 }
             }
-        for (int i = 0; i < 64; ++i) a.st->L[i] = L[i];
-        a.st->status = bad;
+            for (; j < m; ++j) {
+                const double dr = (double)sth[8 * j + r] - mr;
+                const double dc = (double)sth[8 * j + c] - mc;
+                sv = sv + sw[j] * (dr * dc);
+            }
+        }
+        __syncthreads();  // the chunk is replaced next
     }
-    // phase D: bitonic sort of the distances (ascending)
-    for (int k = 2; k <= npow; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = tid; t < npow; t += blockDim.x) {
-                const int p = t ^ j;
-                if (p > t) {
-                    const bool up = (t & k) == 0;
-                    const double x = sd[t], yv = sd[p];
-                    if ((x > yv) == up) {
-                        sd[t] = yv;
-                        sd[p] = x;
+    if (tid < 36) {
+        const double sg = 2.0 * (sv / v_sh);
+        a.st->sigma[8 * r + c] = sg;
+        a.st->sigma[8 * c + r] = sg;
+        sig_sh[8 * r + c] = sg;
+    }
+    // previous distances as order-preserving 64-bit keys, SMC_SEL_PER per thread
+    uint64_t key[SMC_SEL_PER];
+#pragma unroll
+    for (int e = 0; e < SMC_SEL_PER; ++e) {
+        const int j = tid + e * SMC_SETUP_THREADS;
+        key[e] = j < N ? order_key(a.dist[j]) : 0ull;
+    }
+    __syncthreads();
+    // phase C: Cholesky-Banachiewicz, row by row (lane 0). Fully unrolled so
+    // that L stays in registers; nothing is assigned after the first
+    // non-positive pivot, which sets the status.
+    if (tid == 0) {
+        double L[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) L[i] = 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                double s = sig_sh[8 * i + j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) s = s - L[8 * i + k] * L[8 * j + k];
+                if (!bad) {
+                    if (i == j) {
+                        if (!(s > 0.0))
+                            bad = 1;
+                        else
+                            L[8 * i + i] = sqrt(s);
+                    } else {
+                        L[8 * i + j] = s / L[8 * j + j];
                     }
+                }
+            }
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            a.st->L[i] = L[i];
+            l_sh[i] = L[i];
+        }
+        a.st->status = bad;
+        status_sh = bad;
+    }
+    // phase D: eps_t is the kth smallest previous distance: radix selection
+    // over the keys, 8 bits per pass from the most significant, with one
+    // histogram per wavefront in LDS (the distance array is free by now).
+    {
+        unsigned int* hist = reinterpret_cast<unsigned int*>(sd);  // [16][256]
+        uint64_t prefix = 0;
+        unsigned int rank = (unsigned int)a.kth;  // 1-based, among keys matching prefix
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            for (int b = tid; b < 16 * 256; b += SMC_SETUP_THREADS) hist[b] = 0u;
+            __syncthreads();
+            const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+            unsigned int* hw = hist + 256 * (tid >> 6);
+#pragma unroll
+            for (int e = 0; e < SMC_SEL_PER; ++e) {
+                const int j = tid + e * SMC_SETUP_THREADS;
+                if (j < N && (key[e] & hmask) == prefix)
+                    atomicAdd(&hw[(unsigned)(key[e] >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                unsigned int c[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned int t = 0;
+                    for (int w = 0; w < 16; ++w) t += hist[256 * w + 4 * tid + q];
+                    c[q] = t;
+                }
+                const unsigned int tot = c[0] + c[1] + c[2] + c[3];
+                unsigned int incl = tot;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const unsigned int v = __shfl_up(incl, o, 64);
+                    if (tid >= o) incl += v;
+                }
+                const unsigned int excl = incl - tot;
+                if (excl < rank && rank <= incl) {
+                    unsigned int run = excl;
+                    int q = 0;
+                    while (q < 3 && run + c[q] < rank) run += c[q++];
+                    sel_prefix = prefix | ((uint64_t)(4 * tid + q) << shift);
+                    sel_rank = rank - run;
                 }
             }
             __syncthreads();
+            prefix = sel_prefix;
+            rank = sel_rank;
         }
-    if (tid == 0) {
-        const double q = sd[a.kth - 1];
-        a.st->eps64 = q;
-        const double f = (double)a.eps_min;
-        a.st->eps = (float)(q > f ? q : f);
+        if (tid == 0) {
+            const double q = key_value(prefix);
+            a.st->eps64 = q;
+            const double f = (double)a.eps_min;
+            a.st->eps = (float)(q > f ? q : f);
+        }
     }
     __syncthreads();
     // phase E: whitened particles y_j = L^-1 theta_j (forward substitution)
-    if (a.st->status == 0) {
-        double L[36];
-        for (int i = 0, q = 0; i < 8; ++i)
-            for (int j = 0; j <= i; ++j) L[q++] = a.st->L[8 * i + j];
+    if (status_sh == 0) {
+        double L[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) L[i] = l_sh[i];
         for (int j = tid; j < N; j += blockDim.x) {
             double yv[8];
-            for (int r = 0, q = 0; r < 8; ++r) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
                 double s = (double)a.theta[8 * j + r];
-                for (int k = 0; k < r; ++k) s = s - L[q + k] * yv[k];
-                yv[r] = s / L[q + r];
-                q += r + 1;
+#pragma unroll
+                for (int k = 0; k < r; ++k) s = s - L[8 * r + k] * yv[k];
+                yv[r] = s / L[8 * r + r];
             }
+#pragma unroll
             for (int r = 0; r < 8; ++r) a.y[8 * j + r] = yv[r];
         }
     }
@@ -284,21 +398,33 @@ __global__ void k_smc_zero_u64(unsigned long long* p)
 }
 
 // Number of rows of theta [m][8] inside the closed box (added to *count).
+// Candidates inside the prior box: grid-stride count, one atomic per workgroup.
+constexpr int BOX_GRID = 1024;
+
 __global__ __launch_bounds__(256) void k_smc_count_box(const float* theta, int64_t m, abc_prior box,
                                                        unsigned long long* count)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool in = false;
-    if (k < m) {
-        in = true;
+    __shared__ unsigned int part[4];
+    unsigned int c = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const float4* p = reinterpret_cast<const float4*>(theta + 8 * k);
+        const float4 u = p[0], v = p[1];
+        const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+        bool in = true;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float x = theta[8 * k + j];
-            in &= x >= box.lo[j] && x <= box.hi[j];
-        }
+        for (int j = 0; j < 8; ++j) in &= x[j] >= box.lo[j] && x[j] <= box.hi[j];
+        c += in ? 1u : 0u;
     }
-    const uint64_t bal = __ballot(in);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(count, (unsigned long long)__popcll(bal));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        if (t) atomicAdd(count, t);
+    }
 }
 
 // ancestors of the kept candidate rows (row r is candidate oidx[r] - first of the chunk)
@@ -365,16 +491,18 @@ __global__ __launch_bounds__(SUMS_BLOCK) void k_smc_sums(SumsArgs a)
 }
 
 // w_i = 1 / sum_s partial[s][i]; W = w / (w_0 + ... + w_{N-1}); ESS = 1 / sum W^2.
+// The w_i stay in LDS for the single-lane left-to-right sum.
 __global__ __launch_bounds__(1024) void k_smc_finish(const double* partial, int32_t splits,
                                                      int32_t N, double* W, double* ess)
 {
 #pragma clang fp contract(off)
     __shared__ double v_sh;
-    __shared__ double red[1024];
+    __shared__ double wl[SMC_MAX_N];
+    static_assert(SMC_MAX_N >= 1024, "the reduction reuses the weight array");
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         double s = 0.0;
         for (int sp = 0; sp < splits; ++sp) s = s + partial[(int64_t)sp * N + i];
-        W[i] = 1.0 / s;
+        wl[i] = 1.0 / s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -383,20 +511,22 @@ __global__ __launch_bounds__(1024) void k_smc_finish(const double* partial, int3
         for (; i + SMC_PF <= N; i += SMC_PF) {
             double v[SMC_PF];
 #pragma unroll
-            for (int k = 0; k < SMC_PF; ++k) v[k] = W[i + k];
+            for (int k = 0; k < SMC_PF; ++k) v[k] = wl[i + k];
 #pragma unroll
             for (int k = 0; k < SMC_PF; ++k) s = s + v[k];
         }
-        for (; i < N; ++i) s = s + W[i];
+        for (; i < N; ++i) s = s + wl[i];
         v_sh = s;
     }
     __syncthreads();
     double q = 0.0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const double x = W[i] / v_sh;
+        const double x = wl[i] / v_sh;
         W[i] = x;
         q = q + x * x;
     }
+    __syncthreads();  // every wl[i] has been read before the reduction reuses it
+    double* red = wl;
     red[threadIdx.x] = q;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -531,7 +661,7 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
         sa.st = dstate;
         sa.C = dC;
         sa.y = dy;
-        hipLaunchKernelGGL(k_smc_setup, dim3(1), dim3(1024), 0, s, sa);
+        hipLaunchKernelGGL(k_smc_setup, dim3(1), dim3(SMC_SETUP_THREADS), 0, s, sa);
         if ((rc = check_launch("k_smc_setup"))) return rc;
         struct {
             float eps;
@@ -604,8 +734,9 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
             used = samples - first;
         }
         if (gen > 0) {
-            hipLaunchKernelGGL(k_smc_count_box, dim3((unsigned)((used + 255) / 256)), dim3(256), 0, s,
-                               cth, used, *prior, dbox);
+            const int64_t bb = (used + 255) / 256;
+            hipLaunchKernelGGL(k_smc_count_box, dim3((unsigned)(bb < BOX_GRID ? bb : BOX_GRID)),
+                               dim3(256), 0, s, cth, used, *prior, dbox);
             if ((rc = check_launch("k_smc_count_box"))) return rc;
         }
         got += take;

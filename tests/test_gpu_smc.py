@@ -111,6 +111,23 @@ def test_small_populations_and_extreme_quantiles(env, N, alpha):
         _compare(out, gens[t], "gen%d" % t)
 
 
+@pytest.mark.parametrize("alpha", [0.5, 0.37, 1.0])
+def test_tolerance_quantile_with_ties(env, alpha):
+    """eps_t is the ceil(alpha N)-th smallest previous distance also when many
+    previous distances are equal (rounded to one decimal) and some are zero."""
+    abc, s, m, obs, eps0, ser = env
+    g = osmc.smc_abc(m, obs, seed=6, N=256, generations=1, alpha=0.5, eps0=eps0)[0]
+    d = np.round(g.dist, 1)
+    d[[3, 77, 200]] = 0.0
+    assert len(np.unique(d)) < d.size // 2
+    cfg = abc.smc_config(256, eps0, alpha=alpha, chunk0=1 << 14, chunk_max=1 << 16)
+    prev = (torch.from_numpy(np.ascontiguousarray(g.theta)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(g.W)).cuda(),
+            torch.from_numpy(d).cuda())
+    out = abc.smc_generation(ser, cfg, 6, 1, prev)
+    assert out["stats"]["eps"] == np.float32(osmc.quantile_eps(d, alpha, 0.0))
+
+
 def test_full_run_matches_oracle(env):
     abc, s, m, obs, eps0, ser = env
     gens = osmc.smc_abc(m, obs, seed=8, N=200, generations=5, alpha=0.5, eps0=eps0)
