@@ -13,6 +13,19 @@ namespace abc {
 
 abc_status set_error(abc_status st, const char* fmt, ...);
 
+// LDS budget of a float64 row workgroup (several rows side by side per
+// wavefront): small where the rows run beside a float32 launch, so that they
+// do not crowd its workgroups out of the CU (the plain band decision), larger
+// where they run alone (the SMC band decision, float64 row distances).
+constexpr size_t ROW_LDS_BESIDE = 8192;
+constexpr size_t ROW_LDS_ALONE = 20480;
+
+// abc_recheck_band with a chosen LDS budget per row workgroup.
+abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
+                        float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
+                        float* dist, float* weight, int64_t* count, int32_t* rechecked,
+                        void* stream, size_t lds_budget);
+
 #define ABC_REQUIRE(cond, ...)                                 \
     do {                                                       \
         if (!(cond)) return ::abc::set_error(ABC_EINVAL, __VA_ARGS__); \

@@ -665,18 +665,17 @@ static abc_status fill_series(SimArgs& a, const abc_series* ser, const abc_model
 // per wavefront, rows strided over the grid
 constexpr int64_t ROW_WAVE_GRID = 2048;
 constexpr int64_t ROW_WAVE_TARGET = 1024;  // wavefronts that spread rows over all SIMDs
-constexpr size_t ROW_LDS_BUDGET = 20480;   // LDS per row workgroup beyond one row's
 static size_t row_wave_lds_bytes(int T, int R)
 {
     return sizeof(double) * 3 * (size_t)T +
            (size_t)R * (sizeof(double) * 5 * (size_t)T + sizeof(uint64_t) + sizeof(int64_t) +
                         sizeof(int32_t) * 3 * (size_t)T + sizeof(float) * 8);
 }
-// Most rows per wavefront within the LDS budget (at least 1).
-static int row_wave_rows_max(int T)
+// Most rows per wavefront within an LDS budget (at least 1).
+static int row_wave_rows_max(int T, size_t budget)
 {
     int R = ROWS_PER_WAVE_MAX;
-    while (R > 1 && row_wave_lds_bytes(T, R) > ROW_LDS_BUDGET) --R;
+    while (R > 1 && row_wave_lds_bytes(T, R) > budget) --R;
     return R;
 }
 
@@ -935,11 +934,11 @@ extern "C" abc_status abc_get_launch_config(int32_t* spl, int32_t* block, int32_
     return ABC_OK;
 }
 
-extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* model,
-                                       const abc_stream* st, float eps, float band_w,
-                                       int64_t capacity, int64_t* idx, float* theta, float* dist,
-                                       float* weight, int64_t* count, int32_t* rechecked,
-                                       void* stream)
+namespace abc {
+abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
+                        float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
+                        float* dist, float* weight, int64_t* count, int32_t* rechecked,
+                        void* stream, size_t lds_budget)
 {
     abc_status rc;
     if ((rc = check_series(ser, true))) return rc;
@@ -951,7 +950,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     ABC_REQUIRE(count != nullptr, "count is NULL");
     if (capacity == 0) return ABC_OK;
     ABC_REQUIRE(idx && theta && dist, "idx/theta/dist NULL");
-    const int rows_max = row_wave_rows_max(ser->T);
+    const int rows_max = row_wave_rows_max(ser->T, lds_budget);
     const size_t lds = row_wave_lds_bytes(ser->T, rows_max);
     ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 recheck");
     const hipStream_t s = as_stream(stream);
@@ -988,6 +987,17 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
     if (rc == ABC_OK && e != hipSuccess) return set_error(ABC_EHIP, "hipFreeAsync: %s", hipGetErrorString(e));
     return rc;
 }
+}  // namespace abc
+
+extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* model,
+                                       const abc_stream* st, float eps, float band_w,
+                                       int64_t capacity, int64_t* idx, float* theta, float* dist,
+                                       float* weight, int64_t* count, int32_t* rechecked,
+                                       void* stream)
+{
+    return recheck_band(ser, model, st, eps, band_w, capacity, idx, theta, dist, weight, count,
+                        rechecked, stream, ROW_LDS_BESIDE);
+}
 
 extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model* model,
                                             const abc_stream* st, const int64_t* idx,
@@ -1002,7 +1012,7 @@ extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_mod
     if (n == 0) return ABC_OK;
     ABC_REQUIRE(idx && theta && dist64, "idx/theta/dist64 NULL");
     const int64_t want = (n + ROW_WAVE_TARGET - 1) / ROW_WAVE_TARGET;
-    const int rmax = row_wave_rows_max(ser->T);
+    const int rmax = row_wave_rows_max(ser->T, ROW_LDS_ALONE);
     const int rows = (int)(want < rmax ? want : rmax);
     const size_t lds = row_wave_lds_bytes(ser->T, rows);
     ABC_REQUIRE(lds <= max_lds_per_block(), "T too long for the float64 path");

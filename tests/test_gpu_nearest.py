@@ -117,6 +117,23 @@ def test_simulate_rows_f64_matches_oracle(A):
         assert abs(d[q] - ref) <= 1e-12 * ref
 
 
+@pytest.mark.parametrize("country,n", [(0, 1), (0, 63), (0, 3 * 1024 + 17), (0, 9000), (2, 5000)])
+def test_simulate_rows_f64_side_by_side_rows(A, country, n):
+    """Several rows per wavefront (n above 1024 rows), ragged last blocks: the
+    same doubles as the one-lane-per-sample float64 simulation of the same
+    samples and parameters."""
+    s = W.three_countries()[country]
+    m = oracle.make_model(s.P, s.T)
+    obs = oracle.observe(m, s.theta_true, s.obs_seed)
+    ser = A.DeviceSeries(s.P, s.T, torch.from_numpy(obs))
+    first = 1 << 20
+    th = A.sample_prior(n, 4, first=first)
+    idx = torch.arange(first, first + n, dtype=torch.int64, device="cuda")
+    d = A.simulate_rows_f64(ser, 4, idx, th).cpu().numpy()
+    _, d64 = A.simulate_distance(ser, n, 4, theta=th, first=first, flags=A.ABC_FP64, want64=True)
+    np.testing.assert_array_equal(d, d64.cpu().numpy())
+
+
 def test_single_country_nearest_100_of_1e5(A):
     """The single-country workload end to end against the oracle's rule."""
     from paper_2012_14332_amd import pipeline as P
