@@ -19,12 +19,16 @@ abc_status set_error(abc_status st, const char* fmt, ...);
 // where they run alone (the SMC band decision, float64 row distances).
 constexpr size_t ROW_LDS_BESIDE = 8192;
 constexpr size_t ROW_LDS_ALONE = 20480;
+// Float64 row wavefronts that spread rows over all SIMDs (one per SIMD) when
+// the row kernel runs alone; beside a float32 launch the band decision
+// spreads over up to twice as many.
+constexpr int64_t ROW_WAVE_TARGET = 1024;
 
-// abc_recheck_band with a chosen LDS budget per row workgroup.
+// abc_recheck_band with a chosen LDS budget per row workgroup and grid cap.
 abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
                         float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
                         float* dist, float* weight, int64_t* count, int32_t* rechecked,
-                        void* stream, size_t lds_budget);
+                        void* stream, size_t lds_budget, int64_t grid_max);
 
 #define ABC_REQUIRE(cond, ...)                                 \
     do {                                                       \

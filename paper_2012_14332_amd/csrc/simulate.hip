@@ -664,7 +664,6 @@ static abc_status fill_series(SimArgs& a, const abc_series* ser, const abc_model
 // float64 row kernels: one wavefront per workgroup, up to R rows side by side
 // per wavefront, rows strided over the grid
 constexpr int64_t ROW_WAVE_GRID = 2048;
-constexpr int64_t ROW_WAVE_TARGET = 1024;  // wavefronts that spread rows over all SIMDs
 static size_t row_wave_lds_bytes(int T, int R)
 {
     return sizeof(double) * 3 * (size_t)T +
@@ -938,7 +937,7 @@ namespace abc {
 abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
                         float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
                         float* dist, float* weight, int64_t* count, int32_t* rechecked,
-                        void* stream, size_t lds_budget)
+                        void* stream, size_t lds_budget, int64_t grid_max)
 {
     abc_status rc;
     if ((rc = check_series(ser, true))) return rc;
@@ -973,7 +972,7 @@ abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc
     const int noise = (model->flags & ABC_NOISE_LITERAL) ? 1 : 0;
     const int distm = (model->flags & ABC_DIST_RAW) ? 1 : 0;
     if (rechecked) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, rechecked);
-    const dim3 g((unsigned)(capacity < ROW_WAVE_GRID ? capacity : ROW_WAVE_GRID)), b(64);
+    const dim3 g((unsigned)(capacity < grid_max ? capacity : grid_max)), b(64);
     if (noise == 0 && distm == 0) hipLaunchKernelGGL((k_recheck_flags<0, 0>), g, b, lds, s, r);
     else if (noise == 0) hipLaunchKernelGGL((k_recheck_flags<0, 1>), g, b, lds, s, r);
     else if (distm == 0) hipLaunchKernelGGL((k_recheck_flags<1, 0>), g, b, lds, s, r);
@@ -996,7 +995,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
                                        void* stream)
 {
     return recheck_band(ser, model, st, eps, band_w, capacity, idx, theta, dist, weight, count,
-                        rechecked, stream, ROW_LDS_BESIDE);
+                        rechecked, stream, ROW_LDS_BESIDE, ROW_WAVE_GRID);
 }
 
 extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model* model,
