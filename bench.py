@@ -511,10 +511,11 @@ def main():
             enumerate(zip(sers, eps))]
     # stream A simulates back to back; stream B compacts each country's
     # distances as soon as its launch ends (HBM-bound, it overlaps the next
-    # launch); stream C makes the float64 band decision and the moments
+    # launch); one stream C per country makes its float64 band decision and
+    # moments, so that the countries' band decisions overlap one another
     sA = torch.cuda.current_stream()
     sB = torch.cuda.Stream()
-    sC = torch.cuda.Stream()
+    sCs = [torch.cuda.Stream() for _ in runs]
     days = torch.zeros(1, dtype=torch.int64, device="cuda")
     compacted = [None] * len(runs)  # last compaction of each country's distance buffer
 
@@ -541,6 +542,7 @@ def main():
                                                         seed=r.seed, series=c)
                 compacted[c] = torch.cuda.Event()
                 compacted[c].record(sB)
+            sC = sCs[c]
             with torch.cuda.stream(sC):
                 sC.wait_event(compacted[c])
                 abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)

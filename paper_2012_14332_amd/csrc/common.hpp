@@ -24,11 +24,20 @@ constexpr size_t ROW_LDS_ALONE = 20480;
 // spreads over up to twice as many.
 constexpr int64_t ROW_WAVE_TARGET = 1024;
 
-// abc_recheck_band with a chosen LDS budget per row workgroup and grid cap.
+// Candidates a band-decision wavefront scans at least: beside a float32
+// launch a few in-band rows (about a quarter of the candidates) share a
+// wavefront; larger blocks (16, 32) slowed the float32 launches beside them
+// (packed wavefronts live longer); alone the rows are spread for the
+// shortest latency.
+constexpr int32_t ROW_SCAN_BESIDE = 8;
+constexpr int32_t ROW_SCAN_ALONE = 1;
+
+// abc_recheck_band with a chosen LDS budget per row workgroup, grid cap and
+// candidates per wavefront.
 abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
                         float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
                         float* dist, float* weight, int64_t* count, int32_t* rechecked,
-                        void* stream, size_t lds_budget, int64_t grid_max);
+                        void* stream, size_t lds_budget, int64_t grid_max, int32_t scan_min);
 
 #define ABC_REQUIRE(cond, ...)                                 \
     do {                                                       \

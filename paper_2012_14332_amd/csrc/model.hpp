@@ -279,73 +279,128 @@ __device__ inline double simulate_one_f64(const float thv[8], uint64_t i, Key ke
 }
 
 // Up to ROWS_PER_WAVE_MAX float64 trajectories run by one wavefront (one
-// wavefront per workgroup): the lanes draw the normals of every (row, day)
-// pair in parallel, lane r walks row r through the days, the lanes form the
-// squared distance terms in parallel, and lane r adds its row's terms in day
-// order (the order of simulate_one_f64, so each result is the same double).
+// wavefront per workgroup), ROW_WINDOW days at a time: the lanes draw the
+// normals of every (row, day) pair of the window in parallel, lane r walks
+// row r through the window's days, the lanes form the window's squared
+// distance terms in parallel, and lane r adds its row's terms in day order
+// (the order of simulate_one_f64, so each result is the same double).
 // A float64 instruction occupies the SIMD for the same cycles whatever its
 // lane mask, so rows walked side by side in lanes cost no more than one.
+// Each row's counts and running sum stay in LDS between the phases, so no
+// phase holds another's registers.
 // Rows r < nr: theta rth[8 r .. 8 r + 7] and sample index rix[r], in LDS.
-// Scratch in LDS: zs [nr][5 T] doubles, xs [nr][3 T] int32. Returns row r's
+// Scratch in LDS: zs [nr][5 ROW_WINDOW] doubles (normals, then the distance
+// terms), xs [nr][3 ROW_WINDOW] int32, rw [nr] walk states. Returns row r's
 // distance on lane r < nr (other lanes return 0).
 constexpr int ROWS_PER_WAVE_MAX = 8;
+constexpr int ROW_WINDOW = 8;
+
+struct RowWalk {
+    State s;
+    int32_t pad[2];
+    double acc;
+};
+
+// The three phases of a window are separate functions: each keeps its own
+// constants and temporaries, so the kernel needs the registers of the largest
+// phase rather than of all three.
+__device__ __attribute__((noinline)) void rows_window_normals(int nr, int nd, int t0,
+                                                              const uint64_t* rix, Key key,
+                                                              uint32_t series, uint32_t domain,
+                                                              double* zs)
+{
+    constexpr int ZW = 5 * ROW_WINDOW;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int p = lane; p < nr * nd; p += 64) {
+        const int r = p / nd, u = p - r * nd;
+        const uint4 w = stream_words(key, rix[r], series, ctr_word3((uint32_t)(t0 + u), domain, 0));
+        double z[5];
+        normals_f64(w, z);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) zs[r * ZW + 5 * u + k] = z[k];
+    }
+}
+
+template <int NOISE>
+__device__ __attribute__((noinline)) void rows_window_walk(const float* th8, State* sp,
+                                                           const double* zr, int32_t* xr, int nd,
+                                                           int32_t P, double scale)
+{
+#pragma clang fp contract(off)
+    float thv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) thv[k] = th8[k];
+    const Theta th = theta_from(thv);
+    State s = *sp;
+#pragma unroll 1
+    for (int u = 0; u < nd; ++u) {
+        double z[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) z[k] = zr[5 * u + k];
+        day_step_f64<NOISE>(s, th, (double)P, scale, z);
+        xr[3 * u + 0] = s.A;
+        xr[3 * u + 1] = s.R;
+        xr[3 * u + 2] = s.D;
+    }
+    *sp = s;
+}
+
+template <int DIST>
+__device__ __attribute__((noinline)) void rows_window_terms(int nr, int nd, int t0, int T,
+                                                            const int32_t* xs, const double* lobs,
+                                                            double* zs)
+{
+#pragma clang fp contract(off)
+    constexpr int ZW = 5 * ROW_WINDOW, XW = 3 * ROW_WINDOW;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int p = lane; p < nr * 3 * nd; p += 64) {
+        const int r = p / (3 * nd), q = p - r * 3 * nd;
+        const int u = q / 3, c = q - 3 * u;
+        const int t = t0 - 1 + u;  // 0-based day
+        double d;
+        if (DIST == 0)
+            d = log1p((double)xs[r * XW + q]) - lobs[c * T + t];
+        else
+            d = (double)xs[r * XW + q] - lobs[c * T + t];
+        zs[r * ZW + q] = d * d;
+    }
+}
 
 template <int NOISE, int DIST>
 __device__ double simulate_rows_f64_wave(int nr, const float* rth, const uint64_t* rix, Key key,
                                          uint32_t series, uint32_t domain, int32_t P, int32_t A0,
                                          int32_t R0, int32_t D0, int T, double scale,
-                                         const double* lobs, double* zs, int32_t* xs)
+                                         const double* lobs, double* zs, int32_t* xs, RowWalk* rw)
 {
 #pragma clang fp contract(off)
+    constexpr int ZW = 5 * ROW_WINDOW, XW = 3 * ROW_WINDOW;
     const int lane = threadIdx.x & 63;
-    const int ZT = 5 * T, XT = 3 * T;
-    for (int p = lane; p < nr * T; p += 64) {
-        const int r = p / T, t = p - r * T + 1;
-        const uint4 w = stream_words(key, rix[r], series, ctr_word3((uint32_t)t, domain, 0));
-        double z[5];
-        normals_f64(w, z);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) zs[r * ZT + 5 * (t - 1) + k] = z[k];
+    const bool walker = lane < nr;
+    if (walker) {
+        rw[lane].s = init_state(rth[8 * lane + 7], P, A0, R0, D0);
+        rw[lane].acc = 0.0;
     }
-    __syncthreads();
-    if (lane < nr) {
-        float thv[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) thv[k] = rth[8 * lane + k];
-        const Theta th = theta_from(thv);
-        State s = init_state(th.ka, P, A0, R0, D0);
-        const double Pd = (double)P;
-        const double* zr = zs + lane * ZT;
-        int32_t* xr = xs + lane * XT;
-        for (int t = 1; t <= T; ++t) {
-            double z[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) z[k] = zr[5 * (t - 1) + k];
-            day_step_f64<NOISE>(s, th, Pd, scale, z);
-            xr[3 * (t - 1) + 0] = s.A;
-            xr[3 * (t - 1) + 1] = s.R;
-            xr[3 * (t - 1) + 2] = s.D;
+    for (int t0 = 1; t0 <= T; t0 += ROW_WINDOW) {
+        const int nd = T - t0 + 1 < ROW_WINDOW ? T - t0 + 1 : ROW_WINDOW;
+        rows_window_normals(nr, nd, t0, rix, key, series, domain, zs);
+        __syncthreads();
+        if (walker)
+            rows_window_walk<NOISE>(rth + 8 * lane, &rw[lane].s, zs + lane * ZW, xs + lane * XW, nd,
+                                    P, scale);
+        __syncthreads();
+        rows_window_terms<DIST>(nr, nd, t0, T, xs, lobs, zs);
+        __syncthreads();
+        if (walker) {
+            const double* tr = zs + lane * ZW;
+            double acc = rw[lane].acc;
+            for (int q = 0; q < 3 * nd; ++q) acc += tr[q];
+            rw[lane].acc = acc;
         }
+        __syncthreads();  // the window's scratch is reused by the next one
     }
-    __syncthreads();
-    for (int p = lane; p < nr * XT; p += 64) {
-        const int r = p / XT, q = p - r * XT;
-        const int t = q / 3, c = q - 3 * t;
-        double d;
-        if (DIST == 0)
-            d = log1p((double)xs[r * XT + q]) - lobs[c * T + t];
-        else
-            d = (double)xs[r * XT + q] - lobs[c * T + t];
-        zs[r * ZT + q] = d * d;
-    }
-    __syncthreads();
-    double acc = 0.0;
-    if (lane < nr) {
-        const double* tr = zs + lane * ZT;
-        for (int q = 0; q < XT; ++q) acc += tr[q];
-        acc = sqrt(acc);
-    }
-    return acc;
+    return walker ? sqrt(rw[lane].acc) : 0.0;
 }
 
 }  // namespace abc

@@ -420,15 +420,17 @@ struct RecheckArgs {
     uint8_t* keep;   // scratch [capacity]
     int32_t* rechecked;  // nullable: number of rows simulated in float64
     int32_t rows_max;    // rows per wavefront the LDS was sized for
+    int32_t scan_min;    // candidates per wavefront at least
 };
 
-// LDS of the float64 row kernels, for up to R rows per wavefront:
-// obs [3 T] f64 | zs [R][5 T] f64 | rix [R] u64 | rq [R] i64 | xs [R][3 T] i32 | rth [R][8] f32
+// LDS of the float64 row kernels, for up to R rows per wavefront (W = ROW_WINDOW days):
+// obs [3 T] f64 | zs [R][5 W] f64 | rix [R] u64 | rq [R] i64 | rw [R] | xs [R][3 W] i32 | rth [R][8] f32
 struct RowLds {
     double* lobs;
     double* zs;
     uint64_t* rix;
     int64_t* rq;
+    RowWalk* rw;
     int32_t* xs;
     float* rth;
 };
@@ -438,67 +440,94 @@ __device__ __forceinline__ RowLds row_lds(double* base, int T, int R)
     RowLds l;
     l.lobs = base;
     l.zs = base + 3 * T;
-    l.rix = reinterpret_cast<uint64_t*>(l.zs + (size_t)5 * T * R);
+    l.rix = reinterpret_cast<uint64_t*>(l.zs + (size_t)5 * ROW_WINDOW * R);
     l.rq = reinterpret_cast<int64_t*>(l.rix + R);
-    l.xs = reinterpret_cast<int32_t*>(l.rq + R);
-    l.rth = reinterpret_cast<float*>(l.xs + (size_t)3 * T * R);
+    l.rw = reinterpret_cast<RowWalk*>(l.rq + R);
+    l.xs = reinterpret_cast<int32_t*>(l.rw + R);
+    l.rth = reinterpret_cast<float*>(l.xs + (size_t)3 * ROW_WINDOW * R);
     return l;
 }
 
-// Pass 1: each wavefront takes R consecutive candidates at a time, R just
-// enough for the grid to cover the candidate count (at most rows_max); the
-// in-band ones among them are simulated side by side in float64
-// (simulate_rows_f64_wave), the others only get their keep flag. Workgroups
-// that meet no in-band row never stage the observed series. Spreading the
-// rows over many wavefronts keeps the time any one SIMD spends on them short:
-// this kernel runs beside the next float32 launch, which it should not hold up.
+// Pass 1: each wavefront scans a contiguous block of candidates (enough for
+// the grid to cover the candidate count, at least scan_min), 64 at a time;
+// the in-band ones are gathered, in candidate order, into groups of up to
+// rows_max rows that are simulated side by side in float64
+// (simulate_rows_f64_wave); the others only get their keep flag. A large
+// scan_min packs the in-band rows into few wavefronts, so that they take few
+// issue slots from a float32 launch running beside them; scan_min = 1
+// spreads them for the shortest latency. Workgroups that meet no in-band row
+// never stage the observed series.
+template <int NOISE, int DIST>
+__device__ __forceinline__ void recheck_group(const RecheckArgs& r, const RowLds& l, int nr,
+                                              bool& staged)
+{
+    const SimArgs& a = r.sim;
+    if (!staged) {
+        stage_obs_f64<DIST>(a.obs, a.T, l.lobs);
+        staged = true;
+    }
+    __syncthreads();
+    const double d64 = simulate_rows_f64_wave<NOISE, DIST>(
+        nr, l.rth, l.rix, a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, a.T, (double)a.scale,
+        l.lobs, l.zs, l.xs, l.rw);
+    const int lane = threadIdx.x;
+    if (lane < nr) {
+        const int64_t qq = l.rq[lane];
+        r.keep[qq] = d64 <= (double)r.eps ? 1 : 0;
+        r.dist[qq] = (float)d64;
+    }
+    if (lane == 0 && r.rechecked) atomicAdd(r.rechecked, nr);
+    __syncthreads();  // the row slots are refilled next
+}
+
 template <int NOISE, int DIST>
 __global__ __launch_bounds__(64) void k_recheck_flags(RecheckArgs r)
 {
     extern __shared__ double lds_r[];
-    const SimArgs& a = r.sim;
     const int64_t count = *r.count;
     if (count > r.capacity) return;  // overflowed candidate set: left for the caller to rerun
-    const int T = a.T;
-    const RowLds l = row_lds(lds_r, T, r.rows_max);
-    const int64_t per = (count + gridDim.x - 1) / gridDim.x;
-    const int R = (int)(per < 1 ? 1 : (per > r.rows_max ? r.rows_max : per));
+    const RowLds l = row_lds(lds_r, r.sim.T, r.rows_max);
+    int64_t per = (count + gridDim.x - 1) / gridDim.x;
+    if (per < r.scan_min) per = r.scan_min;
+    const int64_t q0 = (int64_t)blockIdx.x * per;
+    if (q0 >= count) return;
+    const int64_t q1 = q0 + per < count ? q0 + per : count;
     const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
     bool staged = false;
-    for (int64_t q0 = (int64_t)blockIdx.x * R; q0 < count; q0 += (int64_t)gridDim.x * R) {
-        const int64_t q = q0 + lane;
+    int nr = 0;  // rows gathered so far (wave-uniform)
+    for (int64_t c0 = q0; c0 < q1; c0 += 64) {
+        const int64_t q = c0 + lane;
         bool inb = false;
-        if (lane < R && q < count) {
+        if (q < q1) {
             const float d = r.dist[q];
             inb = d > r.band_lo && d <= r.band_hi;
             if (!inb) r.keep[q] = d <= r.eps ? 1 : 0;
         }
-        const uint64_t m = __ballot(inb);
-        const int nr = __popcll(m);
-        if (nr == 0) continue;
-        if (!staged) {
-            stage_obs_f64<DIST>(a.obs, T, l.lobs);
-            staged = true;
-        }
-        if (inb) {
-            const int rank = __popcll(m & ((1ull << lane) - 1ull));
-            l.rq[rank] = q;
-            l.rix[rank] = (uint64_t)r.idx[q];
+        uint64_t m = __ballot(inb);
+        while (m) {
+            // the lowest (rows_max - nr) in-band lanes join the group
+            uint64_t take = 0;
+            for (int room = r.rows_max - nr; room > 0 && m; --room) {
+                const uint64_t b = m & (~m + 1ull);
+                take |= b;
+                m ^= b;
+            }
+            if ((take >> lane) & 1ull) {
+                const int slot = nr + __popcll(take & below);
+                l.rq[slot] = q;
+                l.rix[slot] = (uint64_t)r.idx[q];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) l.rth[8 * rank + j] = r.theta[8 * q + j];
+                for (int j = 0; j < 8; ++j) l.rth[8 * slot + j] = r.theta[8 * q + j];
+            }
+            nr += __popcll(take);
+            if (nr == r.rows_max) {
+                recheck_group<NOISE, DIST>(r, l, nr, staged);
+                nr = 0;
+            }
         }
-        __syncthreads();
-        const double d64 = simulate_rows_f64_wave<NOISE, DIST>(
-            nr, l.rth, l.rix, a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
-            (double)a.scale, l.lobs, l.zs, l.xs);
-        if (lane < nr) {
-            const int64_t qq = l.rq[lane];
-            r.keep[qq] = d64 <= (double)r.eps ? 1 : 0;
-            r.dist[qq] = (float)d64;
-        }
-        if (lane == 0 && r.rechecked) atomicAdd(r.rechecked, nr);
-        __syncthreads();  // the scratch is reused by the next rows
     }
+    if (nr > 0) recheck_group<NOISE, DIST>(r, l, nr, staged);
 }
 
 // Pass 2: stable in-place compaction of the kept rows, 256 rows at a time.
@@ -582,7 +611,7 @@ __global__ __launch_bounds__(64) void k_rows_f64(RowsArgs r)
         __syncthreads();
         const double d64 = simulate_rows_f64_wave<NOISE, DIST>(
             nr, l.rth, l.rix, a.key, a.series, a.domain, a.P, a.A0, a.R0, a.D0, T,
-            (double)a.scale, l.lobs, l.zs, l.xs);
+            (double)a.scale, l.lobs, l.zs, l.xs, l.rw);
         if (lane < nr) r.dist64[q0 + lane] = d64;
         __syncthreads();
     }
@@ -667,8 +696,8 @@ constexpr int64_t ROW_WAVE_GRID = 2048;
 static size_t row_wave_lds_bytes(int T, int R)
 {
     return sizeof(double) * 3 * (size_t)T +
-           (size_t)R * (sizeof(double) * 5 * (size_t)T + sizeof(uint64_t) + sizeof(int64_t) +
-                        sizeof(int32_t) * 3 * (size_t)T + sizeof(float) * 8);
+           (size_t)R * (sizeof(double) * 5 * ROW_WINDOW + sizeof(uint64_t) + sizeof(int64_t) +
+                        sizeof(RowWalk) + sizeof(int32_t) * 3 * ROW_WINDOW + sizeof(float) * 8);
 }
 // Most rows per wavefront within an LDS budget (at least 1).
 static int row_wave_rows_max(int T, size_t budget)
@@ -937,7 +966,7 @@ namespace abc {
 abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
                         float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
                         float* dist, float* weight, int64_t* count, int32_t* rechecked,
-                        void* stream, size_t lds_budget, int64_t grid_max)
+                        void* stream, size_t lds_budget, int64_t grid_max, int32_t scan_min)
 {
     abc_status rc;
     if ((rc = check_series(ser, true))) return rc;
@@ -966,6 +995,7 @@ abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc
     r.count = count;
     r.rechecked = rechecked;
     r.rows_max = rows_max;
+    r.scan_min = scan_min < 1 ? 1 : scan_min;
     void* scratch = nullptr;
     ABC_HIP(hipMallocAsync(&scratch, (size_t)capacity, s));
     r.keep = reinterpret_cast<uint8_t*>(scratch);
@@ -995,7 +1025,7 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
                                        void* stream)
 {
     return recheck_band(ser, model, st, eps, band_w, capacity, idx, theta, dist, weight, count,
-                        rechecked, stream, ROW_LDS_BESIDE, ROW_WAVE_GRID);
+                        rechecked, stream, ROW_LDS_BESIDE, ROW_WAVE_GRID, ROW_SCAN_BESIDE);
 }
 
 extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model* model,

@@ -708,7 +708,7 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
             return rc;
         if (cfg->band_w > 0.0f &&
             (rc = recheck_band(ser, &md, &st, eps, cfg->band_w, cap, oidx, oth, od, nullptr, dcnt,
-                               nullptr, stream, ROW_LDS_ALONE, ROW_WAVE_TARGET)))
+                               nullptr, stream, ROW_LDS_ALONE, ROW_WAVE_TARGET, ROW_SCAN_ALONE)))
             return rc;
         int64_t c = 0;
         ABC_HIP(hipMemcpyAsync(&c, dcnt, sizeof c, hipMemcpyDeviceToHost, s));
