@@ -167,3 +167,37 @@ def test_point_prior(A, noise):
         got, th = _device_pass(A, ser, eps, n, seed, prior=pr, cap=n)
         _agree(got, ref, eps)
         assert got.size > 0 and np.all(th == pt)
+
+
+def test_band_decision_many_rows_per_wavefront(A):
+    """A wide band (w = 0.5) around the median distance puts most of ~5e4
+    candidates in the band, so each band-decision wavefront gathers several
+    groups of rows. Every kept row, its order and its distance follow the
+    float64 distances of the same samples: in-band rows are kept when their
+    float64 distance is <= eps and carry it (rounded to float32); the others
+    keep the float32 decision."""
+    s = W.single_country()
+    m = oracle.make_model(s.P, s.T)
+    obs = oracle.observe(m, s.theta_true, s.obs_seed)
+    ser = A.DeviceSeries(s.P, s.T, torch.from_numpy(obs))
+    n, seed, w = 60_000, 12, 0.5
+    d32 = A.simulate_distance(ser, n, seed)
+    eps = float(np.float32(np.median(d32.cpu().numpy())))
+    e_hi = eps * (1.0 + w)
+    idx, th, dd, _, cnt = A.accept_compact(d32, e_hi, n, seed=seed)
+    c0 = int(cnt.item())
+    assert c0 > 2048 * 16
+    cand_idx = idx[:c0].cpu().numpy().copy()
+    cand_d = dd[:c0].cpu().numpy().copy()
+    nre = A.recheck_band(ser, seed, eps, w, idx, th, dd, cnt, want_rechecked=True)
+    _, d64 = A.simulate_distance(ser, n, seed, flags=A.ABC_FP64, want64=True)
+    d64 = d64.cpu().numpy()
+    e32, w64 = np.float64(np.float32(eps)), np.float64(np.float32(w))
+    lo, hi = np.float32(e32 * (1.0 - w64)), np.float32(e32 * (1.0 + w64))
+    inb = (cand_d > lo) & (cand_d <= hi)
+    keep = np.where(inb, d64[cand_idx] <= e32, cand_d <= np.float32(eps))
+    want_d = np.where(inb, d64[cand_idx].astype(np.float32), cand_d)[keep]
+    c = int(cnt.item())
+    assert int(nre.item()) == int(inb.sum())
+    np.testing.assert_array_equal(idx[:c].cpu().numpy(), cand_idx[keep])
+    np.testing.assert_array_equal(dd[:c].cpu().numpy(), want_d)
