@@ -125,6 +125,25 @@ def batched_leg(args):
     acc = int(o["count"].sum().item())
     used = int(o["used"].sum().item())
     nominal = int(sum(int(o["used"][j].item()) * s.T for j, s in enumerate(ss)))
+    # the same quota run with the round size the autotuner picks from whole
+    # timed runs (the workload above fixes 2^22); the accepted sets are the same
+    rt = autotune.tune_round_size(sers, eps, seed=2, quota=args.quota, use_cache=False,
+                                  cand_capacity=4 * args.quota)
+    truns = []
+    for rep in range(args.batch_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ot = abc.batch_run(sers, eps, 2, args.quota, round_size=rt["round_size"],
+                           rounds_per_graph=4, cand_capacity=4 * args.quota)
+        torch.cuda.synchronize()
+        truns.append((time.perf_counter() - t0, ot))
+    twall, ot = min(truns, key=lambda r: r[0])
+    same = all(torch.equal(ot[k], o[k]) for k in ("idx", "count"))
+    tuned_round = {"round_size": rt["round_size"],
+                   "accepted_per_s": int(ot["count"].sum().item()) / twall, "wall_s": twall,
+                   "samples": int(ot["used"].sum().item()), "rounds": ot["stats"]["rounds"],
+                   "same_accepted_sets": bool(same),
+                   "table_ms_round_samples": rt["table"]}
     return {
         "workload": "64 synthetic series, T uniform in [30,200], P log-uniform in [1e5,1e9], "
                     "theta_true from the prior (seed 5); eps_j = 1e-4 pilot quantile; rounds of "
@@ -146,6 +165,7 @@ def batched_leg(args):
                                         (st["rounds_ms"] * 1e-3) / (VALU_PEAK_TOPS * 1e12),
         "refill_min": tune.get("refill"),
         "rechecked_fp64": st["rechecked"],
+        "autotuned_round": tuned_round,
         "launch_shape": [st["spl"], st["block"], st["grid"]],
         "lds_bytes": st["lds_bytes"],
         "autotune_best_ms_per_round": tune["ms_per_round"],

@@ -2,10 +2,12 @@
 
 Sweeps samples per lane (SPL), workgroup size and resident workgroups per CU,
 then the lane-refill threshold at the best shape, times each setting with HIP
-events on short runs of the real workload, and keeps the fastest. Results never depend on the shape (every random number is
-fixed by the sample's counter), so the tuner only trades speed. Choices are
-cached as JSON per (device, kernel, T bucket) in $ABC_TUNE_CACHE (default
-~/.cache/abc_mi355x/tune.json).
+events on short runs of the real workload, and keeps the fastest; for the
+batched quota run it also picks the round size from whole timed runs. Results
+never depend on these choices (every random number is fixed by the sample's
+counter, and each series keeps its first accepts by sample index), so the
+tuner only trades speed. Choices are cached as JSON per (device, kernel,
+T bucket) in $ABC_TUNE_CACHE (default ~/.cache/abc_mi355x/tune.json).
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ SPL_BATCH = (1, 2, 4)
 BLOCKS = (64, 128, 256, 512, 1024)
 PER_CU = (1, 2, 4, 8)
 REFILL = (1, 4, 8, 16, 24)
+ROUND_SIZES = (1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
 
 
 def cache_path() -> str:
@@ -158,5 +161,39 @@ def tune_batch(sers, eps, seed: int = 1, quota: int = 1000, round_size: int = 1 
            "table": [[round(ms, 4)] + list(sh) for ms, sh in table],
            "refill_table": [[round(ms, 4), lanes] for ms, lanes in rtable]}
     _apply(rec)
+    _store(key, rec)
+    return rec
+
+
+def tune_round_size(sers, eps, seed: int = 1, quota: int = 1000,
+                    sizes: Sequence[int] = ROUND_SIZES, reps: int = 2, use_cache: bool = True,
+                    **run_kw) -> Dict:
+    """Round size of the batched quota run, at the launch shape in force.
+    Larger rounds pay the per-round tail (lanes idle at the end of a round)
+    less often but simulate more samples past each series' quota; the fastest
+    whole quota run wins. run_kw goes to abc.batch_run."""
+    key = "%s|round|T%d|m%d|q%d%s" % (device_key(), t_bucket(max(s.T for s in sers)), len(sers),
+                                      quota, "|mix" if run_kw.get("mix") is not None else "")
+    if use_cache:
+        rec = _load().get(key)
+        if rec and "round_size" in rec:
+            return rec
+    table = []
+    for rs in sizes:
+        best, used = math.inf, 0
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            o = abc.batch_run(sers, eps, seed, quota, round_size=rs, **run_kw)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            if ms < best:
+                best, used = ms, int(o["used"].sum().item())
+        table.append((best, int(rs), used))
+    table.sort()
+    rec = {"round_size": table[0][1], "ms": round(table[0][0], 3),
+           "table": [[round(ms, 3), rs, used] for ms, rs, used in table]}
     _store(key, rec)
     return rec

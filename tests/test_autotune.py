@@ -99,3 +99,30 @@ def test_tune_batch_changes_no_result(A, tmp_path, monkeypatch):
     got = A.batch_run(sers, eps, 3, 50, **kw)
     for k in ("idx", "theta", "count", "used"):
         np.testing.assert_array_equal(got[k].cpu().numpy(), ref[k].cpu().numpy(), err_msg=k)
+
+
+@pytest.mark.gpu
+def test_tune_round_size_picks_a_swept_size_and_changes_no_result(A, tmp_path, monkeypatch):
+    """The round-size sweep keeps one of its sizes and caches it; every size
+    yields the same accepted rows (each series' first accepts by index)."""
+    monkeypatch.setenv("ABC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ss = W.uneven_series(64, 5)[:4]
+    sers = [A.DeviceSeries(s.P, s.T, torch.from_numpy(
+        oracle.observe(oracle.make_model(s.P, s.T), s.theta_true, s.obs_seed, series=s.series_id)))
+        for s in ss]
+    eps = []
+    for j, (s, ser) in enumerate(zip(ss, sers)):
+        d = A.simulate_distance(ser, 100_000, 9, series=j).cpu().numpy()
+        eps.append(float(np.quantile(d, 2e-3)))
+    A.set_launch_config(0, 0, 0)
+    A.set_refill_min(0)
+    sizes = (1 << 16, 1 << 18, 1 << 20)
+    rec = autotune.tune_round_size(sers, eps, seed=3, quota=50, sizes=sizes, reps=1,
+                                   series_ids=list(range(4)))
+    assert rec["round_size"] in sizes and sorted(r[1] for r in rec["table"]) == list(sizes)
+    assert rec["ms"] == min(r[0] for r in rec["table"])
+    assert autotune.tune_round_size(sers, eps, seed=3, quota=50, sizes=sizes) == rec  # cached
+    outs = [A.batch_run(sers, eps, 3, 50, round_size=rs, series_ids=list(range(4))) for rs in sizes]
+    for o in outs[1:]:
+        for k in ("idx", "theta", "count"):
+            np.testing.assert_array_equal(o[k].cpu().numpy(), outs[0][k].cpu().numpy(), err_msg=k)
