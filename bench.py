@@ -216,6 +216,24 @@ def learned_leg(args, batched):
         walls.append(time.perf_counter() - t0)
     wall = min(walls)
     acc = int(lb["count"].clamp(max=Q).sum().item())
+    # the same run with the round size the autotuner picks (the workload fixes 2^22)
+    rt = autotune.tune_round_size(sers, eps, seed=2, quota=Q, use_cache=False,
+                                  **{k: v for k, v in kw.items() if k != "round_size"})
+    twalls = []
+    for rep in range(args.batch_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lt = abc.batch_run(sers, eps, 2, Q, **dict(kw, round_size=rt["round_size"]))
+        torch.cuda.synchronize()
+        twalls.append(time.perf_counter() - t0)
+    tacc_s = int(lt["count"].clamp(max=Q).sum().item()) / min(twalls)
+    plain_t = batched["autotuned_round"]["accepted_per_s"]
+    tuned_round = {"round_size": rt["round_size"], "accepted_per_s": tacc_s,
+                   "wall_s": min(twalls), "plain_accepted_per_s_tuned_round": plain_t,
+                   "gain_accepted_per_s": tacc_s / plain_t,
+                   "same_accepted_sets": bool(torch.equal(lt["idx"], lb["idx"]) and
+                                              torch.equal(lt["count"], lb["count"])),
+                   "table_ms_round_samples": rt["table"]}
     w = lb["w"].double().cpu().numpy()
     ess_series = w.sum(1) ** 2 / (w * w).sum(1)
     ess = float(ess_series.sum())
@@ -277,6 +295,7 @@ def learned_leg(args, batched):
         "ess_per_s": ess / wall,
         "plain_accepted_per_s": batched["accepted_per_s"],
         "gain_accepted_per_s": (acc / wall) / batched["accepted_per_s"],
+        "autotuned_round": tuned_round,
         "gain_ess_per_s": (ess / wall) / batched["accepted_per_s"],
         "acceptance_rate_gain_median": float(np.median(gains)),
         "acceptance_rate_gain_range": [float(np.min(gains)), float(np.max(gains))],
