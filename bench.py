@@ -586,7 +586,11 @@ def main():
                 sC.wait_event(compacted[c])
                 abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
                 mean, cov = abc.posterior_moments(th, n_dev=cnt)
-            keep.append((c, idx, th, cnt, mean, cov))
+            # every output stays referenced until the final synchronisation: the
+            # compaction allocates them on stream B and the band decision uses them
+            # on stream C, so a block freed early could be handed to the next
+            # compaction while the band decision still works on it
+            keep.append((c, idx, th, cnt, mean, cov, d))
 
     keep = []
     for s in range(args.warmup):
@@ -603,6 +607,16 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     accepted = sum(int(k[3].item()) for k in keep)
+    # the last step again, one country at a time on one stream: the pipelined
+    # step must have accepted exactly the same rows
+    last_first = first0 + (args.warmup + args.steps - 1) * N
+    same_rows = True
+    for c, r in enumerate(runs):
+        k = [k for k in keep if k[0] == c][-1]
+        ref = r.run(last_first)
+        n_ref, n_got = int(ref.count.item()), int(k[3].item())
+        same_rows &= n_ref == n_got and torch.equal(ref.idx[:n_ref], k[1][:n_got])
+    torch.cuda.synchronize()
     sim_ms = [a.elapsed_time(b) for a, b, _ in ev]
     eff_days = int(days.item())
     nominal_days = args.steps * N * sum(s.T for s in countries)
@@ -646,6 +660,7 @@ def main():
             "refill_min": abc.get_refill_min(),
         },
         "trajectories_per_s": traj / wall,
+        "last_step_rows_match_single_stream": bool(same_rows),
         "sim_days_per_s_effective": eff_days / wall,
         "sim_days_per_s_nominal": nominal_days / wall,
         "simulate_kernel_ms_avg": avg_ms,
