@@ -3,7 +3,7 @@
 // BF16 MFMA GEMMs (FP32 accumulation) and Adam, and a defensive-mixture
 // proposal sampler with importance weights. Not part of the paper, whose
 // proposal is the prior (eq. 2); the prior stays both the fallback and the
-// judge of the learned posterior.
+// reference for the learned posterior.
 //
 // Network: x (96 = log1p A, R, D at 32 evenly spaced days, standardised per
 // feature) -> z1 = x W1 + b1, h1 = gelu(z1) -> z2 = h1 W2 + b2, h2 = gelu(z2)
