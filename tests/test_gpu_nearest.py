@@ -134,6 +134,22 @@ def test_simulate_rows_f64_side_by_side_rows(A, country, n):
     np.testing.assert_array_equal(d, d64.cpu().numpy())
 
 
+@pytest.mark.parametrize("T,n", [(1, 2000), (13, 5000), (1024, 1500)])
+def test_simulate_rows_f64_short_and_long_horizons(A, T, n):
+    """Horizons that end inside the first window (T = 1), a ragged last window
+    (T = 13) and the longest horizon (T = 1024): the row kernel's doubles equal
+    the one-lane float64 simulation's."""
+    P = 1_000_000
+    m = oracle.make_model(P, T)
+    obs = oracle.observe(m, W.THETA_NZ, 21)
+    ser = A.DeviceSeries(P, T, torch.from_numpy(obs))
+    th = A.sample_prior(n, 5)
+    idx = torch.arange(n, dtype=torch.int64, device="cuda")
+    d = A.simulate_rows_f64(ser, 5, idx, th).cpu().numpy()
+    _, d64 = A.simulate_distance(ser, n, 5, theta=th, flags=A.ABC_FP64, want64=True)
+    np.testing.assert_array_equal(d, d64.cpu().numpy())
+
+
 def test_single_country_nearest_100_of_1e5(A):
     """The single-country workload end to end against the oracle's rule."""
     from paper_2012_14332_amd import pipeline as P
