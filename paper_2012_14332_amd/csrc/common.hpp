@@ -33,11 +33,14 @@ constexpr int32_t ROW_SCAN_BESIDE = 8;
 constexpr int32_t ROW_SCAN_ALONE = 1;
 
 // abc_recheck_band with a chosen LDS budget per row workgroup, grid cap and
-// candidates per wavefront.
+// candidates per wavefront; with all_rows every candidate (not only those in
+// the band) is decided by its float64 distance, and dist64 (nullable,
+// [capacity]) receives that distance for each row, compacted with the rows.
 abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
                         float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
                         float* dist, float* weight, int64_t* count, int32_t* rechecked,
-                        void* stream, size_t lds_budget, int64_t grid_max, int32_t scan_min);
+                        void* stream, size_t lds_budget, int64_t grid_max, int32_t scan_min,
+                        double* dist64, bool all_rows);
 
 #define ABC_REQUIRE(cond, ...)                                 \
     do {                                                       \

@@ -421,6 +421,8 @@ struct RecheckArgs {
     int32_t* rechecked;  // nullable: number of rows simulated in float64
     int32_t rows_max;    // rows per wavefront the LDS was sized for
     int32_t scan_min;    // candidates per wavefront at least
+    int32_t all_rows;    // 1: every candidate is decided in float64, not only the band
+    double* dist64;      // nullable [capacity]: float64 distance of each row so decided
 };
 
 // LDS of the float64 row kernels, for up to R rows per wavefront (W = ROW_WINDOW days):
@@ -475,6 +477,7 @@ __device__ __forceinline__ void recheck_group(const RecheckArgs& r, const RowLds
         const int64_t qq = l.rq[lane];
         r.keep[qq] = d64 <= (double)r.eps ? 1 : 0;
         r.dist[qq] = (float)d64;
+        if (r.dist64) r.dist64[qq] = d64;
     }
     if (lane == 0 && r.rechecked) atomicAdd(r.rechecked, nr);
     __syncthreads();  // the row slots are refilled next
@@ -501,7 +504,7 @@ __global__ __launch_bounds__(64) void k_recheck_flags(RecheckArgs r)
         bool inb = false;
         if (q < q1) {
             const float d = r.dist[q];
-            inb = d > r.band_lo && d <= r.band_hi;
+            inb = r.all_rows || (d > r.band_lo && d <= r.band_hi);
             if (!inb) r.keep[q] = d <= r.eps ? 1 : 0;
         }
         uint64_t m = __ballot(inb);
@@ -545,12 +548,14 @@ __global__ __launch_bounds__(256) void k_recheck_compact(RecheckArgs r)
         const bool kp = q < count && r.keep[q];
         int64_t id = 0;
         float th[8], d = 0.0f, w = 0.0f;
+        double d64 = 0.0;
         if (kp) {
             id = r.idx[q];
 #pragma unroll
             for (int j = 0; j < 8; ++j) th[j] = r.theta[8 * q + j];
             d = r.dist[q];
             if (r.weight) w = r.weight[q];
+            if (r.dist64) d64 = r.dist64[q];
         }
         const uint64_t m = __ballot(kp);
         const int rank = __popcll(m & ((1ull << lane) - 1ull));
@@ -569,6 +574,7 @@ __global__ __launch_bounds__(256) void k_recheck_compact(RecheckArgs r)
             for (int j = 0; j < 8; ++j) r.theta[8 * dst + j] = th[j];
             r.dist[dst] = d;
             if (r.weight) r.weight[dst] = w;
+            if (r.dist64) r.dist64[dst] = d64;
         }
         __syncthreads();
         if (threadIdx.x == 0) base_sh += tot;
@@ -966,7 +972,8 @@ namespace abc {
 abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc_stream* st,
                         float eps, float band_w, int64_t capacity, int64_t* idx, float* theta,
                         float* dist, float* weight, int64_t* count, int32_t* rechecked,
-                        void* stream, size_t lds_budget, int64_t grid_max, int32_t scan_min)
+                        void* stream, size_t lds_budget, int64_t grid_max, int32_t scan_min,
+                        double* dist64, bool all_rows)
 {
     abc_status rc;
     if ((rc = check_series(ser, true))) return rc;
@@ -996,6 +1003,8 @@ abc_status recheck_band(const abc_series* ser, const abc_model* model, const abc
     r.rechecked = rechecked;
     r.rows_max = rows_max;
     r.scan_min = scan_min < 1 ? 1 : scan_min;
+    r.all_rows = all_rows ? 1 : 0;
+    r.dist64 = dist64;
     void* scratch = nullptr;
     ABC_HIP(hipMallocAsync(&scratch, (size_t)capacity, s));
     r.keep = reinterpret_cast<uint8_t*>(scratch);
@@ -1025,7 +1034,8 @@ extern "C" abc_status abc_recheck_band(const abc_series* ser, const abc_model* m
                                        void* stream)
 {
     return recheck_band(ser, model, st, eps, band_w, capacity, idx, theta, dist, weight, count,
-                        rechecked, stream, ROW_LDS_BESIDE, ROW_WAVE_GRID, ROW_SCAN_BESIDE);
+                        rechecked, stream, ROW_LDS_BESIDE, ROW_WAVE_GRID, ROW_SCAN_BESIDE,
+                        nullptr, false);
 }
 
 extern "C" abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model* model,

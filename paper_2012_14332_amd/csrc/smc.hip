@@ -13,11 +13,15 @@
 //   k_smc_propose   one lane per candidate: ancestor by binary search of
 //                   u C_{N-1} in C, theta* = theta_anc + L z (float64, rounded
 //                   to float32).
-//   simulate / compact / float64 band decision: the rejection-ABC kernels,
-//                   with the prior-support check (candidates outside the box
-//                   are rejected unsimulated); the first N accepted by index
-//                   form the population.
-//   float64 distances of the population (for eps_{t+1}), abc_simulate_rows_f64.
+//   simulate / compact / float64 decision: the rejection-ABC kernels, with
+//                   the prior-support check (candidates outside the box are
+//                   rejected unsimulated); with a band every candidate is
+//                   decided by its float64 distance; the first N accepted by
+//                   index form the population.
+//   float64 distances of the population (for eps_{t+1}): with a band, the
+//                   float64 decision runs on every candidate (alone on the GPU,
+//                   rows side by side cost no more latency than the band's) and
+//                   its distances are kept; without one, abc_simulate_rows_f64.
 //   k_smc_sums      importance-weight denominators sum_j W_j exp(-|y_i - y_j|^2 / 2),
 //                   split over the previous particles for parallelism.
 //   k_smc_finish    w_i = 1 / denominator, W = w / sum w (left to right), ESS.
@@ -626,7 +630,8 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
     const size_t o_oidx = o_cd + up(sizeof(float) * cap);
     const size_t o_oth = o_oidx + up(sizeof(int64_t) * cap);
     const size_t o_od = o_oth + up(sizeof(float) * 8 * cap);
-    const size_t o_cnt = o_od + up(sizeof(float) * cap);
+    const size_t o_od64 = o_od + up(sizeof(float) * cap);
+    const size_t o_cnt = o_od64 + up(sizeof(double) * cap);
     const size_t o_box = o_cnt + 256;
     const size_t o_ess = o_box + 256;
     const size_t o_anc = o_ess + 256;
@@ -643,6 +648,7 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
     int64_t* oidx = reinterpret_cast<int64_t*>(base + o_oidx);
     float* oth = reinterpret_cast<float*>(base + o_oth);
     float* od = reinterpret_cast<float*>(base + o_od);
+    double* od64 = reinterpret_cast<double*>(base + o_od64);
     int64_t* dcnt = reinterpret_cast<int64_t*>(base + o_cnt);
     unsigned long long* dbox = reinterpret_cast<unsigned long long*>(base + o_box);
     double* dess = reinterpret_cast<double*>(base + o_ess);
@@ -708,7 +714,8 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
             return rc;
         if (cfg->band_w > 0.0f &&
             (rc = recheck_band(ser, &md, &st, eps, cfg->band_w, cap, oidx, oth, od, nullptr, dcnt,
-                               nullptr, stream, ROW_LDS_ALONE, ROW_WAVE_TARGET, ROW_SCAN_ALONE)))
+                               nullptr, stream, ROW_LDS_ALONE, ROW_WAVE_TARGET, ROW_SCAN_ALONE,
+                               od64, true)))
             return rc;
         int64_t c = 0;
         ABC_HIP(hipMemcpyAsync(&c, dcnt, sizeof c, hipMemcpyDeviceToHost, s));
@@ -720,6 +727,9 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
             ABC_HIP(hipMemcpyAsync(idx + got, oidx, sizeof(int64_t) * take, hipMemcpyDeviceToDevice, s));
             ABC_HIP(hipMemcpyAsync(theta + 8 * (size_t)got, oth, sizeof(float) * 8 * take,
                                    hipMemcpyDeviceToDevice, s));
+            if (cfg->band_w > 0.0f)
+                ABC_HIP(hipMemcpyAsync(dist + got, od64, sizeof(double) * take,
+                                       hipMemcpyDeviceToDevice, s));
             if (gen > 0 && ancestors) {
                 hipLaunchKernelGGL(k_smc_gather_anc, dim3((unsigned)((take + 255) / 256)), dim3(256), 0,
                                    s, oidx, take, first, danc, ancestors + got);
@@ -745,8 +755,11 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
         chunk = chunk * 2 < cfg->chunk_max ? chunk * 2 : cfg->chunk_max;
     }
 
-    // float64 distances of the population
-    if ((rc = abc_simulate_rows_f64(ser, model, &st, idx, theta, N, dist, stream))) return rc;
+    // float64 distances of the population: with a band, the float64 decision
+    // of every candidate has already produced them
+    if (cfg->band_w <= 0.0f &&
+        (rc = abc_simulate_rows_f64(ser, model, &st, idx, theta, N, dist, stream)))
+        return rc;
     // weights
     if (gen == 0) {
         hipLaunchKernelGGL(k_smc_equal, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w, N, dess);
