@@ -512,8 +512,10 @@ ABC_API abc_status abc_simulate_rows_f64(const abc_series* ser, const abc_model*
  *     C_j > u C_{N-1} (C = running sums of the weights); theta* = theta_j + L z
  *     in float64, rounded to float32. Candidates outside the closed prior box
  *     are rejected without simulation; the others are simulated (days 1..T of
- *     the same stream) and accepted iff distance <= eps_t (float32 path,
- *     float64 decision within the relative band band_w). The first N accepted
+ *     the same stream) and accepted iff distance <= eps_t: with band_w > 0
+ *     every candidate whose float32 distance is <= eps_t (1 + band_w) is
+ *     decided by its float64 distance (which becomes the particle's distance);
+ *     with band_w = 0 the float32 distance decides. The first N accepted
  *     by index form the population; weights W_i are proportional to
  *     1 / sum_j W_j exp(-(theta_i - theta_j)^T Sigma^-1 (theta_i - theta_j) / 2)
  *     (the uniform prior and the Gaussian normaliser cancel), normalised.
@@ -526,7 +528,8 @@ typedef struct {
     float eps0;           /* tolerance of generation 0 */
     float eps_min;        /* floor of the tolerance sequence; abc_smc_run stops after the
                              generation that reaches it (0 = no floor) */
-    float band_w;         /* relative band of the float64 decision, [0, 1) */
+    float band_w;         /* [0, 1): candidates are float32 distances <= eps (1 + band_w),
+                             decided in float64; 0 = float32 decisions */
     int32_t pad;
     int64_t chunk0;       /* candidates in the first chunk of a generation (doubling) */
     int64_t chunk_max;    /* largest chunk, <= 2^26 */
