@@ -236,7 +236,9 @@ ABC_API abc_status abc_posterior_moments(const float* theta, const float* weight
  * per lane (1, 2, 4 or 8; more than 1 only for the default noise and
  * distance), block = workgroup size (multiple of 64 in [64, 1024/spl]),
  * blocks_per_cu = resident workgroups per compute unit (1..64). A 0 selects
- * that argument's default: spl 1, block 1024 / spl, blocks_per_cu 1. Results
+ * that argument's default: spl 1, block 512 / spl (at least 64), blocks_per_cu
+ * 2 (two 512-thread workgroups per CU were the fastest plain three-country
+ * step on MI355X). Results
  * never depend on these settings, only speed.
  */
 ABC_API abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu);

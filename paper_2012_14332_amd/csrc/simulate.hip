@@ -721,8 +721,8 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 // per lane, workgroup size and resident workgroups per CU (0 = default).
 struct LaunchConfig {
     int spl = 1;
-    int block = 1024;
-    int blocks_per_cu = 1;
+    int block = 512;
+    int blocks_per_cu = 2;
     int refill_min = 8;
 };
 static thread_local LaunchConfig g_launch;
@@ -947,8 +947,8 @@ extern "C" abc_status abc_simulate_record(const abc_series* ser, const abc_model
 extern "C" abc_status abc_set_launch_config(int32_t spl, int32_t block, int32_t blocks_per_cu)
 {
     if (spl == 0) spl = 1;
-    if (block == 0) block = 1024 / spl;
-    if (blocks_per_cu == 0) blocks_per_cu = 1;
+    if (block == 0) block = 512 / spl < 64 ? 64 : 512 / spl;
+    if (blocks_per_cu == 0) blocks_per_cu = 2;
     ABC_REQUIRE(spl == 1 || spl == 2 || spl == 4 || spl == 8, "spl must be 1, 2, 4 or 8");
     ABC_REQUIRE(block >= 64 && block <= 1024 / spl && block % 64 == 0,
                 "block must be a multiple of 64 in [64, 1024/spl]");
