@@ -484,7 +484,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # a first process on a box with only a few warm-up steps has run its whole
+    # timed region a third slower (host side; the kernels themselves at full
+    # speed); about 0.4 s of warm-up steps avoided it
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--samples", type=int, default=10_000_000, help="prior samples per country per step")
     ap.add_argument("--band", type=float, default=0.02)
     ap.add_argument("--pilot", type=int, default=100_000)
