@@ -331,8 +331,9 @@ typedef struct {
  * sum w (theta - mean)(theta - mean)^T / (V1 - V2/V1)). The kept rows are the
  * first `quota` accepted by index, so the result equals the per-series
  * learned-proposal pass run until the same quota. Errors as abc_batch_run,
- * plus ABC_EINVAL for a NULL proposal or out_w, lambda outside [0, 1] or
- * inflate outside [1, 100].
+ * plus ABC_EINVAL for a NULL proposal or out_w, lambda outside [0, 1],
+ * inflate outside [1, 100], or prop->domain equal to `domain` (theta's words
+ * would then be the simulation's day-1 noise words).
  */
 ABC_API abc_status abc_batch_run_weighted(const abc_batch_series* series, int32_t m,
                                           const abc_prior* prior, const abc_model* model,
@@ -436,7 +437,10 @@ ABC_API abc_status abc_mdn_train(abc_mdn* net, const float* features, const floa
  * dropped). Day 1 of the stream: block 0 words 0, 1 choose prior/mixture and
  * the component, blocks 1-2 give the eight uniforms. weight = prior(theta) /
  * q(theta), q = (1 - lambda) q_trunc + lambda prior, q_trunc the truncated
- * mixture's density. Outputs device theta [n][8], weight [n]. */
+ * mixture's density. Outputs device theta [n][8], weight [n]. The caller
+ * simulates these samples on another domain than st->domain: day 1 of
+ * st->domain supplies theta here, and the same words as simulation noise would
+ * tie each sample to its own trajectory. */
 ABC_API abc_status abc_mdn_sample(const abc_mdn* net, const float* mix, float lambda,
                                   float inflate, const abc_stream* st, uint64_t first, int64_t n,
                                   float* theta, float* weight, void* stream);

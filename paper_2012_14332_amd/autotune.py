@@ -22,7 +22,7 @@ import torch
 from . import abc
 
 SPL_PLAIN = (1, 2, 4, 8)
-SPL_BATCH = (1, 2, 4)
+SPL_BATCH = (1, 2, 4, 8)
 BLOCKS = (64, 128, 256, 512, 1024)
 PER_CU = (1, 2, 4, 8)
 REFILL = (1, 4, 8, 16, 24)

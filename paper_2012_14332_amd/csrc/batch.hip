@@ -650,6 +650,11 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         ABC_REQUIRE(isfinite(prop->inflate) && prop->inflate >= 1.0f && prop->inflate <= 100.0f,
                     "inflate must be in [1, 100]");
         ABC_REQUIRE(prop->domain <= 15u, "proposal domain > 15");
+        // theta's Philox words (day 1 of the proposal domain) must not be the
+        // simulation's day-1 noise words: a sample would be correlated with
+        // its own trajectory
+        ABC_REQUIRE(prop->domain != domain, "proposal domain %u equals the simulation domain",
+                    prop->domain);
     }
 
     // host-side series descriptors
@@ -683,6 +688,9 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     }
     int32_t spl = 1, block = 1024, bpc = 1;
     abc_get_launch_config(&spl, &block, &bpc);
+    if (spl != 1 && spl != 2 && spl != 4 && spl != 8)
+        return set_error(ABC_EUNSUPPORTED, "the batched round kernel is built for 1, 2, 4 or 8 "
+                         "samples per lane, not %d", spl);
     const int32_t refill_min = abc_get_refill_min();
     const size_t lds = batch_lds_bytes(m, obs_words, block);
     int dev = 0, num_cu = 0, max_lds = 0;
@@ -805,9 +813,10 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     for (int r = 0; r < rounds_per_graph; ++r) {
         hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(BT_MAX_SERIES), 0, s, a);
         switch (spl) {
+        case 1: launch_round<1>(a, grid, block, lds, s); break;
         case 2: launch_round<2>(a, grid, block, lds, s); break;
         case 4: launch_round<4>(a, grid, block, lds, s); break;
-        default: launch_round<1>(a, grid, block, lds, s); break;
+        case 8: launch_round<8>(a, grid, block, lds, s); break;
         }
     }
     hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(BT_MAX_SERIES), 0, s, a);

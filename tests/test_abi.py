@@ -133,6 +133,13 @@ def test_host_validation_of_the_newer_entry_points(built):
         assert L.abc_batch_run_weighted(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 10, 4096,
                                         100, 0.02, 1, 0, ctypes.byref(prop), fake, fake, fake, fake,
                                         fake, fake, fake, fake, ctypes.byref(bst), None) == -1
+    # the proposal's draws on the simulation's own domain would reuse its
+    # day-1 noise words for theta: rejected
+    prop = abc._BatchProposal(0x1000, 0.5, 2.0, 1, 0)
+    assert L.abc_batch_run_weighted(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 10, 4096,
+                                    100, 0.02, 1, 0, ctypes.byref(prop), fake, fake, fake, fake,
+                                    fake, fake, fake, fake, ctypes.byref(bst), None) == -1
+    assert b"equals the simulation domain" in L.abc_last_error()
 
 
 def test_host_validation_of_limits_and_special_values(built):

@@ -70,7 +70,8 @@ def test_batch_independent_of_round_size_and_launch(env):
                         cand_capacity=4096)
     ref_idx = ref["idx"].cpu().numpy()
     for rs, rpg, cfg, lanes in [(1 << 17, 4, (1, 512, 4), 1), (1 << 16, 8, (2, 256, 4), 16),
-                                (50_000, 2, (4, 128, 2), 64), (1 << 20, 1, (1, 1024, 1), 9)]:
+                                (50_000, 2, (4, 128, 2), 64), (1 << 20, 1, (1, 1024, 1), 9),
+                                (1 << 18, 2, (8, 128, 4), 8), (1 << 16, 4, (8, 64, 8), 24)]:
         abc.set_launch_config(*cfg)
         abc.set_refill_min(lanes)
         o = abc.batch_run(sers, eps, 9, 30, round_size=rs, rounds_per_graph=rpg,
@@ -79,6 +80,7 @@ def test_batch_independent_of_round_size_and_launch(env):
         np.testing.assert_array_equal(o["theta"].cpu().numpy(), ref["theta"].cpu().numpy())
         np.testing.assert_array_equal(o["dist"].cpu().numpy(), ref["dist"].cpu().numpy())
         np.testing.assert_allclose(o["mean"].cpu().numpy(), ref["mean"].cpu().numpy(), rtol=1e-13)
+        assert o["stats"]["spl"] == cfg[0] and o["stats"]["block"] == cfg[1]
     abc.set_launch_config(0, 0, 0)
     abc.set_refill_min(0)
 

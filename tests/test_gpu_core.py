@@ -191,9 +191,13 @@ def test_distance_fp32_accuracy_statement(A):
     d = A.simulate_distance(ser, n, seed=1).cpu().numpy().astype(np.float64)
     ref = oracle.distances(oracle.make_model(s.P, s.T), obs, seed=1, n=n)
     rel = np.abs(d - ref) / ref
-    print("fp32 rel err: median %.2e p99 %.2e max %.2e" % (np.median(rel),
-                                                            np.quantile(rel, 0.99), rel.max()))
-    assert np.median(rel) < 1e-4
+    near = ref <= 2 * np.sort(ref)[99]
+    print("fp32 rel err: median %.2e p99 %.2e max %.2e, near the 100th distance max %.2e"
+          % (np.median(rel), np.quantile(rel, 0.99), rel.max(), rel[near].max()))
+    # measured: median about 1e-7; near the kept set at most a few 1e-4, a
+    # quarter of the float64 band (w = 0.02) protects the band's margin
+    assert np.median(rel) <= 1e-6
+    assert rel[near].max() <= 0.02 / 4
     near_ref = oracle.nearest(ref, 100)
     near_gpu = oracle.nearest(d, 100)
     # differences only where the 100th and 101st distances are within float32 error

@@ -65,15 +65,33 @@ def test_three_countries_full_size(env, c):
     d = d32[idx - first].astype(np.float64)
     ex = np.isinf(d)
     assert np.all(ref[ex] > eps)
-    # completed float32 distances: accuracy near eps and overall
+    # completed float32 distances: accuracy near eps and overall (measured:
+    # median about 1e-7, near eps a few 1e-5; a quarter of the band width w
+    # keeps the band's safety margin)
     fin = ~ex
     rel = np.abs(d[fin] - ref[fin]) / ref[fin]
     near = ref[fin] <= 2 * eps
-    assert np.median(rel) < 1e-5
-    assert rel[near].max() < 1e-2, rel[near].max()
-    print("country %d: %d accepted, %d checked, max rel err near eps %.2e, %d exited of %d sampled"
-          % (c, acc.size, idx.size, rel[near].max() if near.any() else 0.0, ex[np.isin(idx, smp)].sum(),
-             smp.size))
+    assert np.median(rel) <= 1e-6, np.median(rel)
+    assert rel[near].max() <= w / 4, rel[near].max()
+    # near eps, split by whether the float32 integer path equals the oracle's
+    # on every day: same-path rows meet the stated 1e-5, flipped-path rows
+    # are counted and reported
+    near_idx = idx[fin][near]
+    same = np.zeros(near_idx.size, dtype=bool)
+    dser = abc.DeviceSeries(s.P, s.T, torch.from_numpy(obs))
+    for q, i in enumerate(near_idx):
+        th_i = abc.sample_prior(1, seed=1, series=c, first=int(i))
+        tr32 = abc.simulate_record(dser, th_i, seed=1, series=c, first=int(i)).cpu().numpy()
+        tr64 = oracle.record(m, th_i.cpu().numpy(), seed=1, series=c, first=int(i))
+        same[q] = np.array_equal(tr32.astype(np.int64), tr64)
+    rel_near = rel[near]
+    assert same.any()
+    assert rel_near[same].max() <= 1e-5, rel_near[same].max()
+    print("country %d: %d accepted, %d checked, near eps %d rows (%d same path, max rel %.2e; "
+          "%d flipped path, max rel %.2e), median rel %.2e, %d exited of %d sampled"
+          % (c, acc.size, idx.size, near_idx.size, same.sum(), rel_near[same].max(),
+             (~same).sum(), rel_near[~same].max() if (~same).any() else 0.0, np.median(rel),
+             ex[np.isin(idx, smp)].sum(), smp.size))
 
 
 def test_batched_64_series_full_size(env):
