@@ -24,21 +24,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "accepted ABC samples/s at fixed ε (sim-days/s, VALU %); plain vs learned proposal"
-# VALU instructions of one simulated day in the float32 kernel, counted from
-# its gfx950 assembly (16 v_mad_u64_u32, 22 transcendental, 119 other; 8 of
-# them look up the lower bound on the days still to come).
-VALU_PER_SAMPLE_DAY = 157
-# The same day step in the batched round kernel, which has no bound lookup.
-BATCH_VALU_PER_SAMPLE_DAY = 149
-# VALU instructions of the once-per-sample steps in both kernels: the prior
-# draw (two Philox calls, uniforms, theta), the initial state and the
-# per-sample part of the day counters, counted in the block that fills a
-# wave's ring (132 instructions, of which 12 register moves are not counted).
-VALU_PER_SAMPLE = 120
-# FP32 operations of one simulated day (FMA = 2, transcendental = 1).
-FP32_FLOP_PER_SAMPLE_DAY = 72
-# Peak VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic work of the float32 simulate kernel, counted class by class in
+# its gfx950 assembly (the blocks of one simulated day, and the block that
+# prepares one sample in a wave's ring). One simulated day: 158 VALU
+# instructions -- 22 transcendental, 16 v_mad_u64_u32 (Philox), 18
+# conversions, 54 integer/bit, 15 FMA, 16 multiplies, 5 adds, 8
+# compares/selects, 4 moves -- not counting the 10 of the lower-bound lookup
+# (an optimisation, not the method's work). One sample: 120 (the prior draw's
+# two Philox calls, theta, the rates, the initial state, the hoisted Philox
+# words; 13 register moves not counted).
+FP32_FLOP_PER_SAMPLE_DAY = 73     # FMA 2, add / multiply / transcendental 1
+FP32_FLOP_PER_SAMPLE = 25
+# VALU issue cost in quad-cycles (one wave64 instruction on a 16-lane SIMD):
+# a transcendental takes 2, every other instruction here 1 (measured on
+# MI355X with a probe of independent chains: v_log/v_exp/v_sqrt/v_rcp/v_sin
+# 2.0, v_fma_f32 1.0, v_mad_u64_u32 + v_xor 2.0, no co-issue of an FMA with
+# a transcendental).
+ISSUE_QC_PER_SAMPLE_DAY = 158 + 22
+ISSUE_QC_PER_SAMPLE = 120
+# The batched round kernel's day step has no bound lookup either.
+BATCH_ISSUE_QC_PER_SAMPLE_DAY = ISSUE_QC_PER_SAMPLE_DAY
+# Issue peak in lane quad-cycles/s: 256 CUs x 4 SIMDs x 64 lanes x 2.4e9 / 4.
+ISSUE_PEAK_T = 256 * 4 * 64 * 2.4e9 / 4 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/csrc/model.hpp",
                "paper_2012_14332_amd/csrc/philox.hpp"]
@@ -66,33 +73,95 @@ def traffic_per_launch():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(countries, eps, first, n_sample):
+VALU_FILE = os.path.join(ROOT, "profiles", "k_simulate_f32_valu.json")
+
+
+def valu_counters():
+    """VALU counters of the simulate kernel from the committed PMC summary
+    (busy fraction, lane utilisation, counter FP32 FLOP per sample-day), or
+    None when the kernel sources changed since they were taken."""
+    try:
+        with open(VALU_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != sim_source_hash():
+        return None
+    return {k: v for k, v in rec.items() if k != "source_hash"}
+
+
+def cpu_baseline(countries, eps, first, n_sample, reps=3):
     """The FP64 oracle on the host cores, on the first n_sample indices of each
-    country's main range, at the same eps."""
+    country's main range, at the same eps; `reps` runs, the median reported."""
     import numpy as np
 
     import oracle
 
-    t_total = 0.0
-    acc = 0
-    days = 0
-    for c, (s, e) in enumerate(zip(countries, eps)):
+    models = []
+    for s in countries:
         m = oracle.make_model(s.P, s.T)
-        obs = oracle.observe(m, s.theta_true, s.obs_seed, series=s.series_id)
-        t0 = time.perf_counter()
-        d = oracle.distances(m, obs, seed=1, n=n_sample, first=first, series=c)
-        t_total += time.perf_counter() - t0
-        acc += int(np.sum(d <= e))
-        days += n_sample * s.T
+        models.append((m, oracle.observe(m, s.theta_true, s.obs_seed, series=s.series_id)))
+    runs = []
+    for r in range(reps):
+        t_total = 0.0
+        acc = 0
+        days = 0
+        for c, ((m, obs), s, e) in enumerate(zip(models, countries, eps)):
+            t0 = time.perf_counter()
+            d = oracle.distances(m, obs, seed=1, n=n_sample, first=first, series=c)
+            t_total += time.perf_counter() - t0
+            acc += int(np.sum(d <= e))
+            days += n_sample * s.T
+        runs.append((acc / t_total, t_total, acc, days))
+    rates = [r[0] for r in runs]
+    med = sorted(runs, key=lambda r: r[0])[len(runs) // 2]
     return {
-        "value": acc / t_total,
+        "value": float(np.median(rates)),
         "unit": "accepted samples/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": "%d prior samples of each country (indices %d..%d), same eps; %d accepted in "
-                  "%.2f s; %.3e trajectories/s, %.3e sample-days/s (no early exit)"
-                  % (n_sample, first, first + n_sample - 1, acc, t_total,
-                     3 * n_sample / t_total, days / t_total),
+                  "%.2f s (median of %d runs); %.3e trajectories/s, %.3e sample-days/s (no early "
+                  "exit)" % (n_sample, first, first + n_sample - 1, med[2], med[1], reps,
+                             3 * n_sample / med[1], med[3] / med[1]),
+        "runs_accepted_per_s": [round(x, 2) for x in rates],
+    }
+
+
+def single_country_leg(args):
+    """The single-country workload: 1e5 prior samples of the P = 1e7, T = 49
+    series, the 100 nearest kept (float32 simulation of every day, device
+    nearest-k, float64 decision of the band around the 100th distance,
+    float64 moments). Timed per run on the host clock around device
+    synchronisation, median and IQR of the repetitions."""
+    import numpy as np
+    import torch
+
+    from paper_2012_14332_amd import pipeline as PL
+    from paper_2012_14332_amd import workloads as W
+
+    s = W.single_country()
+    ser = PL.observed_series(s)
+    n, k = 100_000, 100
+    run = PL.NearestABC(ser, 1, n, k)
+    res = run.run(0)  # warm-up; also the run the parity tests check
+    ms = []
+    for r in range(max(args.reps, 10)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = run.run((r + 1) * n)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    med = float(np.median(ms))
+    return {
+        "workload": "%s: %d prior samples, the %d nearest kept (float64 decision)" % (s.name, n, k),
+        "ms_per_run_median": med,
+        "ms_per_run_iqr": [float(np.percentile(ms, 25)), float(np.percentile(ms, 75))],
+        "runs": len(ms),
+        "kept_per_s": k / (med * 1e-3),
+        "trajectories_per_s": n / (med * 1e-3),
+        "sim_days_per_s": n * s.T / (med * 1e-3),
+        "float64_rows_last_run": int(res.candidates),
     }
 
 
@@ -158,11 +227,12 @@ def batched_leg(args):
         "rounds": st["rounds"],
         "graph_replays": st["graph_replays"],
         "rounds_ms": st["rounds_ms"],
-        # algorithmic VALU rate of the round kernels over the replays' wall time
-        # (host waits between replays included, so a lower bound on the kernel's)
-        "valu_frac_rounds_lower_bound": (BATCH_VALU_PER_SAMPLE_DAY * st["sample_days"] +
-                                         VALU_PER_SAMPLE * used) /
-                                        (st["rounds_ms"] * 1e-3) / (VALU_PEAK_TOPS * 1e12),
+        # algorithmic VALU issue (lane quad-cycles) of the round kernels over the
+        # replays' wall time (host waits between replays included, so a lower
+        # bound on the kernel's own fraction)
+        "issue_frac_rounds_lower_bound": (BATCH_ISSUE_QC_PER_SAMPLE_DAY * st["sample_days"] +
+                                          ISSUE_QC_PER_SAMPLE * used) /
+                                         (st["rounds_ms"] * 1e-3) / (ISSUE_PEAK_T * 1e12),
         "refill_min": tune.get("refill"),
         "rechecked_fp64": st["rechecked"],
         "autotuned_round": tuned_round,
@@ -196,8 +266,12 @@ def learned_leg(args, batched):
     sers = [PL.observed_series(s) for s in ss]
     eps = batched["_eps"]
     # one forward pass for all 64 observed series
+    torch.cuda.synchronize()
+    tf0 = time.perf_counter()
     feats = torch.stack([abc.series_features(ser) for ser in sers])
     mix = net.forward(feats).contiguous()
+    torch.cuda.synchronize()
+    train_total_s = (data_ms + train_ms) * 1e-3 + (time.perf_counter() - tf0)
     Q = args.quota
     kw = dict(round_size=1 << 22, rounds_per_graph=4, cand_capacity=4 * Q, mix=mix, lam=args.lam,
               inflate=args.inflate)
@@ -292,6 +366,14 @@ def learned_leg(args, batched):
         "refill_min": tune["refill"],
         "autotune_top": tune["table"][:5],
         "accepted_per_s": acc / wall,
+        # end to end: the training pairs, the 20 epochs and the one forward pass
+        # of the series' features counted in the learned run's time
+        "train_total_s": train_total_s,
+        "accepted_per_s_incl_training": acc / (wall + train_total_s),
+        # accepted samples per series set beyond which the trained proposal
+        # pays for its training at these rates
+        "break_even_accepted": (train_total_s / (1.0 / batched["accepted_per_s"] - wall / acc)
+                                if acc / wall > batched["accepted_per_s"] else None),
         "ess_per_s": ess / wall,
         "plain_accepted_per_s": batched["accepted_per_s"],
         "gain_accepted_per_s": (acc / wall) / batched["accepted_per_s"],
@@ -489,6 +571,9 @@ def main():
     # speed); about 0.4 s of warm-up steps avoided it
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--samples", type=int, default=10_000_000, help="prior samples per country per step")
+    ap.add_argument("--reps", type=int, default=10, help="timed K-step regions (the first is `value`)")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-single", action="store_true", help="skip the single-country nearest-100 leg")
     ap.add_argument("--band", type=float, default=0.02)
     ap.add_argument("--pilot", type=int, default=100_000)
     ap.add_argument("--q", type=float, default=1e-4)
@@ -589,29 +674,38 @@ def main():
                 sC.wait_event(compacted[c])
                 abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
                 mean, cov = abc.posterior_moments(th, n_dev=cnt)
-            # every output stays referenced until the final synchronisation: the
-            # compaction allocates them on stream B and the band decision uses them
-            # on stream C, so a block freed early could be handed to the next
-            # compaction while the band decision still works on it
+            # the outputs are kept for the accepted counts and the last-step
+            # check; the binding marks every tensor it hands to stream C as in
+            # use there, so dropping them early would be safe as well
             keep.append((c, idx, th, cnt, mean, cov, d))
+
+    def timed_region(s0, ev):
+        """K steps from step s0, bracketed by device synchronisation."""
+        keep = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(s0, s0 + args.steps):
+            step(s, keep, ev)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, sum(int(k[3].item()) for k in keep), keep
 
     keep = []
     for s in range(args.warmup):
         step(s, keep, None)
     torch.cuda.synchronize()
-    keep = []
     ev = []
     days.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.warmup, args.warmup + args.steps):
-        step(s, keep, ev)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    accepted = sum(int(k[3].item()) for k in keep)
-    # the last step again, one country at a time on one stream: the pipelined
-    # step must have accepted exactly the same rows
+    wall, accepted, keep = timed_region(args.warmup, ev)
+    # further repetitions of the same K-step region on fresh sample ranges
+    # (median and interquartile range, as the paper repeats its runs)
+    rep_rates, rep_ms = [accepted / wall], [wall / args.steps * 1e3]
+    for r in range(1, args.reps):
+        w_r, a_r, _ = timed_region(args.warmup + r * args.steps, None)
+        rep_rates.append(a_r / w_r)
+        rep_ms.append(w_r / args.steps * 1e3)
+    # the last step of the first region again, one country at a time on one
+    # stream: the pipelined step must have accepted exactly the same rows
     last_first = first0 + (args.warmup + args.steps - 1) * N
     same_rows = True
     for c, r in enumerate(runs):
@@ -628,9 +722,16 @@ def main():
     avg_ms = float(np.mean(sim_ms))
     days_per_launch = eff_days / launches
     samples_per_launch = N
-    achieved = (VALU_PER_SAMPLE_DAY * days_per_launch + VALU_PER_SAMPLE * samples_per_launch) / \
-        (avg_ms * 1e-3) / 1e12
-    flops = FP32_FLOP_PER_SAMPLE_DAY * days_per_launch / (avg_ms * 1e-3) / 1e12
+    # algorithmic work of one launch over its average duration (HIP events on
+    # the launch stream): FP32 FLOP against the FP32 vector peak, and VALU issue
+    # (transcendentals weighted by their measured cost) against the issue peak
+    flop_launch = FP32_FLOP_PER_SAMPLE_DAY * days_per_launch + FP32_FLOP_PER_SAMPLE * samples_per_launch
+    issue_launch = ISSUE_QC_PER_SAMPLE_DAY * days_per_launch + ISSUE_QC_PER_SAMPLE * samples_per_launch
+    flops = flop_launch / (avg_ms * 1e-3) / 1e12
+    issue = issue_launch / (avg_ms * 1e-3) / 1e12
+    # the FP32 FLOP rate this instruction mix reaches at 100% VALU issue
+    mix_ceiling = flop_launch / issue_launch * ISSUE_PEAK_T
+    valu_pmc = valu_counters()
     traffic = traffic_per_launch()
     per_country = {}
     for c, s in enumerate(countries):
@@ -662,26 +763,40 @@ def main():
             "launch_config": list(abc.get_launch_config()),
             "refill_min": abc.get_refill_min(),
         },
+        "value_median": float(np.median(rep_rates)),
+        "value_iqr": [float(np.percentile(rep_rates, 25)), float(np.percentile(rep_rates, 75))],
+        "ms_per_step_median": float(np.median(rep_ms)),
+        "repetitions": {"n": len(rep_rates), "steps_each": args.steps,
+                        "accepted_per_s": [round(x, 1) for x in rep_rates],
+                        "ms_per_step": [round(x, 4) for x in rep_ms]},
         "trajectories_per_s": traj / wall,
         "last_step_rows_match_single_stream": bool(same_rows),
         "sim_days_per_s_effective": eff_days / wall,
         "sim_days_per_s_nominal": nominal_days / wall,
         "simulate_kernel_ms_avg": avg_ms,
-        "valu_frac": achieved / VALU_PEAK_TOPS,
-        "fp32_flops": {"achieved_tflops": flops, "peak_tflops": FP32_PEAK_TFLOPS,
-                       "frac": flops / FP32_PEAK_TFLOPS},
         "roofline": {
             "bound": "alu",
             "kernel": "k_simulate_f32",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS,
+            "achieved": flops,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": flops / FP32_PEAK_TFLOPS,
             "traffic": traffic,
-            "ops_per_sample_day": VALU_PER_SAMPLE_DAY,
+            "flop_per_sample_day": FP32_FLOP_PER_SAMPLE_DAY,
+            "flop_per_sample": FP32_FLOP_PER_SAMPLE,
             "sample_days_per_launch": days_per_launch,
-            "ops_per_sample": VALU_PER_SAMPLE,
             "samples_per_launch": samples_per_launch,
+            "launch_ms": avg_ms,
+            # the same work in VALU issue: the kernel is bound by instruction
+            # issue, and FP32 arithmetic is a fraction of its instruction mix
+            "mix_ceiling_tflops": mix_ceiling,
+            "mix_ceiling_frac": mix_ceiling / FP32_PEAK_TFLOPS,
+            "frac_of_mix_ceiling": flops / mix_ceiling,
+            "issue": {"unit": "T lane quad-cycles/s", "achieved": issue, "peak": ISSUE_PEAK_T,
+                      "frac": issue / ISSUE_PEAK_T,
+                      "qc_per_sample_day": ISSUE_QC_PER_SAMPLE_DAY,
+                      "qc_per_sample": ISSUE_QC_PER_SAMPLE},
+            "valu_counters": valu_pmc,
         },
         "per_country": per_country,
     }
@@ -701,8 +816,10 @@ def main():
     out["paper_style"] = paper_style_leg(args)
     if not args.no_hbm:
         out["hbm_passes"] = hbm_leg(args)
+    if not args.no_single:
+        out["single_country"] = single_country_leg(args)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples)
+        out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples, args.cpu_reps)
     print(json.dumps(out))
 
 

@@ -180,12 +180,19 @@ def _stream_handle():
 
 
 def _dptr(t: Optional[torch.Tensor]):
+    """Device address of a contiguous device tensor that the library call about to
+    be made uses on the current stream. The tensor is marked as in use by that
+    stream (record_stream), so torch's caching allocator does not hand its memory
+    to other work before the call's kernels have finished, even when the tensor
+    came from another stream and the caller drops it right after the call
+    (a no-op for tensors allocated on the current stream)."""
     if t is None:
         return None
     if not t.is_cuda:
         raise AbcError("expected a device tensor")
     if not t.is_contiguous():
         raise AbcError("expected a contiguous tensor")
+    t.record_stream(torch.cuda.current_stream(t.device))
     return ctypes.c_void_p(t.data_ptr())
 
 

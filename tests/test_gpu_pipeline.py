@@ -86,3 +86,51 @@ def test_overflowed_pass_raises_instead_of_answering(P):
         res.n()
     ok = P.PlainABC(ser, 11, 1e30, 100_000, capacity=100_000).run(0)
     assert ok.n() == 100_000
+
+
+def test_outputs_handed_across_streams_survive_early_release(P):
+    """Compaction on stream B, band decision and moments on stream C that is
+    held back behind a spin kernel, and every tensor dropped right after the
+    calls while stream B allocates and overwrites new tensors of the same
+    sizes: the rows stream C computes equal a one-stream pass, because the
+    binding marks each tensor it hands to a call as in use on that call's
+    stream."""
+    from paper_2012_14332_amd import abc
+
+    s = W.three_countries()[0]
+    ser = P.observed_series(s)
+    eps = P.pilot_eps(ser, 1, n=100_000, q=1e-3, series=0)
+    n, first, w, cap = 1_000_000, 100_000, 0.02, 1 << 14
+    ref = P.PlainABC(ser, 1, eps, n, series=0, band_w=w, capacity=cap).run(first)
+    c_ref = ref.n()
+    sB, sC = torch.cuda.Stream(), torch.cuda.Stream()
+    dist = torch.empty(n, dtype=torch.float32, device="cuda")
+    e_hi = eps * (1 + w)
+    abc.simulate_distance(ser, n, 1, first=first, series=0, eps_exit=e_hi, out=dist)
+    done = torch.cuda.Event()
+    done.record()
+    results = []
+    for rep in range(3):
+        with torch.cuda.stream(sB):
+            sB.wait_event(done)
+            idx, th, d, _, cnt = abc.accept_compact(dist, e_hi, cap, first=first, seed=1, series=0)
+            ready = torch.cuda.Event()
+            ready.record(sB)
+        with torch.cuda.stream(sC):
+            sC.wait_event(ready)
+            torch.cuda._sleep(50_000_000)  # hold stream C back
+            abc.recheck_band(ser, 1, eps, w, idx, th, d, cnt, series=0)
+            mean, _ = abc.posterior_moments(th, n_dev=cnt)
+            idx_c = idx.clone()
+            cnt_c = cnt.clone()
+        del idx, th, d, cnt
+        with torch.cuda.stream(sB):
+            junk = [torch.full((cap,), -3, dtype=torch.int64, device="cuda"),
+                    torch.full((cap, 8), -3.0, device="cuda"), torch.full((cap,), -3.0, device="cuda"),
+                    torch.full((1,), 7, dtype=torch.int64, device="cuda")]
+        results.append((idx_c, cnt_c, mean, junk))
+    torch.cuda.synchronize()
+    for idx_c, cnt_c, mean, _ in results:
+        assert int(cnt_c.item()) == c_ref
+        assert torch.equal(idx_c[:c_ref], ref.idx[:c_ref])
+        assert torch.equal(mean, ref.mean)
