@@ -212,6 +212,28 @@ ABC_API abc_status abc_accept_compact(const float* dist, const float* theta, con
                               int64_t* out_count, void* stream);
 
 /*
+ * abc_accept_compact for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. Same arguments, layout, result and errors; the caller still
+ * passes every input and output. The compaction's scratch (one status word
+ * per tile of 16384 or 65536 samples, plus a ticket) lives in a fixed
+ * library-owned device array of about 128 KiB, which each GPU the library runs
+ * on holds until the process ends; the call makes no hipMalloc, hipFree or
+ * other allocating call, and clears the scratch with a kernel, not a memset.
+ * n is limited to ABC_NOALLOC_COMPACT_MAX_N (larger n: ABC_EINVAL). Every call
+ * on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or host threads) race and must be serialised by the
+ * caller; calls in one stream are ordered and safe.
+ */
+#define ABC_NOALLOC_COMPACT_MAX_N ((int64_t)1 << 30)
+ABC_API abc_status abc_accept_compact_noalloc(const float* dist, const float* theta,
+                                      const float* weight, const abc_prior* prior,
+                                      const abc_stream* st, int64_t n, uint64_t first, float eps,
+                                      int64_t capacity, int64_t* out_idx, float* out_theta,
+                                      float* out_dist, float* out_w, int64_t* out_count,
+                                      void* stream);
+
+/*
  * Posterior mean and covariance of accepted theta in float64 (the summaries
  * the paper reports as posterior averages, Table "t:trajectories").
  *   theta   device float32 [n_max][8], 16-byte aligned; the first n rows are

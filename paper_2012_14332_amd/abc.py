@@ -100,9 +100,10 @@ def lib():
         L.abc_simulate_record.argtypes = [P(_Series), P(_Model), P(_Stream), vp, u64, i64, vp, vp]
         L.abc_accept_compact.argtypes = [vp, vp, vp, P(_Prior), P(_Stream), i64, u64, f32, i64,
                                          vp, vp, vp, vp, vp, vp]
+        L.abc_accept_compact_noalloc.argtypes = L.abc_accept_compact.argtypes
         L.abc_posterior_moments.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         for f in ("abc_sample_prior", "abc_simulate_distance", "abc_simulate_record",
-                  "abc_accept_compact", "abc_posterior_moments"):
+                  "abc_accept_compact", "abc_accept_compact_noalloc", "abc_posterior_moments"):
             getattr(L, f).restype = ctypes.c_int32
         L.abc_recheck_band.argtypes = [P(_Series), P(_Model), P(_Stream), f32, f32, i64, vp, vp,
                                        vp, vp, vp, vp, vp]
@@ -287,6 +288,24 @@ def accept_compact(dist: torch.Tensor, eps: float, capacity: int, *,
                                     _dptr(out_idx), _dptr(out_th), _dptr(out_d), _dptr(out_w),
                                     _dptr(count), _stream_handle()))
     return out_idx, out_th, out_d, out_w, count
+
+
+def accept_compact_noalloc(dist: torch.Tensor, eps: float, out_idx: torch.Tensor,
+                           out_theta: torch.Tensor, out_count: torch.Tensor, *,
+                           out_dist: Optional[torch.Tensor] = None,
+                           out_w: Optional[torch.Tensor] = None,
+                           theta: Optional[torch.Tensor] = None,
+                           weight: Optional[torch.Tensor] = None, first: int = 0, seed: int = 0,
+                           domain: int = 1, series: int = 0, prior: Optional[_Prior] = None):
+    """accept_compact into caller-provided outputs (capacity = out_idx rows), with the
+    library's fixed scratch instead of an allocation."""
+    pr = prior or make_prior()
+    st = make_stream(seed, domain, series)
+    _check(lib().abc_accept_compact_noalloc(_dptr(dist), _dptr(theta), _dptr(weight),
+                                            ctypes.byref(pr), ctypes.byref(st), int(dist.shape[0]),
+                                            int(first), float(eps), int(out_idx.shape[0]),
+                                            _dptr(out_idx), _dptr(out_theta), _dptr(out_dist),
+                                            _dptr(out_w), _dptr(out_count), _stream_handle()))
 
 
 def recheck_band(ser: DeviceSeries, seed: int, eps: float, band_w: float, idx: torch.Tensor,

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "model.hpp"
 
@@ -214,17 +216,59 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
 
 using namespace abc;
 
-extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
-                                         const float* weight, const abc_prior* prior,
-                                         const abc_stream* st, int64_t n, uint64_t first,
-                                         float eps, int64_t capacity, int64_t* out_idx,
-                                         float* out_theta, float* out_dist, float* out_w,
-                                         int64_t* out_count, void* stream)
+// Scratch of the allocation-free entry point: one status word per tile plus
+// the ticket, for at most CT_STATIC_TILES tiles. Every GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device (the array's
+// name is a host-side stand-in, not a device address).
+constexpr int64_t CT_STATIC_TILES = 16384;
+static __device__ __align__(256) unsigned long long scratch[CT_STATIC_TILES + 1];
+
+namespace {
+
+constexpr int CT_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[CT_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+abc_status static_scratch(unsigned long long** out)
+{
+    int dev = 0;
+    ABC_HIP(hipGetDevice(&dev));
+    ABC_REQUIRE(dev >= 0 && dev < CT_MAX_DEVICES, "device %d beyond the library's %d", dev,
+                CT_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return set_error(ABC_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = reinterpret_cast<unsigned long long*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ABC_OK;
+}
+
+int compact_waves(int64_t n) { return n >= CT_BIG_N ? CT_WAVES_BIG : CT_WAVES_SMALL; }
+
+int64_t compact_tiles(int64_t n)
+{
+    const int64_t tile = (int64_t)compact_waves(n) * CT_WAVE_SPAN;
+    return (n + tile - 1) / tile;
+}
+
+// Validates the arguments and fills everything but the scratch words.
+abc_status compact_args(const float* dist, const float* theta, const float* weight,
+                        const abc_prior* prior, const abc_stream* st, int64_t n, uint64_t first,
+                        float eps, int64_t capacity, int64_t* out_idx, float* out_theta,
+                        float* out_dist, float* out_w, int64_t* out_count, CompactArgs& a)
 {
     ABC_REQUIRE(n >= 0 && capacity >= 0, "n and capacity must be >= 0");
     ABC_REQUIRE(out_count != nullptr, "out_count is NULL");
     ABC_REQUIRE(!isnan(eps), "eps is NaN");
-    CompactArgs a{};
+    a = CompactArgs{};
     if (n > 0) {
         ABC_REQUIRE((weight == nullptr) == (out_w == nullptr),
                     "weight and out_w must both be set or both NULL");
@@ -240,16 +284,6 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
             a.series = st->series;
         }
     }
-    const hipStream_t s = as_stream(stream);
-    const int waves = n >= CT_BIG_N ? CT_WAVES_BIG : CT_WAVES_SMALL;
-    const int64_t tile = (int64_t)waves * CT_WAVE_SPAN;
-    const int64_t num_tiles = (n + tile - 1) / tile;
-    // scratch: one status word per tile + the ticket, stream-ordered
-    void* scratch = nullptr;
-    const size_t bytes = sizeof(unsigned long long) * (size_t)(num_tiles + 1);
-    ABC_HIP(hipMallocAsync(&scratch, bytes, s));
-    a.status = reinterpret_cast<unsigned long long*>(scratch);
-    a.ticket = reinterpret_cast<unsigned int*>(a.status + num_tiles);
     a.dist = dist;
     a.theta = theta;
     a.weight = weight;
@@ -262,21 +296,73 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
     a.out_dist = out_dist;
     a.out_w = out_w;
     a.out_count = out_count;
-    a.num_tiles = num_tiles;
-    const int64_t init_n = num_tiles > 0 ? num_tiles : 1;
+    a.num_tiles = compact_tiles(n);
+    return ABC_OK;
+}
+
+// Enqueues the clearing kernel and the compaction on `s`; `words` holds
+// num_tiles + 1 device words (status words, then the ticket).
+abc_status compact_launch(CompactArgs& a, unsigned long long* words, hipStream_t s)
+{
+    a.status = words;
+    a.ticket = reinterpret_cast<unsigned int*>(words + a.num_tiles);
+    const int64_t init_n = a.num_tiles > 0 ? a.num_tiles : 1;
     hipLaunchKernelGGL(k_compact_init, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, s,
-                       a.status, num_tiles, a.ticket, out_count);
+                       a.status, a.num_tiles, a.ticket, a.out_count);
     abc_status rc = check_launch("k_compact_init");
-    if (rc == ABC_OK && num_tiles > 0) {
-        if (waves == CT_WAVES_BIG)
-            hipLaunchKernelGGL((k_compact<CT_WAVES_BIG>), dim3((unsigned)num_tiles),
+    if (rc == ABC_OK && a.num_tiles > 0) {
+        if (compact_waves(a.n) == CT_WAVES_BIG)
+            hipLaunchKernelGGL((k_compact<CT_WAVES_BIG>), dim3((unsigned)a.num_tiles),
                                dim3(64 * CT_WAVES_BIG), 0, s, a);
         else
-            hipLaunchKernelGGL((k_compact<CT_WAVES_SMALL>), dim3((unsigned)num_tiles),
+            hipLaunchKernelGGL((k_compact<CT_WAVES_SMALL>), dim3((unsigned)a.num_tiles),
                                dim3(64 * CT_WAVES_SMALL), 0, s, a);
         rc = check_launch("k_compact");
     }
-    hipError_t e = hipFreeAsync(scratch, s);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
+                                         const float* weight, const abc_prior* prior,
+                                         const abc_stream* st, int64_t n, uint64_t first,
+                                         float eps, int64_t capacity, int64_t* out_idx,
+                                         float* out_theta, float* out_dist, float* out_w,
+                                         int64_t* out_count, void* stream)
+{
+    CompactArgs a;
+    abc_status rc = compact_args(dist, theta, weight, prior, st, n, first, eps, capacity, out_idx,
+                                 out_theta, out_dist, out_w, out_count, a);
+    if (rc) return rc;
+    const hipStream_t s = as_stream(stream);
+    // scratch: one status word per tile + the ticket, stream-ordered
+    void* words = nullptr;
+    const size_t bytes = sizeof(unsigned long long) * (size_t)(a.num_tiles + 1);
+    ABC_HIP(hipMallocAsync(&words, bytes, s));
+    rc = compact_launch(a, reinterpret_cast<unsigned long long*>(words), s);
+    hipError_t e = hipFreeAsync(words, s);
     if (rc == ABC_OK && e != hipSuccess) return set_error(ABC_EHIP, "hipFreeAsync: %s", hipGetErrorString(e));
     return rc;
+}
+
+extern "C" abc_status abc_accept_compact_noalloc(const float* dist, const float* theta,
+                                                 const float* weight, const abc_prior* prior,
+                                                 const abc_stream* st, int64_t n, uint64_t first,
+                                                 float eps, int64_t capacity, int64_t* out_idx,
+                                                 float* out_theta, float* out_dist, float* out_w,
+                                                 int64_t* out_count, void* stream)
+{
+    ABC_REQUIRE(n <= ABC_NOALLOC_COMPACT_MAX_N, "n = %lld exceeds ABC_NOALLOC_COMPACT_MAX_N = %lld",
+                (long long)n, (long long)ABC_NOALLOC_COMPACT_MAX_N);
+    CompactArgs a;
+    abc_status rc = compact_args(dist, theta, weight, prior, st, n, first, eps, capacity, out_idx,
+                                 out_theta, out_dist, out_w, out_count, a);
+    if (rc) return rc;
+    if (a.num_tiles > CT_STATIC_TILES)  // cannot happen below the size limit; kept as a guard
+        return set_error(ABC_EINVAL, "%lld tiles exceed the static scratch of %lld",
+                         (long long)a.num_tiles, (long long)CT_STATIC_TILES);
+    unsigned long long* words = nullptr;
+    if ((rc = static_scratch(&words))) return rc;
+    return compact_launch(a, words, as_stream(stream));
 }
