@@ -47,7 +47,8 @@ BATCH_ISSUE_QC_PER_SAMPLE_DAY = ISSUE_QC_PER_SAMPLE_DAY
 # Issue peak in lane quad-cycles/s: 256 CUs x 4 SIMDs x 64 lanes x 2.4e9 / 4.
 ISSUE_PEAK_T = 256 * 4 * 64 * 2.4e9 / 4 / 1e12
 FP32_PEAK_TFLOPS = 157.3
-SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/csrc/model.hpp",
+SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/csrc/multi.hip",
+               "paper_2012_14332_amd/csrc/bound.hpp", "paper_2012_14332_amd/csrc/model.hpp",
                "paper_2012_14332_amd/csrc/philox.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_f32_traffic.json")
 
@@ -574,6 +575,8 @@ def main():
     ap.add_argument("--reps", type=int, default=10, help="timed K-step regions (the first is `value`)")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-single", action="store_true", help="skip the single-country nearest-100 leg")
+    ap.add_argument("--per-series-launches", action="store_true",
+                    help="one simulate launch per country instead of one for all three")
     ap.add_argument("--band", type=float, default=0.02)
     ap.add_argument("--pilot", type=int, default=100_000)
     ap.add_argument("--q", type=float, default=1e-4)
@@ -620,6 +623,10 @@ def main():
     abc.lib()
     if args.launch:
         abc.set_launch_config(*[int(x) for x in args.launch.split(",")])
+    elif not args.per_series_launches:
+        # the three countries' observed rows and bound tables fill most of a
+        # workgroup's LDS: one 1024-thread workgroup per CU
+        abc.set_launch_config(1, 1024, 1)
     if args.refill_min:
         abc.set_refill_min(args.refill_min)
     if args.copy_calibration_mib:
@@ -636,48 +643,75 @@ def main():
     first0 = args.pilot  # main-run indices follow the pilot prefix
     runs = [PL.PlainABC(ser, 1, e, N, series=c, band_w=args.band) for c, (ser, e) in
             enumerate(zip(sers, eps))]
-    # stream A simulates back to back; stream B compacts each country's
-    # distances as soon as its launch ends (HBM-bound, it overlaps the next
-    # launch); one stream C per country makes its float64 band decision and
-    # moments, so that the countries' band decisions overlap one another
+    # One step: a single launch simulates all three countries' samples (their
+    # 64-sample chunks form one queue, so the launch ends with one tail); then
+    # stream B compacts each country's distances and one stream C per country
+    # makes its float64 band decision and moments. The distance buffers are
+    # double-buffered by step parity, so the next step's launch never waits on
+    # this step's compactions; those and the band decisions run beside it.
+    # (--per-series-launches: one launch per country, each country's compaction
+    # overlapping the next country's launch.)
     sA = torch.cuda.current_stream()
     sB = torch.cuda.Stream()
     sCs = [torch.cuda.Stream() for _ in runs]
     days = torch.zeros(1, dtype=torch.int64, device="cuda")
-    compacted = [None] * len(runs)  # last compaction of each country's distance buffer
+    bufs = [[torch.empty(N, dtype=torch.float32, device="cuda") for _ in runs] for _ in range(2)]
+    compacted = {}  # (parity, country) -> event after the buffer's last compaction
+
+    def finish_country(c, r, first, dist, ready, par, keep):
+        e_hi = r.eps * (1 + r.band_w)
+        with torch.cuda.stream(sB):
+            sB.wait_event(ready)
+            idx, th, d, _, cnt = abc.accept_compact(dist, e_hi, r.cap, first=first,
+                                                    seed=r.seed, series=c)
+            compacted[(par, c)] = torch.cuda.Event()
+            compacted[(par, c)].record(sB)
+        sC = sCs[c]
+        with torch.cuda.stream(sC):
+            sC.wait_event(compacted[(par, c)])
+            abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
+            mean, cov = abc.posterior_moments(th, n_dev=cnt)
+        # kept for the accepted counts and the last-step check; the binding
+        # marks every tensor it hands to stream C as in use there
+        keep.append((c, idx, th, cnt, mean, cov, d))
 
     def step(s, keep, ev):
         first = first0 + s * N
-        for c, r in enumerate(runs):
-            e_hi = r.eps * (1 + r.band_w)
-            if compacted[c] is not None:
-                sA.wait_event(compacted[c])  # the buffer is free once compacted
+        par = s % 2
+        for c in range(len(runs)):
+            if (par, c) in compacted:
+                sA.wait_event(compacted[(par, c)])  # the buffer is free once compacted
+        if not args.per_series_launches:
+            jobs = [{"ser": r.ser, "n": N, "first": first, "series": c,
+                     "eps_exit": r.eps * (1 + r.band_w), "out": bufs[par][c]}
+                    for c, r in enumerate(runs)]
             if ev is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e0.record(sA)
-            abc.simulate_distance(r.ser, N, r.seed, first=first, series=c, eps_exit=e_hi,
-                                  out=r.dist, days=days if ev is not None else None)
+            abc.simulate_distance_multi(jobs, 1, days=days if ev is not None else None)
+            if ev is not None:
+                e1 = torch.cuda.Event(enable_timing=True)
+                e1.record(sA)
+                ev.append((e0, e1, -1))
+            simulated = torch.cuda.Event()
+            simulated.record(sA)
+            for c, r in enumerate(runs):
+                finish_country(c, r, first, bufs[par][c], simulated, par, keep)
+            return
+        for c, r in enumerate(runs):
+            if ev is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e0.record(sA)
+            abc.simulate_distance(r.ser, N, r.seed, first=first, series=c,
+                                  eps_exit=r.eps * (1 + r.band_w), out=bufs[par][c],
+                                  days=days if ev is not None else None)
             if ev is not None:
                 e1 = torch.cuda.Event(enable_timing=True)
                 e1.record(sA)
                 ev.append((e0, e1, c))
             simulated = torch.cuda.Event()
             simulated.record(sA)
-            with torch.cuda.stream(sB):
-                sB.wait_event(simulated)
-                idx, th, d, _, cnt = abc.accept_compact(r.dist, e_hi, r.cap, first=first,
-                                                        seed=r.seed, series=c)
-                compacted[c] = torch.cuda.Event()
-                compacted[c].record(sB)
-            sC = sCs[c]
-            with torch.cuda.stream(sC):
-                sC.wait_event(compacted[c])
-                abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
-                mean, cov = abc.posterior_moments(th, n_dev=cnt)
-            # the outputs are kept for the accepted counts and the last-step
-            # check; the binding marks every tensor it hands to stream C as in
-            # use there, so dropping them early would be safe as well
-            keep.append((c, idx, th, cnt, mean, cov, d))
+            finish_country(c, r, first, bufs[par][c], simulated, par, keep)
 
     def timed_region(s0, ev):
         """K steps from step s0, bracketed by device synchronisation."""
@@ -721,7 +755,7 @@ def main():
     launches = len(sim_ms)
     avg_ms = float(np.mean(sim_ms))
     days_per_launch = eff_days / launches
-    samples_per_launch = N
+    samples_per_launch = N * len(countries) // (launches // args.steps)
     # algorithmic work of one launch over its average duration (HIP events on
     # the launch stream): FP32 FLOP against the FP32 vector peak, and VALU issue
     # (transcendentals weighted by their measured cost) against the issue peak
@@ -776,7 +810,7 @@ def main():
         "simulate_kernel_ms_avg": avg_ms,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_simulate_f32",
+            "kernel": "k_simulate_f32" if args.per_series_launches else "k_simulate_multi_f32",
             "achieved": flops,
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -154,6 +154,45 @@ ABC_API abc_status abc_simulate_distance(const abc_series* ser, const abc_model*
                                  unsigned long long* days, void* stream);
 
 /*
+ * Several series in one persistent launch (Sec. 3.1: many independent
+ * samples in parallel; here the samples of up to ABC_MULTI_MAX series share
+ * one launch instead of one launch per series). Job j simulates samples
+ * first .. first+n-1 of series `ser` on stream (seed, domain, series) with
+ * theta drawn in-kernel from `prior` (as abc_simulate_distance with theta =
+ * NULL), early exit at eps_exit, and writes dist [n] -- bit for bit what
+ * abc_simulate_distance would write for that job. The 64-sample chunks of
+ * all jobs form one queue, longest horizon first, so the launch ends with one
+ * tail of short trajectories instead of one per series.
+ *   jobs    host array [m], 1 <= m <= ABC_MULTI_MAX; each ser->obs device [3][T];
+ *           dist device float32 [n] (NULL allowed when n = 0).
+ *   model   float32 path only: ABC_FP64 and ABC_SUPPORT are rejected.
+ *   days    device uint64 or NULL: += sample-days simulated over all jobs.
+ * The observed rows and the future-days bound tables of all jobs live in the
+ * workgroup's LDS; tables get coarser time blocks (a weaker bound, never a
+ * different distance) when they would not fit, and the launch shape set by
+ * abc_set_launch_config gives the workgroup size and at most blocks_per_cu
+ * resident workgroups per CU (fewer when the LDS allows fewer).
+ * Errors: ABC_EINVAL (m out of range, a job's series, n or eps_exit invalid,
+ * total n > 2^36, unsupported flags), ABC_EUNSUPPORTED (the observed rows
+ * alone exceed the LDS of a workgroup).
+ */
+#define ABC_MULTI_MAX 8
+typedef struct {
+    const abc_series* ser;  /* host struct; ser->obs device [3][T] */
+    uint32_t series;        /* stream series id of the job */
+    uint32_t pad;
+    uint64_t first;         /* first sample index */
+    int64_t n;              /* samples */
+    float eps_exit;         /* early-exit bound (+INF: none) */
+    uint32_t pad2;
+    float* dist;            /* device float32 [n] */
+} abc_sim_job;
+ABC_API abc_status abc_simulate_distance_multi(const abc_sim_job* jobs, int32_t m,
+                                       const abc_model* model, const abc_prior* prior,
+                                       uint64_t seed, uint32_t domain,
+                                       unsigned long long* days, void* stream);
+
+/*
  * Simulate like abc_simulate_distance but record the full integer state
  * (S, I, A, R, D, Ru) of days 0..T: traj is device int32 [n][T+1][6].
  * ser->obs is not read. theta is device float32 [n][8] (required).
@@ -611,6 +650,16 @@ ABC_API abc_status abc_smc_run(const abc_series* ser, const abc_model* model,
                                const abc_smc_config* cfg, int64_t* idx, float* theta, double* w,
                                double* dist, abc_smc_gen_stats* stats, int32_t* gens_done,
                                void* stream);
+
+/* Library scratch. Calls that need device scratch (compaction tiles, moment
+ * partials, band flags, selection histograms, SMC work space) take it from a
+ * library-owned buffer kept per (device, stream): the first calls on a stream
+ * allocate it (growing it synchronises that stream once), later calls reuse it
+ * without allocating, so a steady-state call never waits for the device.
+ * Calls on one stream are ordered and may share it; calls on one stream from
+ * several host threads at once are not supported. abc_release_scratch()
+ * synchronises the current device and frees every such buffer on it. */
+ABC_API abc_status abc_release_scratch(void);
 
 /* Message describing the last non-OK status returned on this thread. */
 ABC_API const char* abc_last_error(void);

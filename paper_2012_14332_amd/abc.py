@@ -50,6 +50,12 @@ class _Model(ctypes.Structure):
     _fields_ = [("noise_scale", ctypes.c_float), ("flags", ctypes.c_uint32)]
 
 
+class _SimJob(ctypes.Structure):
+    _fields_ = [("ser", ctypes.POINTER(_Series)), ("series", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("first", ctypes.c_uint64), ("n", ctypes.c_int64),
+                ("eps_exit", ctypes.c_float), ("pad2", ctypes.c_uint32), ("dist", ctypes.c_void_p)]
+
+
 class _BatchSeries(ctypes.Structure):
     _fields_ = [("P", ctypes.c_int64), ("A0", ctypes.c_int32), ("R0", ctypes.c_int32),
                 ("D0", ctypes.c_int32), ("T", ctypes.c_int32), ("obs", ctypes.c_void_p),
@@ -105,6 +111,9 @@ def lib():
         for f in ("abc_sample_prior", "abc_simulate_distance", "abc_simulate_record",
                   "abc_accept_compact", "abc_accept_compact_noalloc", "abc_posterior_moments"):
             getattr(L, f).restype = ctypes.c_int32
+        L.abc_simulate_distance_multi.argtypes = [P(_SimJob), ctypes.c_int32, P(_Model), P(_Prior),
+                                                  u64, ctypes.c_uint32, vp, vp]
+        L.abc_simulate_distance_multi.restype = ctypes.c_int32
         L.abc_recheck_band.argtypes = [P(_Series), P(_Model), P(_Stream), f32, f32, i64, vp, vp,
                                        vp, vp, vp, vp, vp]
         L.abc_recheck_band.restype = ctypes.c_int32
@@ -252,6 +261,35 @@ def simulate_distance(ser: DeviceSeries, n: int, seed: int, *, theta: Optional[t
                                        float(eps_exit), _dptr(dist), _dptr(d64), _dptr(days),
                                        _stream_handle()))
     return (dist, d64) if want64 else dist
+
+
+def simulate_distance_multi(jobs, seed: int, *, domain: int = 1, flags: int = 0,
+                            noise_scale: float = 1.0, prior: Optional[_Prior] = None,
+                            days: Optional[torch.Tensor] = None, device="cuda"):
+    """One launch for several series. jobs: sequence of dicts with keys ser
+    (DeviceSeries), n, and optionally series (stream series id, default the job's
+    position), first (0), eps_exit (+INF), out (float32 [n] device tensor).
+    Returns the list of distance tensors, each equal to simulate_distance's for
+    that job."""
+    m = len(jobs)
+    arr = (_SimJob * max(m, 1))()
+    sers, outs = [], []
+    for j, jb in enumerate(jobs):
+        n = int(jb["n"])
+        out = jb.get("out")
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.float32, device=device)[:n]
+        cs = jb["ser"].c()
+        sers.append(cs)
+        outs.append(out)
+        arr[j] = _SimJob(ctypes.pointer(cs), int(jb.get("series", j)), 0, int(jb.get("first", 0)), n,
+                         float(jb.get("eps_exit", math.inf)), 0,
+                         _dptr(out) if n > 0 else None)
+    pr = prior or make_prior()
+    md = _Model(float(noise_scale), int(flags))
+    _check(lib().abc_simulate_distance_multi(arr, m, ctypes.byref(md), ctypes.byref(pr), int(seed),
+                                             int(domain), _dptr(days), _stream_handle()))
+    return outs
 
 
 def simulate_record(ser: DeviceSeries, theta: torch.Tensor, seed: int, *, first: int = 0,

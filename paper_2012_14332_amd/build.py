@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabc.so")
-SOURCES = ["runtime.hip", "simulate.hip", "compact.hip", "moments.hip", "batch.hip", "mdn.hip", "bands.hip", "smc.hip", "topk.hip"]
+SOURCES = ["runtime.hip", "simulate.hip", "multi.hip", "compact.hip", "moments.hip", "batch.hip", "mdn.hip", "bands.hip", "smc.hip", "topk.hip"]
 
 # Packed FP32 (v_pk_*_f32) is switched off for all device code.
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -693,10 +693,9 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
                          "samples per lane, not %d", spl);
     const int32_t refill_min = abc_get_refill_min();
     const size_t lds = batch_lds_bytes(m, obs_words, block);
-    int dev = 0, num_cu = 0, max_lds = 0;
-    ABC_HIP(hipGetDevice(&dev));
-    ABC_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    ABC_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    DeviceInfo info;
+    if ((rc = device_info(&info))) return rc;
+    const int num_cu = info.num_cu, max_lds = info.max_lds;
     const size_t static_lds = sizeof(RoundTable);
     if (lds + static_lds > (size_t)max_lds)
         return set_error(ABC_EUNSUPPORTED,

@@ -63,6 +63,29 @@ inline abc_status check_launch(const char* what)
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Compute units and LDS bytes per workgroup of the current device, queried
+// once per device (attribute queries cost tens of microseconds each, too much
+// for a per-launch path).
+struct DeviceInfo {
+    int num_cu = 0;
+    int max_lds = 0;
+};
+abc_status device_info(DeviceInfo* out);
+
+// Library-owned scratch for the kernels a call enqueues on stream s: one
+// device buffer per (device, stream, slot), grown to the largest request and
+// kept (abc_release_scratch frees it). Consecutive calls on one stream reuse
+// a slot's buffer, which stream order makes safe; growing it synchronises s
+// once before the old buffer is freed. Unlike stream-ordered allocation, which
+// on this runtime waits for the device, taking the buffer never blocks the
+// host. Calls that enqueue their kernels and return use slot 0; a call that
+// keeps its own scratch across nested calls on the same stream (the SMC
+// generation around compaction and the band decision) uses higher slots.
+constexpr int SCRATCH_LEAF = 0;
+constexpr int SCRATCH_SMC_WS = 1;
+constexpr int SCRATCH_SMC_SUMS = 2;
+abc_status stream_scratch(hipStream_t s, size_t bytes, void** out, int slot = SCRATCH_LEAF);
+
 // Prior box -> (lo, width) with width = fl32(hi - lo), as the draw uses it.
 inline abc_status prior_lo_width(const abc_prior* prior, float lo[8], float width[8])
 {

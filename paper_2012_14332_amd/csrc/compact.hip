@@ -336,14 +336,11 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
                                  out_theta, out_dist, out_w, out_count, a);
     if (rc) return rc;
     const hipStream_t s = as_stream(stream);
-    // scratch: one status word per tile + the ticket, stream-ordered
+    // scratch: one status word per tile + the ticket, from the stream's buffer
     void* words = nullptr;
     const size_t bytes = sizeof(unsigned long long) * (size_t)(a.num_tiles + 1);
-    ABC_HIP(hipMallocAsync(&words, bytes, s));
-    rc = compact_launch(a, reinterpret_cast<unsigned long long*>(words), s);
-    hipError_t e = hipFreeAsync(words, s);
-    if (rc == ABC_OK && e != hipSuccess) return set_error(ABC_EHIP, "hipFreeAsync: %s", hipGetErrorString(e));
-    return rc;
+    if ((rc = stream_scratch(s, bytes, &words))) return rc;
+    return compact_launch(a, reinterpret_cast<unsigned long long*>(words), s);
 }
 
 extern "C" abc_status abc_accept_compact_noalloc(const float* dist, const float* theta,

@@ -185,9 +185,9 @@ extern "C" abc_status abc_posterior_moments(const float* theta, const float* wei
     const int64_t groups = mom_groups(n_max);  // enough for any device count <= n_max
     void* scratch = nullptr;
     const size_t bytes = sizeof(double) * MOM_NSUM * (size_t)(groups > 0 ? groups : 1);
-    ABC_HIP(hipMallocAsync(&scratch, bytes, s));
+    abc_status rc = stream_scratch(s, bytes, &scratch);
+    if (rc) return rc;
     a.partial = reinterpret_cast<double*>(scratch);
-    abc_status rc = ABC_OK;
     if (groups > 0) {
         hipLaunchKernelGGL(k_moments_partial, dim3((unsigned)groups), dim3(MOM_BLOCK), 0, s, a);
         rc = check_launch("k_moments_partial");
@@ -196,7 +196,5 @@ extern "C" abc_status abc_posterior_moments(const float* theta, const float* wei
         hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64 * MOM_FINAL_SPLIT), 0, s, a);
         rc = check_launch("k_moments_final");
     }
-    hipError_t e = hipFreeAsync(scratch, s);
-    if (rc == ABC_OK && e != hipSuccess) return set_error(ABC_EHIP, "hipFreeAsync: %s", hipGetErrorString(e));
     return rc;
 }

@@ -550,15 +550,6 @@ __global__ __launch_bounds__(256) void k_smc_equal(double* W, int32_t N, double*
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-struct DevBuf {
-    void* p = nullptr;
-    hipStream_t s = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFreeAsync(p, s);
-    }
-};
-
 static abc_status check_cfg(const abc_smc_config* c)
 {
     ABC_REQUIRE(c != nullptr, "config is NULL");
@@ -636,10 +627,9 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
     const size_t o_ess = o_box + 256;
     const size_t o_anc = o_ess + 256;
     const size_t total = o_anc + up(sizeof(int32_t) * cap);
-    DevBuf ws;
-    ws.s = s;
-    ABC_HIP(hipMallocAsync(&ws.p, total, s));
-    char* base = static_cast<char*>(ws.p);
+    void* ws = nullptr;
+    if ((rc = stream_scratch(s, total, &ws, SCRATCH_SMC_WS))) return rc;
+    char* base = static_cast<char*>(ws);
     SmcState* dstate = reinterpret_cast<SmcState*>(base + o_state);
     double* dC = reinterpret_cast<double*>(base + o_C);
     double* dy = reinterpret_cast<double*>(base + o_y);
@@ -771,9 +761,9 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
         if (splits > max_splits) splits = max_splits;
         if (splits < 1) splits = 1;
         const int per = (n_prev + splits - 1) / splits;
-        DevBuf part;
-        part.s = s;
-        ABC_HIP(hipMallocAsync(&part.p, sizeof(double) * (size_t)splits * N, s));
+        void* part = nullptr;
+        if ((rc = stream_scratch(s, sizeof(double) * (size_t)splits * N, &part, SCRATCH_SMC_SUMS)))
+            return rc;
         SumsArgs sa{};
         sa.theta = theta;
         sa.N = N;
@@ -782,7 +772,7 @@ extern "C" abc_status abc_smc_generation(const abc_series* ser, const abc_model*
         sa.Np = n_prev;
         sa.per_split = per;
         sa.st = dstate;
-        sa.partial = static_cast<double*>(part.p);
+        sa.partial = static_cast<double*>(part);
         hipLaunchKernelGGL(k_smc_sums, dim3(bx, splits), dim3(SUMS_BLOCK), 0, s, sa);
         if ((rc = check_launch("k_smc_sums"))) return rc;
         hipLaunchKernelGGL(k_smc_finish, dim3(1), dim3(1024), 0, s, sa.partial, splits, N, w, dess);

@@ -274,15 +274,6 @@ __global__ __launch_bounds__(256) void k_rows_place(const double* d, const int64
         for (int j = 0; j < 8; ++j) out_theta[8 * pos + j] = theta[8 * q + j];
 }
 
-struct DevMem {
-    void* p = nullptr;
-    hipStream_t s = nullptr;
-    ~DevMem()
-    {
-        if (p) (void)hipFreeAsync(p, s);
-    }
-};
-
 static unsigned nk_grid(int64_t n)
 {
     const int64_t g = (n + 255) / 256;
@@ -311,12 +302,14 @@ extern "C" abc_status abc_nearest_k(const float* dist, const float* theta, const
         fa.series = st->series;
     }
     const hipStream_t s = as_stream(stream);
-    DevMem mem;
-    mem.s = s;
+    void* mem = nullptr;
     const size_t ctl_bytes = (sizeof(NkCtl) + 255) & ~(size_t)255;
-    ABC_HIP(hipMallocAsync(&mem.p, ctl_bytes + sizeof(uint64_t) * NK_CAP, s));
-    NkCtl* dc = static_cast<NkCtl*>(mem.p);
-    uint64_t* cand = reinterpret_cast<uint64_t*>(static_cast<char*>(mem.p) + ctl_bytes);
+    {
+        const abc_status rs = stream_scratch(s, ctl_bytes + sizeof(uint64_t) * NK_CAP, &mem);
+        if (rs) return rs;
+    }
+    NkCtl* dc = static_cast<NkCtl*>(mem);
+    uint64_t* cand = reinterpret_cast<uint64_t*>(static_cast<char*>(mem) + ctl_bytes);
     const unsigned grid = nk_grid(n);
     hipLaunchKernelGGL(k_nk_init, dim3(1), dim3(256), 0, s, dc);
     hipLaunchKernelGGL(k_nk_minmax, dim3(grid), dim3(256), 0, s, dist, n, dc);
@@ -411,10 +404,12 @@ extern "C" abc_status abc_nearest_k_rows(const double* dist64, const int64_t* id
     ABC_REQUIRE(n >= 1 && n <= 65536, "n must be in [1, 65536]");
     ABC_REQUIRE(k >= 1 && k <= n, "k must be in [1, n]");
     const hipStream_t s = as_stream(stream);
-    DevMem mem;
-    mem.s = s;
-    ABC_HIP(hipMallocAsync(&mem.p, sizeof(int32_t) * (size_t)n, s));
-    int32_t* rank = static_cast<int32_t*>(mem.p);
+    void* mem = nullptr;
+    {
+        const abc_status rs = stream_scratch(s, sizeof(int32_t) * (size_t)n, &mem);
+        if (rs) return rs;
+    }
+    int32_t* rank = static_cast<int32_t*>(mem);
     const dim3 g((unsigned)((n + 255) / 256)), b(256);
     hipLaunchKernelGGL(k_rows_rank, g, b, 0, s, dist64, idx, n, k, rank);
     abc_status rc = check_launch("k_rows_rank");

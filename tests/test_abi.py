@@ -182,3 +182,27 @@ def test_host_validation_of_limits_and_special_values(built):
         assert L.abc_batch_run(bs, 1, ctypes.byref(pr), ctypes.byref(md), 1, 1, 100, 4096, 1000,
                                0.02, 1, cap, fake, fake, fake, fake, fake, fake, fake,
                                ctypes.byref(bst), None) == -1
+
+
+def test_host_validation_of_the_multi_series_launch(built):
+    """abc_simulate_distance_multi: job count, per-job series and sizes, and
+    the float32-only options are checked on the host."""
+    from paper_2012_14332_amd import abc
+
+    L = abc.lib()
+    pr = abc.make_prior()
+    md = abc._Model(1.0, 0)
+    ser = abc._Series(1000000, 100, 0, 0, 50, 0x1000)
+    bad_ser = abc._Series(1000000, 100, 0, 0, 0, 0x1000)  # T = 0
+    job = lambda s, n=10, e=1.0, d=0x1000: abc._SimJob(ctypes.pointer(s), 0, 0, 0, n, e, 0, d)
+    arr = (abc._SimJob * 9)(*[job(ser) for _ in range(9)])
+    run = lambda a, m, model=md: L.abc_simulate_distance_multi(a, m, ctypes.byref(model),
+                                                               ctypes.byref(pr), 1, 1, None, None)
+    assert run(arr, 0) == -1
+    assert run(arr, 9) == -1                                    # more than ABC_MULTI_MAX
+    assert run((abc._SimJob * 1)(job(bad_ser)), 1) == -1 and b"T = 0" in L.abc_last_error()
+    assert run((abc._SimJob * 1)(job(ser, n=-1)), 1) == -1
+    assert run((abc._SimJob * 1)(job(ser, e=float("nan"))), 1) == -1
+    assert run((abc._SimJob * 1)(job(ser, d=None)), 1) == -1   # n > 0 needs dist
+    assert run((abc._SimJob * 1)(job(ser)), 1, abc._Model(1.0, abc.ABC_FP64)) == -1
+    assert run((abc._SimJob * 1)(job(ser, n=0, d=None)), 1) == 0  # nothing to do
