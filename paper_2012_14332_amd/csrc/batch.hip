@@ -379,7 +379,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
             if (!l.active) continue;
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | (a.domain << 4), l.b1, a.key);
-            float z[5];
+            Noise32 z;
             normals_f32(w, a.nc, z);
             day_step_f32<0>(l.s, l.r, l.invP, z);
             const int32_t X[3] = {l.s.A, l.s.R, l.s.D};

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_mdn_features(FeatArgs a)
     int next = 0;
     for (int t = 1; t <= T; ++t) {
         const uint4 wd = ph.day(((uint32_t)t << 8) | (a.domain << 4), ps.b1, a.key);
-        float z[5];
+        Noise32 z;
         normals_f32(wd, nc, z);
         day_step_f32<0>(s, r, invP, z);
         while (next < 32 && days[next] == t) {

@@ -83,8 +83,6 @@ __device__ __forceinline__ void day_fields(uint4 w, uint32_t f[6])
 // v_sqrt_f32, v_rcp_f32, v_sin/v_cos_f32 which take revolutions).
 // ---------------------------------------------------------------------------
 
-// Standard normals scaled by the noise scale s: the factor enters under the
-// Box-Muller square root, c = -2 ln(2) s^2, so it costs nothing per draw.
 // Final float32 distance from the squared-sum accumulator: one hardware
 // square root (about 1 ulp) times the unit scale (ln 2 for the log2-unit
 // log1p distance, 1 for raw counts).
@@ -93,22 +91,31 @@ __device__ __forceinline__ float finish_distance_f32(float acc, float scale)
     return __builtin_amdgcn_sqrtf(acc) * scale;
 }
 
-__device__ __forceinline__ void normals_f32(uint4 w, float c, float z[5])
+// The five noise draws of one day in Box-Muller form, kept apart: the squared
+// radii scaled by the noise scale s, rr_j = -2 s^2 ln u_{2j} = c log2 u_{2j}
+// with c = -2 ln(2) s^2, and the angles' cosines and sines, tr_k, so that
+// s z_k = sqrt(rr_j) tr_k. A draw then takes its standard deviation and its
+// radius under one square root: sd(h) s z = sqrt(h rr_j) tr_k.
+struct Noise32 {
+    float rr[3];
+    float tr[5];
+};
+
+__device__ __forceinline__ void normals_f32(uint4 w, float c, Noise32& z)
 {
     uint32_t f[6];
     day_fields(w, f);
     float u[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = fmaf((float)f[k], 0x1p-21f, 0x1p-22f);  // exact
-    // -2 s^2 ln u = c log2(u)
-    const float r0 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[0]));
-    const float r1 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[2]));
-    const float r2 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u[4]));
-    z[0] = r0 * __builtin_amdgcn_cosf(u[1]);  // cos(2 pi u1)
-    z[1] = r0 * __builtin_amdgcn_sinf(u[1]);
-    z[2] = r1 * __builtin_amdgcn_cosf(u[3]);
-    z[3] = r1 * __builtin_amdgcn_sinf(u[3]);
-    z[4] = r2 * __builtin_amdgcn_cosf(u[5]);
+    z.rr[0] = c * __builtin_amdgcn_logf(u[0]);
+    z.rr[1] = c * __builtin_amdgcn_logf(u[2]);
+    z.rr[2] = c * __builtin_amdgcn_logf(u[4]);
+    z.tr[0] = __builtin_amdgcn_cosf(u[1]);  // cos(2 pi u1)
+    z.tr[1] = __builtin_amdgcn_sinf(u[1]);
+    z.tr[2] = __builtin_amdgcn_cosf(u[3]);
+    z.tr[3] = __builtin_amdgcn_sinf(u[3]);
+    z.tr[4] = __builtin_amdgcn_cosf(u[5]);
 }
 
 __device__ __forceinline__ float noise_c(float scale)
@@ -116,18 +123,18 @@ __device__ __forceinline__ float noise_c(float scale)
     return -1.38629436111989061883f * scale * scale;
 }
 
-// floor(h + sd z) limited to [0, avail] (z already carries the noise scale).
-// For x >= 0 the float->int conversion truncates, which is the floor, and
-// the clamp at 0 absorbs negative x, so no separate floor is needed. The
-// float is limited below 2^31 before the conversion and the integer is then
-// limited to avail, so a float rounding of avail cannot leak into the count.
-// Rates are non-negative, so h >= 0 and sd is finite.
+// floor(h + sd(h) s z) limited to [0, avail], with s z = sqrt(rr) tr: the
+// standard deviation sqrt(h) (h^(1/4) read literally) and the radius share one
+// square root. For x >= 0 the float->int conversion truncates, which is the
+// floor, and the clamp at 0 absorbs negative x, so no separate floor is
+// needed. The float is limited below 2^31 before the conversion and the
+// integer is then limited to avail, so a float rounding of avail cannot leak
+// into the count. Rates are non-negative, so h >= 0 and the root is finite.
 template <int NOISE>
-__device__ __forceinline__ int32_t draw_f32(float h, float z, int32_t avail)
+__device__ __forceinline__ int32_t draw_f32(float h, float rr, float tr, int32_t avail)
 {
-    float sd = __builtin_amdgcn_sqrtf(h);
-    if (NOISE == 1) sd = __builtin_amdgcn_sqrtf(sd);
-    const float x = fmaf(sd, z, h);
+    const float v = NOISE == 1 ? __builtin_amdgcn_sqrtf(h) * rr : h * rr;
+    const float x = fmaf(__builtin_amdgcn_sqrtf(v), tr, h);
     const float f = __builtin_amdgcn_fmed3f(x, 0.0f, 2147483520.0f);
     return min((int32_t)f, avail);
 }
@@ -143,7 +150,7 @@ __device__ __forceinline__ RatesF rates_f32(const Theta& t)
 
 template <int NOISE>
 __device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float invP,
-                                             const float z[5])
+                                             const Noise32& z)
 {
     const float M = (float)(s.A + s.R + s.D);
     const float pw = __builtin_amdgcn_exp2f(r.n * __builtin_amdgcn_logf(M));
@@ -155,11 +162,11 @@ __device__ __forceinline__ void day_step_f32(State& s, const RatesF& r, float in
     const float h3 = r.be * Af;
     const float h4 = r.de * Af;
     const float h5 = r.bh * If;
-    const int32_t n1 = draw_f32<NOISE>(h1, z[0], s.S);
-    const int32_t n2 = draw_f32<NOISE>(h2, z[1], s.I);
-    const int32_t n3 = draw_f32<NOISE>(h3, z[2], s.A);
-    const int32_t n4 = draw_f32<NOISE>(h4, z[3], s.A - n3);
-    const int32_t n5 = draw_f32<NOISE>(h5, z[4], s.I - n2);
+    const int32_t n1 = draw_f32<NOISE>(h1, z.rr[0], z.tr[0], s.S);
+    const int32_t n2 = draw_f32<NOISE>(h2, z.rr[0], z.tr[1], s.I);
+    const int32_t n3 = draw_f32<NOISE>(h3, z.rr[1], z.tr[2], s.A);
+    const int32_t n4 = draw_f32<NOISE>(h4, z.rr[1], z.tr[3], s.A - n3);
+    const int32_t n5 = draw_f32<NOISE>(h5, z.rr[2], z.tr[4], s.I - n2);
     s.S -= n1;
     s.I += n1 - n2 - n5;
     s.A += n2 - n3 - n4;

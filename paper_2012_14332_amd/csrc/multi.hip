@@ -161,9 +161,11 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
     const uint32_t wdom = a.domain << 4;
 
     // the chunk in the ring (wave-uniform): its series, the offset of its
-    // first sample in that series, and the series' sample count
+    // first sample in that series, and how many of its 64 positions hold a
+    // sample (fewer only in a series' last chunk)
     int cur_ls = 0;
-    int64_t cur_base = 0, cur_n = 0;
+    int64_t cur_base = 0;
+    uint32_t cur_valid = 0;
     // chunk c into the ring: series by the chunk ranges
     auto fill = [&](int64_t c) {
         int ls = 0;
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
         const MSeries& sj = a.s[ls];
         cur_ls = ls;
         cur_base = (c - sj.chunk0) << 6;
-        cur_n = sj.n;
+        cur_valid = (uint32_t)min(sj.n - cur_base, (int64_t)64);
         const int64_t k = cur_base + lane;
         MSlot& sl = ring[lane];
         if (k < sj.n) {
@@ -198,7 +200,11 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
     uint32_t days_done = 0;
 
     while (true) {
-        uint64_t m = __ballot(!l.active);
+        // refill: the idle lanes take the next queue positions in lane order,
+        // once at least refill_min of them are idle; a pass may span the end
+        // of one chunk and the start of the next
+        bool want = !l.active;
+        uint64_t m = __ballot(want);
         if (__popcll(m) >= a.refill_min) {
             while (m != 0ull && qb < Q) {
                 const uint32_t jc = qb >> 6;
@@ -206,40 +212,41 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
                     fill(wg + (int64_t)jc * nw);
                     filled = jc;
                 }
-                const uint32_t avail = 64u - (qb & 63u);
-                const bool inm = (m >> lane) & 1ull;
-                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                const bool take = inm && rank < avail;
-                const int64_t k = cur_base + (int64_t)((qb & 63u) + rank);
-                if (take && k < cur_n) {
-                    const MSlot sl = ring[(qb & 63u) + rank];
-                    {
-                        const SerLds e = ser[cur_ls];
-                        l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
-                        l.s.A = e.A0; l.s.R = e.R0; l.s.D = e.D0; l.s.Ru = 0;
-                        l.s.I = sl.i0;
-                        l.s.S = e.room - sl.i0;
-                        l.ph.c1base = sl.c1base; l.ph.g3 = sl.g3; l.ph.h3 = sl.h3; l.ph.f3 = sl.f3;
-                        l.k = k;
-                        l.ls = cur_ls;
-                        l.T = e.T; l.obs_off = e.obs_off; l.tab_r = e.tab_r; l.tab_d = e.tab_d;
-                        l.lb_sh = e.lb_sh; l.invP = e.invP; l.exitb = e.exitb; l.b1 = e.b1;
-                        l.t = 1;
-                        l.acc = 0.0f;
-                        l.comp = 0.0f;
-                        l.active = true;
-                    }
+                const uint32_t off = qb & 63u;
+                const uint32_t avail = 64u - off;
+                // lanes of m below this one
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const bool take = want && rank < avail;
+                const uint32_t pos = off + rank;
+                if (take && pos < cur_valid) {
+                    const MSlot sl = ring[pos];
+                    const SerLds e = ser[cur_ls];
+                    l.r = RatesF{sl.a0, sl.al, sl.n, sl.be, sl.ga, sl.de, sl.bh};
+                    l.s.A = e.A0; l.s.R = e.R0; l.s.D = e.D0; l.s.Ru = 0;
+                    l.s.I = sl.i0;
+                    l.s.S = e.room - sl.i0;
+                    l.ph.c1base = sl.c1base; l.ph.g3 = sl.g3; l.ph.h3 = sl.h3; l.ph.f3 = sl.f3;
+                    l.k = cur_base + (int64_t)pos;
+                    l.ls = cur_ls;
+                    l.T = e.T; l.obs_off = e.obs_off; l.tab_r = e.tab_r; l.tab_d = e.tab_d;
+                    l.lb_sh = e.lb_sh; l.invP = e.invP; l.exitb = e.exitb; l.b1 = e.b1;
+                    l.t = 1;
+                    l.acc = 0.0f;
+                    l.comp = 0.0f;
+                    l.active = true;
                 }
+                want = want && !take;
                 const uint32_t cnt = (uint32_t)__popcll(m);
-                qb = __builtin_amdgcn_readfirstlane(qb + (cnt < avail ? cnt : avail));
-                m = __ballot(inm && !take);
+                qb += cnt < avail ? cnt : avail;
+                m = __ballot(want);
             }
         }
         if (__ballot(l.active) == 0ull && qb >= Q) break;
         if (l.active) {
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | wdom, l.b1, a.key);
-            float z[5];
+            Noise32 z;
             normals_f32(w, nc, z);
             day_step_f32<NOISE>(l.s, l.r, l.invP, z);
             const int32_t X[3] = {l.s.A, l.s.R, l.s.D};

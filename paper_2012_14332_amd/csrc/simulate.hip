@@ -241,7 +241,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
             if (!l.active) continue;
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | wdom, ps.b1, a.key);
-            float z[5];
+            Noise32 z;
             normals_f32(w, nc, z);
             day_step_f32<NOISE>(l.s, l.r, invP, z);
             const int32_t X[3] = {l.s.A, l.s.R, l.s.D};
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(SIM_BLOCK) void k_record(SimArgs a)
             normals_f64(w, z);
             day_step_f64<NOISE>(s, th, (double)a.P, (double)a.scale, z);
         } else {
-            float z[5];
+            Noise32 z;
             normals_f32(w, nc, z);
             day_step_f32<NOISE>(s, r, invP, z);
         }
