@@ -314,40 +314,38 @@ def learned_leg(args, batched):
     ess = float(ess_series.sum())
     used = lb["used"].cpu().numpy()
     samples = int(used.sum())
-    # posterior comparison against plain ABC at the same eps with Qc accepted each
-    # posterior check: independent runs on other seeds pooled, >= 1e4 plain
-    # accepts and >= 1e4 effective learned samples per series, weighted moments
-    # of the pooled rows by the same FP64 moments kernel
+    # posterior comparison against plain ABC at the same eps: both sides pool
+    # runs of Qc accepted per series on further seeds until the learned ESS is
+    # >= 1e4 and the 5 % criterion is resolved at four standard errors (the
+    # posteriors of some series are heavy-tailed, so their sds need far more
+    # samples than 1e4 to be known to 5 %)
     Qc = args.compare_quota
     cap_c = min(2 * Qc, 8192)  # the finalisation sorts the candidates of a series in LDS
 
-    def pooled(runs_kw, seeds):
-        th, ww = [], []
-        for sd in seeds:
-            o = abc.batch_run(sers, eps, sd, Qc, round_size=1 << 22, cand_capacity=cap_c, **runs_kw)
-            th.append(o["theta"])
-            ww.append(o["w"] if "w" in o else torch.ones((len(sers), Qc), device="cuda"))
-        th = torch.cat(th, dim=1)
-        ww = torch.cat(ww, dim=1)
-        mean = np.zeros((len(sers), 8))
-        sd_ = np.zeros((len(sers), 8))
-        ess_ = np.zeros(len(sers))
-        for j in range(len(sers)):
-            m_, c_ = abc.posterior_moments(th[j].contiguous(), ww[j].contiguous())
-            mean[j] = m_.cpu().numpy()
-            sd_[j] = np.sqrt(np.maximum(np.diag(c_.cpu().numpy()), 0))
-            wj = ww[j].double().cpu().numpy()
-            ess_[j] = wj.sum() ** 2 / (wj * wj).sum()
-        return mean, sd_, ess_
+    def sampler(runs_kw):
+        def run(seed, idxs):
+            o = abc.batch_run([sers[j] for j in idxs], [eps[j] for j in idxs], seed, Qc,
+                              series_ids=idxs, round_size=1 << 22, cand_capacity=cap_c,
+                              **({k: (v[idxs].contiguous() if k == "mix" else v)
+                                  for k, v in runs_kw.items()}))
+            th = o["theta"].cpu().numpy().astype(np.float64)
+            w = (o["w"].double().cpu().numpy() if "w" in o else np.ones((len(idxs), Qc)))
+            return th, w
+        return run
 
-    pm, psd, pn = pooled({}, args.compare_seeds_plain)
-    lkw = dict(mix=mix, lam=args.lam, inflate=args.inflate)
-    lm, lsd, ess_c = pooled(lkw, args.compare_seeds_learned)
-    tol_mu = 0.05 * np.maximum(np.abs(pm), psd)
-    ok_mu = np.abs(lm - pm) <= tol_mu
-    ok_sd = np.abs(lsd - psd) <= 0.05 * psd
-    worst_mu = (np.abs(lm - pm) / tol_mu).max(1)
-    worst_sd = (np.abs(lsd - psd) / (0.05 * psd)).max(1)
+    torch.cuda.synchronize()
+    tc0 = time.perf_counter()
+    cmp_ = PL.compare_posteriors(sers, eps, sampler({}),
+                                 sampler(dict(mix=mix, lam=args.lam, inflate=args.inflate)),
+                                 quota=Qc, seeds_a=args.compare_seeds_plain,
+                                 seeds_b=args.compare_seeds_learned, max_runs=args.compare_max_runs)
+    compare_s = time.perf_counter() - tc0
+    worst_mu = np.array([r["mean_ratio"] for r in cmp_])
+    worst_sd = np.array([r["sd_ratio"] for r in cmp_])
+    ok_mu = np.array([r["mean_ok"] for r in cmp_])
+    ok_sd = np.array([r["sd_ok"] for r in cmp_])
+    ess_c = np.array([r["ess_b"] for r in cmp_])
+    pn = np.array([r["ess_a"] for r in cmp_])
     gains = [(Q / u) / (Q / pu) for u, pu in zip(used, batched["_used"])]
     net.close()
     abc.set_launch_config(*prev_shape)
@@ -385,10 +383,18 @@ def learned_leg(args, batched):
         "ess_median": float(np.median(ess_series)),
         "wall_s": wall,
         "samples": samples,
-        "posterior_check": "plain: %d seeds x %d accepted per series pooled; learned: %d seeds x %d "
-                           "accepted pooled (weights kept)" % (len(args.compare_seeds_plain), Qc,
-                                                               len(args.compare_seeds_learned), Qc),
+        "posterior_check": "runs of %d accepted per series pooled on further seeds until the learned "
+                           "ESS >= 1e4 and every difference's standard error (from the samples' second "
+                           "and fourth moments) is <= 1/4 of its 5%% tolerance, at most %d runs a side"
+                           % (Qc, args.compare_max_runs),
+        "posterior_check_s": compare_s,
         "posterior_check_plain_n": int(pn.min()),
+        "posterior_check_runs_max": [int(max(r["runs_a"] for r in cmp_)),
+                                     int(max(r["runs_b"] for r in cmp_))],
+        "posterior_check_resolved_series": int(sum(r["se_over_tol"] * 4 <= 1.0 for r in cmp_)),
+        "posterior_check_se_over_tol_max": float(max(r["se_over_tol"] for r in cmp_)),
+        "posterior_check_unresolved_series": [j for j, r in enumerate(cmp_) if r["se_over_tol"] * 4 > 1.0],
+        "posterior_check_runs_per_series": [[int(r["runs_a"]), int(r["runs_b"])] for r in cmp_],
         "posterior_check_ess_median": float(np.median(ess_c)),
         "posterior_check_ess_min": float(ess_c.min()),
         "posterior_worst_mean_over_tol_per_series": [round(float(x), 3) for x in worst_mu],
@@ -594,6 +600,7 @@ def main():
     ap.add_argument("--compare-quota", type=int, default=4096)
     ap.add_argument("--compare-seeds-plain", type=int, nargs="+", default=[2, 3, 4])
     ap.add_argument("--compare-seeds-learned", type=int, nargs="+", default=[2, 3, 4, 5])
+    ap.add_argument("--compare-max-runs", type=int, default=400)
     ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")
     ap.add_argument("--no-smc", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the compaction/moments bandwidth leg")

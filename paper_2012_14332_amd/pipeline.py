@@ -249,3 +249,98 @@ def predictive_bands(s: W.Series, theta: torch.Tensor, horizon: int = 120, seed:
     traj = abc.simulate_record(ser, theta.contiguous(), seed, domain=DOMAIN_PROJECTION,
                                series=s.series_id, flags=flags)
     return traj, abc.trajectory_bands(traj, quantiles)
+
+
+# ----------------------------------------------------------------------------
+# posterior agreement of two ABC samplers (measurement, not the hot path)
+# ----------------------------------------------------------------------------
+def _weighted_summary(theta: np.ndarray, w: np.ndarray):
+    """Weighted mean and sd (reliability-weight variance, as the moments kernel
+    forms it) of rows theta [n, 8], the Kish effective size, and standard
+    errors of the mean and of the sd from the sample's own second and fourth
+    central moments: SE(mean) = sd / sqrt(ess), SE(sd) = sd sqrt((k - 1) / (4 ess))
+    with k the kurtosis (delta method for the square root of the variance)."""
+    w = w / w.sum()
+    ess = 1.0 / float((w * w).sum())
+    m = (w[:, None] * theta).sum(0)
+    c = theta - m
+    m2 = (w[:, None] * c * c).sum(0)
+    m4 = (w[:, None] * c ** 4).sum(0)
+    sd = np.sqrt(m2 / max(1.0 - 1.0 / ess, 1e-12))
+    kurt = m4 / np.maximum(m2 * m2, 1e-300)
+    se_m = sd / np.sqrt(ess)
+    se_sd = sd * np.sqrt(np.maximum(kurt - 1.0, 0.0) / (4.0 * ess))
+    return m, sd, ess, se_m, se_sd
+
+
+def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2, 3, 4),
+                       seeds_b=(2, 3, 4), max_runs: int = 48, resolution: float = 4.0,
+                       min_ess: float = 1e4, rel: float = 0.05):
+    """Posterior mean and sd of sampler B against sampler A, series by series
+    (the learned-proposal criterion: per parameter |dmean| <= rel max(|mean_A|,
+    sd_A) and |dsd| <= rel sd_A). run_a(seed, idxs) and run_b(seed, idxs) return
+    (theta [len(idxs), quota, 8], weights [len(idxs), quota]) as host arrays for
+    the series idxs. Each side pools runs on further seeds, series by series,
+    until B's effective size is at least min_ess and the standard error of every
+    difference is at most tolerance / resolution -- the criterion is then
+    decided at `resolution` standard errors rather than at Monte Carlo noise --
+    or until max_runs runs. Returns per-series records."""
+    m = len(sers)
+    pools = {"a": [[[], []] for _ in range(m)], "b": [[[], []] for _ in range(m)]}
+    next_seed = {"a": list(seeds_a), "b": list(seeds_b)}
+    # further runs take fresh seeds per side (so no series sees a seed twice)
+    extra = {"a": 100, "b": 200}
+    runs = {"a": [0] * m, "b": [0] * m}
+
+    def pull(side, idxs):
+        if not idxs:
+            return
+        fn = run_a if side == "a" else run_b
+        seq = next_seed[side]
+        if seq:
+            seed = seq.pop(0)
+        else:
+            seed = extra[side]
+            extra[side] += 1
+        th, w = fn(seed, idxs)
+        for q, j in enumerate(idxs):
+            pools[side][j][0].append(th[q])
+            pools[side][j][1].append(w[q])
+            runs[side][j] += 1
+
+    for _ in range(max(len(seeds_a), len(seeds_b))):
+        pull("a", list(range(m)) if next_seed["a"] else [])
+        pull("b", list(range(m)) if next_seed["b"] else [])
+    out = [None] * m
+    todo = list(range(m))
+    while todo:
+        need_a, need_b = [], []
+        for j in todo:
+            sa = _weighted_summary(np.concatenate(pools["a"][j][0]), np.concatenate(pools["a"][j][1]))
+            sb = _weighted_summary(np.concatenate(pools["b"][j][0]), np.concatenate(pools["b"][j][1]))
+            tol_m = rel * np.maximum(np.abs(sa[0]), sa[1])
+            tol_s = rel * sa[1]
+            se_dm = np.sqrt(sa[3] ** 2 + sb[3] ** 2)
+            se_ds = np.sqrt(sa[4] ** 2 + sb[4] ** 2)
+            res = max(float((se_dm / tol_m).max()), float((se_ds / tol_s).max()))
+            out[j] = {"mean_ratio": float((np.abs(sb[0] - sa[0]) / tol_m).max()),
+                      "sd_ratio": float((np.abs(sb[1] - sa[1]) / tol_s).max()),
+                      "se_over_tol": res, "ess_a": sa[2], "ess_b": sb[2],
+                      "runs_a": runs["a"][j], "runs_b": runs["b"][j],
+                      "mean_ok": [bool(x) for x in np.abs(sb[0] - sa[0]) <= tol_m],
+                      "sd_ok": [bool(x) for x in np.abs(sb[1] - sa[1]) <= tol_s]}
+            if res * resolution <= 1.0 and sb[2] >= min_ess:
+                continue
+            # pool on the side whose standard errors dominate (both if close)
+            va = max(float((sa[3] / tol_m).max()), float((sa[4] / tol_s).max()))
+            vb = max(float((sb[3] / tol_m).max()), float((sb[4] / tol_s).max()))
+            if (vb >= 0.5 * va or sb[2] < min_ess) and runs["b"][j] < max_runs:
+                need_b.append(j)
+            if va >= 0.5 * vb and runs["a"][j] < max_runs:
+                need_a.append(j)
+        if not need_a and not need_b:
+            break
+        pull("a", need_a)
+        pull("b", need_b)
+        todo = sorted(set(need_a) | set(need_b))
+    return out
