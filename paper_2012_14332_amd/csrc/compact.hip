@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
         const float4* p = reinterpret_cast<const float4*>(a.dist + wbase) + lane;
         float4 v[CT_STEPS];
 #pragma unroll
-        for (int q = 0; q < CT_STEPS; ++q) v[q] = p[64 * q];
+        for (int q = 0; q < CT_STEPS; ++q) v[q] = load_stream(p + 64 * q);
 #pragma unroll
         for (int q = 0; q < CT_STEPS; ++q) {
             const uint64_t m = (uint64_t)(v[q].x <= a.eps) | ((uint64_t)(v[q].y <= a.eps) << 1) |
@@ -209,6 +209,152 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
             ++r;
         }
         r0 += __builtin_amdgcn_readlane(incl, 63);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass compaction (abc_accept_compact). Each wavefront owns a unit of
+// CP_SPAN consecutive samples. Pass 1 streams the unit's distances once and,
+// with no dependency on any other wavefront, counts its accepted samples and
+// keeps the unit offsets of the first CP_SLOTS of them in sample order. A
+// single workgroup then forms the exclusive prefix of the unit counts, and
+// pass 2 writes each unit's rows at its prefix: from the kept offsets, or --
+// for a unit holding more than CP_SLOTS accepts -- by streaming the unit
+// again. Rows come out in sample-index order, exactly as from the look-back
+// kernel above; the streaming pass has no ticket and no look-back to wait on.
+// ---------------------------------------------------------------------------
+constexpr int CP_CHUNKS = 16;                        // 4096-sample steps per unit
+constexpr int64_t CP_SPAN = (int64_t)CT_WAVE_SPAN * CP_CHUNKS;  // 65536 samples
+constexpr int CP_SLOTS = 64;                         // accepted offsets kept per unit
+constexpr int CP_WAVES = 4;                          // wavefronts per workgroup
+
+struct CpArgs {
+    CompactArgs a;
+    int64_t units;
+    uint32_t* cnt;   // [units]
+    uint32_t* slot;  // [units][CP_SLOTS]
+    int64_t* pref;   // [units]
+};
+
+// Accept mask of one 4096-sample step of a unit: bit 4 q + c for sample
+// s0 + 256 q + 4 lane + c.
+__device__ __forceinline__ uint64_t step_mask(const CompactArgs& a, int64_t s0, int lane)
+{
+    uint64_t bits = 0;
+    if (s0 + CT_WAVE_SPAN <= a.n) {
+        const float4* p = reinterpret_cast<const float4*>(a.dist + s0) + lane;
+        float4 v[CT_STEPS];
+#pragma unroll
+        for (int q = 0; q < CT_STEPS; ++q) v[q] = load_stream(p + 64 * q);
+#pragma unroll
+        for (int q = 0; q < CT_STEPS; ++q) {
+            const uint64_t m = (uint64_t)(v[q].x <= a.eps) | ((uint64_t)(v[q].y <= a.eps) << 1) |
+                               ((uint64_t)(v[q].z <= a.eps) << 2) | ((uint64_t)(v[q].w <= a.eps) << 3);
+            bits |= m << (4 * q);
+        }
+    } else {
+        for (int q = 0; q < CT_STEPS; ++q)
+            for (int c = 0; c < 4; ++c) {
+                const int64_t k = s0 + 256 * q + 4 * lane + c;
+                if (k < a.n && a.dist[k] <= a.eps) bits |= 1ull << (4 * q + c);
+            }
+    }
+    return bits;
+}
+
+// Visits the accepted samples of one step in sample order: f(k, r) for the
+// r-th accept of the unit (r counted from r0). Returns the step's count.
+template <typename F>
+__device__ __forceinline__ int step_visit(uint64_t bits, int64_t s0, int lane, int64_t r0, F f)
+{
+    int64_t r = r0;
+    for (int q = 0; q < CT_STEPS; ++q) {
+        const uint32_t m = (uint32_t)(bits >> (4 * q)) & 15u;
+        if (__ballot(m != 0u) == 0ull) continue;
+        const int c = __popc(m);
+        const int incl = wave_incl_scan_i32(c, lane);
+        int64_t rr = r + (incl - c);
+        for (uint32_t mm = m; mm != 0u; mm &= mm - 1u) {
+            f(s0 + 256 * q + 4 * lane + (__ffs(mm) - 1), rr);
+            ++rr;
+        }
+        r += __builtin_amdgcn_readlane(incl, 63);
+    }
+    return (int)(r - r0);
+}
+
+__global__ __launch_bounds__(64 * CP_WAVES) void k_cp_count(CpArgs p)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
+    if (u >= p.units) return;
+    const int64_t start = u * CP_SPAN;
+    uint32_t* slot = p.slot + u * CP_SLOTS;
+    int64_t total = 0;
+    for (int j = 0; j < CP_CHUNKS; ++j) {
+        const int64_t s0 = start + (int64_t)j * CT_WAVE_SPAN;
+        if (s0 >= p.a.n) break;
+        const uint64_t bits = step_mask(p.a, s0, lane);
+        if (__ballot(bits != 0ull) == 0ull) continue;
+        total += step_visit(bits, s0, lane, total, [&](int64_t k, int64_t r) {
+            if (r < CP_SLOTS) slot[r] = (uint32_t)(k - start);
+        });
+    }
+    if (lane == 0) p.cnt[u] = (uint32_t)total;
+}
+
+// Exclusive prefix of the unit counts in one workgroup of 1024 threads:
+// thread t sums a contiguous block of units, the block sums are scanned in
+// LDS, then each thread writes its block's prefixes in order.
+__global__ __launch_bounds__(1024) void k_cp_scan(CpArgs p)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (p.units + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = b0 + per < p.units ? b0 + per : p.units;
+    int64_t sum = 0;
+    for (int64_t b = b0; b < b1; ++b) sum += p.cnt[b];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int64_t b = b0; b < b1; ++b) {
+        p.pref[b] = run;
+        run += p.cnt[b];
+    }
+    if (t == 1023) *p.a.out_count = part[1023];
+}
+
+__global__ __launch_bounds__(64 * CP_WAVES) void k_cp_emit(CpArgs p)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
+    if (u >= p.units) return;
+    const uint32_t c = p.cnt[u];
+    if (c == 0) return;
+    const int64_t base = p.pref[u];
+    if (base >= p.a.capacity) return;
+    const int64_t start = u * CP_SPAN;
+    if (c <= (uint32_t)CP_SLOTS) {
+        for (uint32_t j = lane; j < c; j += 64)
+            emit_row(p.a, start + p.slot[u * CP_SLOTS + j], base + j);
+        return;
+    }
+    // more accepts than kept offsets: stream the unit again, in order
+    int64_t total = 0;
+    for (int j = 0; j < CP_CHUNKS; ++j) {
+        const int64_t s0 = start + (int64_t)j * CT_WAVE_SPAN;
+        if (s0 >= p.a.n || base + total >= p.a.capacity) break;
+        const uint64_t bits = step_mask(p.a, s0, lane);
+        if (__ballot(bits != 0ull) == 0ull) continue;
+        total += step_visit(bits, s0, lane, total, [&](int64_t k, int64_t r) {
+            emit_row(p.a, k, base + r);
+        });
     }
 }
 
@@ -336,11 +482,31 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
                                  out_theta, out_dist, out_w, out_count, a);
     if (rc) return rc;
     const hipStream_t s = as_stream(stream);
-    // scratch: one status word per tile + the ticket, from the stream's buffer
-    void* words = nullptr;
-    const size_t bytes = sizeof(unsigned long long) * (size_t)(a.num_tiles + 1);
-    if ((rc = stream_scratch(s, bytes, &words))) return rc;
-    return compact_launch(a, reinterpret_cast<unsigned long long*>(words), s);
+    // two passes; scratch (unit counts, kept offsets, prefixes) from the
+    // stream's buffer
+    CpArgs p{};
+    p.a = a;
+    p.units = (n + CP_SPAN - 1) / CP_SPAN;
+    const int64_t units = p.units > 0 ? p.units : 1;
+    void* mem = nullptr;
+    const size_t bytes = sizeof(int64_t) * (size_t)units + sizeof(uint32_t) * (size_t)units +
+                         sizeof(uint32_t) * (size_t)CP_SLOTS * (size_t)units;
+    if ((rc = stream_scratch(s, bytes, &mem))) return rc;
+    p.pref = static_cast<int64_t*>(mem);
+    p.cnt = reinterpret_cast<uint32_t*>(p.pref + units);
+    p.slot = p.cnt + units;
+    const unsigned grid = (unsigned)((units + CP_WAVES - 1) / CP_WAVES);
+    if (p.units > 0) {
+        hipLaunchKernelGGL(k_cp_count, dim3(grid), dim3(64 * CP_WAVES), 0, s, p);
+        if ((rc = check_launch("k_cp_count"))) return rc;
+    }
+    hipLaunchKernelGGL(k_cp_scan, dim3(1), dim3(1024), 0, s, p);  // also writes the count
+    if ((rc = check_launch("k_cp_scan"))) return rc;
+    if (p.units > 0 && capacity > 0) {
+        hipLaunchKernelGGL(k_cp_emit, dim3(grid), dim3(64 * CP_WAVES), 0, s, p);
+        rc = check_launch("k_cp_emit");
+    }
+    return rc;
 }
 
 extern "C" abc_status abc_accept_compact_noalloc(const float* dist, const float* theta,

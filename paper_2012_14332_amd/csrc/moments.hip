@@ -2,7 +2,7 @@
 // parameter averages of Table "t:trajectories", extended to the covariance
 // and to importance weights), and its C-ABI entry point abc_posterior_moments.
 //
-// Deterministic: the n rows are cut into G = min(768, ceil(n / 2048))
+// Deterministic: the n rows are cut into G = min(512, ceil(n / 2048))
 // contiguous ranges, a function of n alone. Workgroup b sums its range (each
 // thread every 256th row, in row order; theta read as two float4 per row)
 // into V1, V2, S1 = sum w (theta - c), S2 = sum w (theta - c)(theta - c)^T
@@ -21,9 +21,14 @@
 namespace abc {
 
 constexpr int MOM_BLOCK = 256;
-constexpr int MOM_GROUPS = 768;     // most row ranges (workgroups of the partial pass)
+// Most row ranges (workgroups of the partial pass): at the partial pass's
+// register budget two wavefronts fit a SIMD, so 512 workgroups of four
+// wavefronts are one resident round on 256 CUs (768 left half the chip idle
+// for the last third of the pass).
+constexpr int MOM_GROUPS = 512;
 constexpr int MOM_MIN_ROWS = 2048;  // fewest rows per range
 constexpr int MOM_NSUM = 2 + 8 + 36;
+constexpr int MOM_BATCH = 4;        // rows whose loads a thread issues together
 
 // number of row ranges for n rows (depends on n only)
 __host__ __device__ inline int64_t mom_groups(int64_t n)
@@ -50,6 +55,16 @@ __device__ __forceinline__ int64_t rows_used(const MomArgs& a)
     return n;
 }
 
+// Orders one wavefront's LDS writes before its lanes read what other lanes
+// wrote (and reads before the next writes): a wavefront-scope fence pair
+// around a wave barrier, which the compiler does not move accesses across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
 #pragma unroll
@@ -60,6 +75,8 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 __global__ __launch_bounds__(MOM_BLOCK) void k_moments_partial(MomArgs a)
 {
     __shared__ double red[MOM_BLOCK / 64][MOM_NSUM];
+    // per wavefront: MOM_BATCH steps of 64 theta rows (128 float4) staged
+    __shared__ float4 stage[MOM_BLOCK / 64][MOM_BATCH][128];
     const int64_t n = rows_used(a);
     const int64_t G = mom_groups(n);
     if ((int64_t)blockIdx.x >= G) return;
@@ -77,21 +94,56 @@ __global__ __launch_bounds__(MOM_BLOCK) void k_moments_partial(MomArgs a)
     double s[MOM_NSUM];
 #pragma unroll
     for (int q = 0; q < MOM_NSUM; ++q) s[q] = 0.0;
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += MOM_BLOCK) {
-        const double w = a.weight ? (double)a.weight[row] : 1.0;
-        const float4 u = th4[2 * row], v = th4[2 * row + 1];
-        const double x[8] = {(double)u.x - c[0], (double)u.y - c[1], (double)u.z - c[2],
-                             (double)u.w - c[3], (double)v.x - c[4], (double)v.y - c[5],
-                             (double)v.z - c[6], (double)v.w - c[7]};
-        s[0] += w;
-        s[1] += w * w;
+    // Thread t sums its rows r0 + t, r0 + t + 256, ... in order. Wavefront w
+    // reads the 64 consecutive rows r0 + 64 w + 256 k + [0, 64) of its step k
+    // as two fully coalesced 1 KiB streams (row halves side by side), stages
+    // them in LDS and each lane takes its row back; MOM_BATCH steps are
+    // loaded before the float64 sums of the previous batch run.
+    float4 h0[MOM_BATCH], h1[MOM_BATCH];
+    float wv[MOM_BATCH];
+    auto load_batch = [&](int64_t k0) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s[2 + j] += w * x[j];
-        int q = 10;
+        for (int b = 0; b < MOM_BATCH; ++b) {
+            const int64_t R0 = r0 + 64 * wave + MOM_BLOCK * (k0 + b);  // first row of the step
+            const int64_t i0 = 2 * R0 + lane, i1 = i0 + 64;              // float4 indices
+            h0[b] = i0 < 2 * r1 ? load_stream(th4 + i0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            h1[b] = i1 < 2 * r1 ? load_stream(th4 + i1) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int64_t row = R0 + lane;
+            wv[b] = row < r1 ? (a.weight ? load_stream(a.weight + row) : 1.0f) : 0.0f;
+        }
+    };
+    const int64_t steps = (r1 - r0 + MOM_BLOCK - 1) / MOM_BLOCK;
+    load_batch(0);
+    for (int64_t k0 = 0; k0 < steps; k0 += MOM_BATCH) {
+        float wc[MOM_BATCH];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int b = 0; b < MOM_BATCH; ++b) {
+            stage[wave][b][lane] = h0[b];
+            stage[wave][b][64 + lane] = h1[b];
+            wc[b] = wv[b];
+        }
+        wave_lds_sync();
+        load_batch(k0 + MOM_BATCH);  // in flight during the sums below
 #pragma unroll
-            for (int l = j; l < 8; ++l) s[q++] += w * x[j] * x[l];
+        for (int b = 0; b < MOM_BATCH; ++b) {
+            const int64_t row = r0 + 64 * wave + MOM_BLOCK * (k0 + b) + lane;
+            if (row >= r1) break;
+            const float4 u = stage[wave][b][2 * lane], v = stage[wave][b][2 * lane + 1];
+            const double w = (double)wc[b];
+            const double x[8] = {(double)u.x - c[0], (double)u.y - c[1], (double)u.z - c[2],
+                                 (double)u.w - c[3], (double)v.x - c[4], (double)v.y - c[5],
+                                 (double)v.z - c[6], (double)v.w - c[7]};
+            s[0] += w;
+            s[1] += w * w;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[2 + j] += w * x[j];
+            int q = 10;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+#pragma unroll
+                for (int l = j; l < 8; ++l) s[q++] += w * x[j] * x[l];
+        }
+        wave_lds_sync();  // the next batch overwrites the staged rows
     }
 #pragma unroll
     for (int q = 0; q < MOM_NSUM; ++q) {
