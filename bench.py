@@ -53,6 +53,11 @@ SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/c
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_f32_traffic.json")
 
 
+def note(text):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print("bench: " + text, file=sys.stderr, flush=True)
+
+
 def sim_source_hash():
     h = hashlib.sha256()
     for p in SIM_SOURCES:
@@ -320,7 +325,10 @@ def learned_leg(args, batched):
     # posteriors of some series are heavy-tailed, so their sds need far more
     # samples than 1e4 to be known to 5 %)
     Qc = args.compare_quota
-    cap_c = min(2 * Qc, 8192)  # the finalisation sorts the candidates of a series in LDS
+    # candidates (within the float64 band around eps) per certain accept can
+    # exceed 2 where the distance distribution is steep near eps: 4x headroom,
+    # within the 8192 rows the finalisation sorts in LDS
+    cap_c = min(4 * Qc, 8192)
 
     def sampler(runs_kw):
         def run(seed, idxs):
@@ -338,7 +346,8 @@ def learned_leg(args, batched):
     cmp_ = PL.compare_posteriors(sers, eps, sampler({}),
                                  sampler(dict(mix=mix, lam=args.lam, inflate=args.inflate)),
                                  quota=Qc, seeds_a=args.compare_seeds_plain,
-                                 seeds_b=args.compare_seeds_learned, max_runs=args.compare_max_runs)
+                                 seeds_b=args.compare_seeds_learned, max_runs=args.compare_max_runs,
+                                 time_limit_s=args.compare_time_s, progress=note)
     compare_s = time.perf_counter() - tc0
     worst_mu = np.array([r["mean_ratio"] for r in cmp_])
     worst_sd = np.array([r["sd_ratio"] for r in cmp_])
@@ -597,10 +606,12 @@ def main():
     ap.add_argument("--mdn-epochs", type=int, default=20)
     ap.add_argument("--lam", type=float, default=0.5)
     ap.add_argument("--inflate", type=float, default=8.0)
-    ap.add_argument("--compare-quota", type=int, default=4096)
+    ap.add_argument("--compare-quota", type=int, default=2048)
     ap.add_argument("--compare-seeds-plain", type=int, nargs="+", default=[2, 3, 4])
     ap.add_argument("--compare-seeds-learned", type=int, nargs="+", default=[2, 3, 4, 5])
-    ap.add_argument("--compare-max-runs", type=int, default=400)
+    ap.add_argument("--compare-max-runs", type=int, default=800)
+    ap.add_argument("--compare-time-s", type=float, default=90.0,
+                    help="wall-time bound on the posterior check's pooling")
     ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")
     ap.add_argument("--no-smc", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the compaction/moments bandwidth leg")
@@ -738,6 +749,7 @@ def main():
     ev = []
     days.zero_()
     wall, accepted, keep = timed_region(args.warmup, ev)
+    note("timed region: %.3f ms per step" % (wall / args.steps * 1e3))
     # further repetitions of the same K-step region on fresh sample ranges
     # (median and interquartile range, as the paper repeats its runs)
     rep_rates, rep_ms = [accepted / wall], [wall / args.steps * 1e3]
@@ -846,19 +858,25 @@ def main():
         # of the later legs gets the main step's shape back
         main_shape, main_refill = abc.get_launch_config(), abc.get_refill_min()
         out["batched"] = batched_leg(args)
+        note("batched leg done")
         if not args.no_learned:
             out["learned"] = learned_leg(args, out["batched"])
+            note("learned leg done")
         out["batched"].pop("_eps", None)
         abc.set_launch_config(*main_shape)
         abc.set_refill_min(main_refill)
         out["batched"].pop("_used", None)
     if not args.no_smc:
         out["smc"] = smc_leg(args)
+        note("smc leg done")
     out["paper_style"] = paper_style_leg(args)
+    note("paper-style leg done")
     if not args.no_hbm:
         out["hbm_passes"] = hbm_leg(args)
+        note("hbm leg done")
     if not args.no_single:
         out["single_country"] = single_country_leg(args)
+        note("single-country leg done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(countries, eps, first0, args.cpu_samples, args.cpu_reps)
     print(json.dumps(out))

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_colstats(const float* x, int64_t n, int
 // BF16 MFMA GEMM: C[M][N] = op(A)[M][K] op(B)[K][N], float32 accumulation.
 // op(A)[m][k] = A[m lda + k] (TA = false) or A[k lda + m] (TA = true);
 // op(B)[k][n] = B[k ldb + n] (TB = false) or B[n ldb + k] (TB = true).
-// 64x64 workgroup tile, 4 wavefronts of 32x32, v_mfma_f32_16x16x16_bf16
+// 64x64 workgroup tile, 4 wavefronts of 32x32, v_mfma_f32_16x16x32_bf16
 // fragments, K staged through LDS in steps of 32. Epilogues:
 //   EPI_STORE    C (float32), optional + bias[n]
 //   EPI_GELU     Z = acc + bias -> C (float32), H = gelu(Z) as bf16
@@ -182,7 +182,6 @@ __global__ __launch_bounds__(256) void k_colstats(const float* x, int64_t n, int
 constexpr int EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2;
 constexpr int G_BM = 64, G_BN = 64, G_BK = 32, G_LD = G_BK + 8;
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
@@ -199,16 +198,104 @@ struct GemmArgs {
     bf16* H;
     int ldh;
     const float* Zin;
+    float* cs;  // EPI_DGELU: column-sum partials [row tiles][N], or null
 };
 
-// VEC: every operand row, column count and K range is a multiple of 8
-// elements and 16-byte aligned, so each thread stages one 8-element vector of
-// A and one of B per K step (one global load each) instead of eight scalars.
+// Staging of one K tile (BK = 32) into registers, then LDS. VEC: every
+// operand row, column count and K range is a multiple of 8 elements and
+// 16-byte aligned, so each thread holds one 8-element vector of A and one of B
+// per K tile (one global load each); otherwise eight scalars each.
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <bool TA, bool TB, bool VEC>
+struct TileRegs {
+    us8 a, b;
+
+    __device__ __forceinline__ void load(const GemmArgs& g, int tid, int m0, int n0, int k0, int kend)
+    {
+        const us8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (VEC) {
+            if (!TA) {
+                const int gm = m0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
+                a = (gm < g.M && gk < kend) ? *reinterpret_cast<const us8*>(g.A + (int64_t)gm * g.lda + gk)
+                                            : zero;
+            } else {
+                const int gm = m0 + (tid & 7) * 8, gk = k0 + (tid >> 3);
+                a = (gm < g.M && gk < kend) ? *reinterpret_cast<const us8*>(g.A + (int64_t)gk * g.lda + gm)
+                                            : zero;
+            }
+            if (TB) {
+                const int gn = n0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
+                b = (gn < g.N && gk < kend) ? *reinterpret_cast<const us8*>(g.B + (int64_t)gn * g.ldb + gk)
+                                            : zero;
+            } else {
+                const int gn = n0 + (tid & 7) * 8, gk = k0 + (tid >> 3);
+                b = (gn < g.N && gk < kend) ? *reinterpret_cast<const us8*>(g.B + (int64_t)gk * g.ldb + gn)
+                                            : zero;
+            }
+        } else {
+            // element e = 8 tid + q of the 64 x 32 tile, in the operand's memory order
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = 8 * tid + q;
+                int mm, kk;
+                if (TA) { kk = e / G_BM; mm = e % G_BM; }
+                else { mm = e / G_BK; kk = e % G_BK; }
+                const int gm = m0 + mm, gk = k0 + kk;
+                a[q] = (gm < g.M && gk < kend) ? (TA ? g.A[(int64_t)gk * g.lda + gm] : g.A[(int64_t)gm * g.lda + gk])
+                                               : (unsigned short)0;
+                int nn;
+                if (TB) { nn = e / G_BK; kk = e % G_BK; }
+                else { kk = e / G_BN; nn = e % G_BN; }
+                const int gn = n0 + nn, gk2 = k0 + kk;
+                b[q] = (gn < g.N && gk2 < kend) ? (TB ? g.B[(int64_t)gn * g.ldb + gk2] : g.B[(int64_t)gk2 * g.ldb + gn])
+                                                : (unsigned short)0;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(bf16 (*As)[G_LD], bf16 (*Bs)[G_LD], int tid) const
+    {
+        if constexpr (VEC) {
+            if (!TA) {
+                *reinterpret_cast<us8*>(&As[tid >> 2][(tid & 3) * 8]) = a;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) As[(tid & 7) * 8 + q][tid >> 3] = a[q];
+            }
+            if (TB) {
+                *reinterpret_cast<us8*>(&Bs[tid >> 2][(tid & 3) * 8]) = b;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Bs[(tid & 7) * 8 + q][tid >> 3] = b[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = 8 * tid + q;
+                if (TA) As[e % G_BM][e / G_BM] = a[q];
+                else As[e / G_BK][e % G_BK] = a[q];
+                if (TB) Bs[e / G_BK][e % G_BK] = b[q];
+                else Bs[e % G_BN][e / G_BN] = b[q];
+            }
+        }
+    }
+};
+
+// 64 x 64 workgroup tile, four wavefronts of 32 x 32, K tiles of 32 on
+// gfx950's v_mfma_f32_16x16x32_bf16: lane l supplies row (l & 15) of A and
+// column (l & 15) of B at k = 8 (l >> 4) + 0..7, one 16-byte LDS read per
+// operand fragment, and receives C[4 (l >> 4) + r][l & 15]. The next K tile is
+// loaded into registers while the current one is multiplied. With
+// EPI_DGELU and cs != null, workgroup (x, y) also writes the float32 column
+// sums of its 64 output rows to cs[y][n] (the bias gradient's partials).
 template <bool TA, bool TB, int EPI, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 {
     __shared__ __align__(16) bf16 As[G_BM][G_LD];
     __shared__ __align__(16) bf16 Bs[G_BN][G_LD];  // [n][k]
+    __shared__ float cs_sh[2][G_BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * G_BM, n0 = blockIdx.x * G_BN;
     const int kbeg = blockIdx.z * g.k_per_split;
@@ -221,90 +308,29 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
+    TileRegs<TA, TB, VEC> regs;
+    regs.load(g, tid, m0, n0, kbeg, kend);
     for (int k0 = kbeg; k0 < kend; k0 += G_BK) {
-        if constexpr (VEC) {
-            typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-            const us8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-            // A: 64 x 32 as 256 vectors of 8
-            if (!TA) {
-                const int mm = tid >> 2, kv = (tid & 3) * 8;
-                const int gm = m0 + mm, gk = k0 + kv;
-                us8 v = zero;
-                if (gm < g.M && gk < kend)
-                    v = *reinterpret_cast<const us8*>(g.A + (int64_t)gm * g.lda + gk);
-                *reinterpret_cast<us8*>(&As[mm][kv]) = v;
-            } else {
-                const int kk = tid >> 3, mv = (tid & 7) * 8;
-                const int gm = m0 + mv, gk = k0 + kk;
-                us8 v = zero;
-                if (gm < g.M && gk < kend)
-                    v = *reinterpret_cast<const us8*>(g.A + (int64_t)gk * g.lda + gm);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) As[mv + q][kk] = v[q];
-            }
-            // B: 32 x 64 as 256 vectors of 8, stored [n][k]
-            if (TB) {
-                const int nn = tid >> 2, kv = (tid & 3) * 8;
-                const int gn = n0 + nn, gk = k0 + kv;
-                us8 v = zero;
-                if (gn < g.N && gk < kend)
-                    v = *reinterpret_cast<const us8*>(g.B + (int64_t)gn * g.ldb + gk);
-                *reinterpret_cast<us8*>(&Bs[nn][kv]) = v;
-            } else {
-                const int kk = tid >> 3, nv = (tid & 7) * 8;
-                const int gn = n0 + nv, gk = k0 + kk;
-                us8 v = zero;
-                if (gn < g.N && gk < kend)
-                    v = *reinterpret_cast<const us8*>(g.B + (int64_t)gk * g.ldb + gn);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) Bs[nv + q][kk] = v[q];
-            }
-        } else {
-        // stage A: 64 x 32
-        for (int e = tid; e < G_BM * G_BK; e += 256) {
-            int mm, kk;
-            if (TA) { kk = e / G_BM; mm = e % G_BM; }   // m contiguous in memory
-            else { mm = e / G_BK; kk = e % G_BK; }      // k contiguous in memory
-            const int gm = m0 + mm, gk = k0 + kk;
-            bf16 v = 0;
-            if (gm < g.M && gk < kend) v = TA ? g.A[(int64_t)gk * g.lda + gm] : g.A[(int64_t)gm * g.lda + gk];
-            As[mm][kk] = v;
-        }
-        // stage B: 32 x 64, stored [n][k]
-        for (int e = tid; e < G_BN * G_BK; e += 256) {
-            int nn, kk;
-            if (TB) { nn = e / G_BK; kk = e % G_BK; }   // k contiguous in memory
-            else { kk = e / G_BN; nn = e % G_BN; }      // n contiguous in memory
-            const int gn = n0 + nn, gk = k0 + kk;
-            bf16 v = 0;
-            if (gn < g.N && gk < kend) v = TB ? g.B[(int64_t)gn * g.ldb + gk] : g.B[(int64_t)gk * g.ldb + gn];
-            Bs[nn][kk] = v;
-        }
-        }
+        regs.store(As, Bs, tid);
         __syncthreads();
+        if (k0 + G_BK < kend) regs.load(g, tid, m0, n0, k0 + G_BK, kend);  // next tile in flight
+        const int kq = 8 * (lane >> 4);
+        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int kk = 0; kk < G_BK; kk += 16) {
-            short4_t a[2], b[2];
-            const int kq = kk + 4 * (lane >> 4);
+        for (int i = 0; i < 2; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(&As[wy * 32 + i * 16 + (lane & 15)][kq]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const bf16* p = &As[wy * 32 + i * 16 + (lane & 15)][kq];
-                a[i] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-            }
+        for (int j = 0; j < 2; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wx * 32 + j * 16 + (lane & 15)][kq]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16* p = &Bs[wx * 32 + j * 16 + (lane & 15)][kq];
-                b[j] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-            }
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
     float* C = g.C + (int64_t)blockIdx.z * g.split_stride;
+    float csum[2] = {0.0f, 0.0f};  // this lane's column sums (j = 0, 1) over its rows
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -326,75 +352,26 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
                     v *= gelu_grad_f(g.Zin[(int64_t)m * g.ldc + n]);
                     C[(int64_t)m * g.ldc + n] = v;
                     g.H[(int64_t)m * g.ldh + n] = f2bf(v);
+                    csum[j] += v;
                 }
             }
-}
-
-// sum of split-K partials [splits][M][N] in split order -> out (float32)
-__global__ void k_sum_splits(const float* part, int splits, int64_t mn, float* out)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= mn) return;
-    // in split order, loads issued 8 ahead of the adds
-    float s = 0.0f;
-    int z = 0;
-    for (; z + 8 <= splits; z += 8) {
-        float v[8];
+    if (EPI == EPI_DGELU && g.cs) {
+        // rows of the lane groups l >> 4 (fixed order), then the two wy halves
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(z + q) * mn + e];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s += v[q];
-    }
-    for (; z < splits; ++z) s += part[(int64_t)z * mn + e];
-    out[e] = s;
-}
-
-// column sums of x [rows][cols] -> out[cols], in two fixed-order levels:
-// workgroup (column tile, row block) sums CS_ROWS rows of 64 columns, four
-// row groups per column (rows r0 + g, r0 + g + 4, ... in order, loaded 16
-// ahead) added in group order; then each column adds its row blocks in order.
-constexpr int CS_ROWS = 256;
-
-__global__ __launch_bounds__(256) void k_colsum_part(const float* x, int rows, int cols, float* part)
-{
-    __shared__ float red[4][64];
-    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + l;
-    const int r0 = blockIdx.y * CS_ROWS;
-    const int r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
-    float s = 0.0f;
-    if (c < cols) {
-        int r = r0 + g;
-        for (; r + 4 * 15 < r1; r += 64) {
-            float v[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = x[(int64_t)(r + 4 * k) * cols + c];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) s += v[k];
+        for (int j = 0; j < 2; ++j) {
+            float v = csum[j];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            csum[j] = v;
         }
-        for (; r < r1; r += 4) s += x[(int64_t)r * cols + c];
+        if (lane < 16) {
+            cs_sh[wy][wx * 32 + lane] = csum[0];
+            cs_sh[wy][wx * 32 + 16 + lane] = csum[1];
+        }
+        __syncthreads();
+        if (tid < G_BN && n0 + tid < g.N)
+            g.cs[(int64_t)blockIdx.y * g.N + n0 + tid] = cs_sh[0][tid] + cs_sh[1][tid];
     }
-    red[g][l] = s;
-    __syncthreads();
-    if (g == 0 && c < cols)
-        part[(int64_t)blockIdx.y * cols + c] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
-}
-
-__global__ void k_colsum_fin(const float* part, int blocks, int cols, float* out)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.0f;
-    int b = 0;
-    for (; b + 8 <= blocks; b += 8) {
-        float v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(b + q) * cols + c];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s += v[q];
-    }
-    for (; b < blocks; ++b) s += part[(int64_t)b * cols + c];
-    out[c] = s;
 }
 
 // ----------------------------------------------------------------------------
@@ -437,27 +414,36 @@ __global__ void k_gather(GatherArgs a)
 // mixture negative log-likelihood and its gradient w.r.t. the 136 outputs
 // (divided by the batch size); loss_acc[0] += sum of NLL / batch
 // ----------------------------------------------------------------------------
+// One workgroup of four wavefronts per LOSS_ROWS rows, a wavefront per row at
+// a time; cs != null: the workgroup also writes the float32 column sums of
+// its rows' gradient, cs[blockIdx][136] (the output bias's gradient partials).
+constexpr int LOSS_ROWS = 64;
+
 __global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float* T, int n,
-                                                  float* dout, bf16* dout_b, float* loss_acc)
+                                                  float* dout, bf16* dout_b, float* loss_acc,
+                                                  float* cs)
 {
-    // one wavefront per row; lane = k NN_D + j holds component k, dimension j
+    // lane = k NN_D + j holds component k, dimension j
     static_assert(NN_K * NN_D == 64, "one lane per (component, dimension)");
     __shared__ float red[4];
+    __shared__ float csh[4][NN_OUT];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int r = blockIdx.x * 4 + wv;
-    float nll = 0.0f;
-    if (r < n) {  // uniform over the wavefront
+    const int k = lane / NN_D, j = lane % NN_D;
+    const float inv_n = 1.0f / (float)n;
+    float nll_sum = 0.0f, c_mu = 0.0f, c_ls = 0.0f, c_k = 0.0f;
+    for (int q = 0; q < LOSS_ROWS / 4; ++q) {
+        const int r = blockIdx.x * LOSS_ROWS + wv * (LOSS_ROWS / 4) + q;
+        if (r >= n) break;  // uniform over the wavefront
         const float* o = out + (int64_t)r * NN_OUT;
         float* g = dout + (int64_t)r * NN_OUT;
         bf16* gb = dout_b + (int64_t)r * NN_OUT;
-        const int k = lane / NN_D, j = lane % NN_D;
         // log-softmax of the mixture logits (every lane, same values)
         float lmax = -INFINITY;
 #pragma unroll
-        for (int q = 0; q < NN_K; ++q) lmax = fmaxf(lmax, o[q]);
+        for (int c = 0; c < NN_K; ++c) lmax = fmaxf(lmax, o[c]);
         float se = 0.0f;
 #pragma unroll
-        for (int q = 0; q < NN_K; ++q) se += expf(o[q] - lmax);
+        for (int c = 0; c < NN_K; ++c) se += expf(o[c] - lmax);
         const float lse_logits = lmax + logf(se);
         // this lane's Gaussian factor
         const float mu = o[NN_K + lane];
@@ -481,8 +467,7 @@ __global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float*
         sr += __shfl_xor(sr, 16, 64);
         sr += __shfl_xor(sr, 32, 64);
         const float lse = Lmax + logf(sr);
-        nll = -lse;
-        const float inv_n = 1.0f / (float)n;
+        nll_sum += -lse;
         const float resp = expf(Lk - lse);
         const float gmu = -resp * u * si * inv_n;
         const float gls = (raw > LOGSIG_LO && raw < LOGSIG_HI) ? -resp * (u * u - 1.0f) * inv_n : 0.0f;
@@ -490,48 +475,95 @@ __global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float*
         gb[NN_K + lane] = f2bf(gmu);
         g[NN_K + NN_K * NN_D + lane] = gls;
         gb[NN_K + NN_K * NN_D + lane] = f2bf(gls);
+        c_mu += gmu;
+        c_ls += gls;
         if (j == 0) {
             const float gk = (expf(logit - lse_logits) - resp) * inv_n;
             g[k] = gk;
             gb[k] = f2bf(gk);
+            c_k += gk;
         }
     }
-    // block sum of the NLL (the same in every lane of a row), one atomic per workgroup
-    if (lane == 0) red[wv] = nll;
+    if (lane == 0) red[wv] = nll_sum;
+    if (cs) {
+        csh[wv][NN_K + lane] = c_mu;
+        csh[wv][NN_K + NN_K * NN_D + lane] = c_ls;
+        if (j == 0) csh[wv][k] = c_k;
+    }
     __syncthreads();
+    // one atomic per workgroup for the logged loss (its value only)
     if (threadIdx.x == 0 && loss_acc) atomicAdd(loss_acc, (red[0] + red[1] + red[2] + red[3]) / (float)n);
+    if (cs && threadIdx.x < NN_OUT) {
+        const int c = threadIdx.x;
+        cs[(int64_t)blockIdx.x * NN_OUT + c] = ((csh[0][c] + csh[1][c]) + csh[2][c]) + csh[3][c];
+    }
 }
 
 // ----------------------------------------------------------------------------
 // Adam (Kingma & Ba) on the float32 master parameters, then the bf16 copies
 // of the weights; the step counter advances after every update
 // ----------------------------------------------------------------------------
-struct AdamArgs {
+// The gradient of every parameter from its partials, added in fixed order:
+// a weight entry from the split-K partials of its layer's product (split
+// order), a bias entry from the column-sum partials of its layer (row-block
+// order). With adam, the same thread then applies Adam (Kingma & Ba) to the
+// float32 master parameter and refreshes its bf16 copy; the step counter
+// advances afterwards (k_step_inc).
+struct FinishArgs {
+    const float* part1;   // [splits][96][256]
+    const float* part2;   // [splits][256][256]
+    const float* part3;   // [splits][256][136]
+    int splits;
+    const float* cs1;     // [row tiles][256]
+    const float* cs2;     // [row tiles][256]
+    const float* cs3;     // [loss blocks][136]
+    int tiles, lblocks;
+    float* g;
+    int adam;
     float* p;
-    const float* g;
     float* m;
     float* v;
     bf16* pb;
-    int32_t* step;
+    const int32_t* step;
     float lr, b1, b2, eps;
 };
 
-__global__ void k_adam(AdamArgs a)
+__global__ void k_grad_finish(FinishArgs a)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int st = *a.step + 1;
-    if (e < NN_PARAMS) {
-        const float g = a.g[e];
-        const float m = a.b1 * a.m[e] + (1.0f - a.b1) * g;
-        const float v = a.b2 * a.v[e] + (1.0f - a.b2) * g * g;
-        a.m[e] = m;
-        a.v[e] = v;
-        const float mh = m / (1.0f - powf(a.b1, (float)st));
-        const float vh = v / (1.0f - powf(a.b2, (float)st));
-        const float p = a.p[e] - a.lr * mh / (sqrtf(vh) + a.eps);
-        a.p[e] = p;
-        a.pb[e] = f2bf(p);
+    if (e >= NN_PARAMS) return;
+    const float* src;
+    int64_t stride;
+    int cnt;
+    if (e < OFF_B1) { src = a.part1 + e; stride = (int64_t)NN_IN * NN_H; cnt = a.splits; }
+    else if (e < OFF_W2) { src = a.cs1 + (e - OFF_B1); stride = NN_H; cnt = a.tiles; }
+    else if (e < OFF_B2) { src = a.part2 + (e - OFF_W2); stride = (int64_t)NN_H * NN_H; cnt = a.splits; }
+    else if (e < OFF_W3) { src = a.cs2 + (e - OFF_B2); stride = NN_H; cnt = a.tiles; }
+    else if (e < OFF_B3) { src = a.part3 + (e - OFF_W3); stride = (int64_t)NN_H * NN_OUT; cnt = a.splits; }
+    else { src = a.cs3 + (e - OFF_B3); stride = NN_OUT; cnt = a.lblocks; }
+    // in order, loads issued eight ahead of the adds
+    float gsum = 0.0f;
+    int z = 0;
+    for (; z + 8 <= cnt; z += 8) {
+        float t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = src[(int64_t)(z + q) * stride];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) gsum += t[q];
     }
+    for (; z < cnt; ++z) gsum += src[(int64_t)z * stride];
+    a.g[e] = gsum;
+    if (!a.adam) return;
+    const int st = *a.step + 1;
+    const float m = a.b1 * a.m[e] + (1.0f - a.b1) * gsum;
+    const float v = a.b2 * a.v[e] + (1.0f - a.b2) * gsum * gsum;
+    a.m[e] = m;
+    a.v[e] = v;
+    const float mh = m / (1.0f - powf(a.b1, (float)st));
+    const float vh = v / (1.0f - powf(a.b2, (float)st));
+    const float p = a.p[e] - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.p[e] = p;
+    a.pb[e] = f2bf(p);
 }
 
 __global__ void k_step_inc(int32_t* step, float* loss_log, const float* loss_acc)
@@ -651,7 +683,11 @@ struct abc_mdn {
     int ws = 0;  // workspace rows
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dOUTb = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
     float *T = nullptr, *Z1 = nullptr, *Z2 = nullptr, *OUT = nullptr, *dOUT = nullptr,
-          *dZ2 = nullptr, *dZ1 = nullptr, *part = nullptr, *cs_part = nullptr;
+          *dZ2 = nullptr, *dZ1 = nullptr;
+    // split-K partials of the three weight gradients, column-sum partials of
+    // the three bias gradients
+    float *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *cs1 = nullptr, *cs2 = nullptr,
+          *cs3 = nullptr;
     int64_t* perm = nullptr;
 };
 
@@ -660,11 +696,13 @@ namespace {
 void free_ws(abc_mdn* n)
 {
     void* ptrs[] = {n->X, n->H1, n->H2, n->dOUTb, n->dZ2b, n->dZ1b, n->T, n->Z1, n->Z2,
-                    n->OUT, n->dOUT, n->dZ2, n->dZ1, n->part, n->cs_part};
+                    n->OUT, n->dOUT, n->dZ2, n->dZ1, n->part1, n->part2, n->part3,
+                    n->cs1, n->cs2, n->cs3};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     n->X = n->H1 = n->H2 = n->dOUTb = n->dZ2b = n->dZ1b = nullptr;
-    n->T = n->Z1 = n->Z2 = n->OUT = n->dOUT = n->dZ2 = n->dZ1 = n->part = n->cs_part = nullptr;
+    n->T = n->Z1 = n->Z2 = n->OUT = n->dOUT = n->dZ2 = n->dZ1 = nullptr;
+    n->part1 = n->part2 = n->part3 = n->cs1 = n->cs2 = n->cs3 = nullptr;
     n->ws = 0;
 }
 
@@ -688,8 +726,12 @@ abc_status ensure_ws(abc_mdn* n, int rows)
     ALLOC(n->dZ2b, r * NN_H * sizeof(bf16));
     ALLOC(n->dZ1, r * NN_H * sizeof(float));
     ALLOC(n->dZ1b, r * NN_H * sizeof(bf16));
-    ALLOC(n->part, (size_t)splits * NN_H * NN_H * sizeof(float));
-    ALLOC(n->cs_part, (size_t)((rows + CS_ROWS - 1) / CS_ROWS) * NN_H * sizeof(float));
+    ALLOC(n->part1, (size_t)splits * NN_IN * NN_H * sizeof(float));
+    ALLOC(n->part2, (size_t)splits * NN_H * NN_H * sizeof(float));
+    ALLOC(n->part3, (size_t)splits * NN_H * NN_OUT * sizeof(float));
+    ALLOC(n->cs1, (size_t)((rows + G_BM - 1) / G_BM) * NN_H * sizeof(float));
+    ALLOC(n->cs2, (size_t)((rows + G_BM - 1) / G_BM) * NN_H * sizeof(float));
+    ALLOC(n->cs3, (size_t)((rows + LOSS_ROWS - 1) / LOSS_ROWS) * NN_OUT * sizeof(float));
 #undef ALLOC
     n->ws = rows;
     return ABC_OK;
@@ -734,60 +776,55 @@ void forward(abc_mdn* net, int n, hipStream_t s)
     gemm<false, false, EPI_STORE>(g, 0, s);
 }
 
-void colsum(const float* x, int rows, int cols, float* out, float* part, hipStream_t s)
-{
-    const int blocks = (rows + CS_ROWS - 1) / CS_ROWS;
-    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, blocks), dim3(256), 0, s, x, rows, cols,
-                       part);
-    hipLaunchKernelGGL(k_colsum_fin, dim3((cols + 255) / 256), dim3(256), 0, s, part, blocks, cols,
-                       out);
-}
-
-// loss + gradient of the mean NLL into net->g (forward must have run)
+// loss and the gradient partials of the mean NLL (forward must have run); the
+// gradient itself is formed by k_grad_finish
 void backward(abc_mdn* net, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mdn_loss, dim3((n + 3) / 4), dim3(256), 0, s, net->OUT, net->T, n,
-                       net->dOUT, net->dOUTb, net->loss_acc);
-    const int kps = k_per_split_for(n), used = splits_for(n);
-    // dW3 = H2^T dOUT, db3 = colsum(dOUT)
+    hipLaunchKernelGGL(k_mdn_loss, dim3((n + LOSS_ROWS - 1) / LOSS_ROWS), dim3(256), 0, s, net->OUT,
+                       net->T, n, net->dOUT, net->dOUTb, net->loss_acc, net->cs3);
+    const int kps = k_per_split_for(n);
+    // dW3 = H2^T dOUT (db3: the loss kernel's column partials)
     GemmArgs g{};
     g.M = NN_H; g.N = NN_OUT; g.K = n;
     g.A = net->H2; g.lda = NN_H; g.B = net->dOUTb; g.ldb = NN_OUT;
-    g.C = net->part; g.ldc = NN_OUT;
+    g.C = net->part3; g.ldc = NN_OUT;
     gemm<true, false, EPI_STORE>(g, kps, s);
-    hipLaunchKernelGGL(k_sum_splits, dim3((NN_H * NN_OUT + 255) / 256), dim3(256), 0, s, net->part,
-                       used, (int64_t)NN_H * NN_OUT, net->g + OFF_W3);
-    colsum(net->dOUT, n, NN_OUT, net->g + OFF_B3, net->cs_part, s);
-    // dZ2 = (dOUT W3^T) gelu'(Z2)
+    // dZ2 = (dOUT W3^T) gelu'(Z2), with the column partials of db2
     g = GemmArgs{};
     g.M = n; g.N = NN_H; g.K = NN_OUT;
     g.A = net->dOUTb; g.lda = NN_OUT; g.B = net->pb + OFF_W3; g.ldb = NN_OUT;
-    g.C = net->dZ2; g.ldc = NN_H; g.Zin = net->Z2; g.H = net->dZ2b; g.ldh = NN_H;
+    g.C = net->dZ2; g.ldc = NN_H; g.Zin = net->Z2; g.H = net->dZ2b; g.ldh = NN_H; g.cs = net->cs2;
     gemm<false, true, EPI_DGELU>(g, 0, s);
-    // dW2 = H1^T dZ2, db2
+    // dW2 = H1^T dZ2
     g = GemmArgs{};
     g.M = NN_H; g.N = NN_H; g.K = n;
     g.A = net->H1; g.lda = NN_H; g.B = net->dZ2b; g.ldb = NN_H;
-    g.C = net->part; g.ldc = NN_H;
+    g.C = net->part2; g.ldc = NN_H;
     gemm<true, false, EPI_STORE>(g, kps, s);
-    hipLaunchKernelGGL(k_sum_splits, dim3((NN_H * NN_H + 255) / 256), dim3(256), 0, s, net->part,
-                       used, (int64_t)NN_H * NN_H, net->g + OFF_W2);
-    colsum(net->dZ2, n, NN_H, net->g + OFF_B2, net->cs_part, s);
-    // dZ1 = (dZ2 W2^T) gelu'(Z1)
+    // dZ1 = (dZ2 W2^T) gelu'(Z1), with the column partials of db1
     g = GemmArgs{};
     g.M = n; g.N = NN_H; g.K = NN_H;
     g.A = net->dZ2b; g.lda = NN_H; g.B = net->pb + OFF_W2; g.ldb = NN_H;
-    g.C = net->dZ1; g.ldc = NN_H; g.Zin = net->Z1; g.H = net->dZ1b; g.ldh = NN_H;
+    g.C = net->dZ1; g.ldc = NN_H; g.Zin = net->Z1; g.H = net->dZ1b; g.ldh = NN_H; g.cs = net->cs1;
     gemm<false, true, EPI_DGELU>(g, 0, s);
-    // dW1 = X^T dZ1, db1
+    // dW1 = X^T dZ1
     g = GemmArgs{};
     g.M = NN_IN; g.N = NN_H; g.K = n;
     g.A = net->X; g.lda = NN_IN; g.B = net->dZ1b; g.ldb = NN_H;
-    g.C = net->part; g.ldc = NN_H;
+    g.C = net->part1; g.ldc = NN_H;
     gemm<true, false, EPI_STORE>(g, kps, s);
-    hipLaunchKernelGGL(k_sum_splits, dim3((NN_IN * NN_H + 255) / 256), dim3(256), 0, s, net->part,
-                       used, (int64_t)NN_IN * NN_H, net->g + OFF_W1);
-    colsum(net->dZ1, n, NN_H, net->g + OFF_B1, net->cs_part, s);
+}
+
+FinishArgs finish_args(abc_mdn* net, int n)
+{
+    FinishArgs f{};
+    f.part1 = net->part1; f.part2 = net->part2; f.part3 = net->part3;
+    f.splits = splits_for(n);
+    f.cs1 = net->cs1; f.cs2 = net->cs2; f.cs3 = net->cs3;
+    f.tiles = (n + G_BM - 1) / G_BM;
+    f.lblocks = (n + LOSS_ROWS - 1) / LOSS_ROWS;
+    f.g = net->g;
+    return f;
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -946,6 +983,8 @@ extern "C" abc_status abc_mdn_loss_grad(abc_mdn* net, const float* features, con
     launch_gather(net, features, theta, n, (int)n, 1, nullptr, nullptr, s);
     forward(net, (int)n, s);
     backward(net, (int)n, s);
+    const FinishArgs f = finish_args(net, (int)n);
+    hipLaunchKernelGGL(k_grad_finish, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, f);
     if (loss) ABC_HIP(hipMemcpyAsync(loss, net->loss_acc, sizeof(float), hipMemcpyDeviceToDevice, s));
     if (grad) ABC_HIP(hipMemcpyAsync(grad, net->g, NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s));
     return check_launch("abc_mdn_loss_grad");
@@ -1009,10 +1048,11 @@ extern "C" abc_status abc_mdn_train(abc_mdn* net, const float* features, const f
     launch_gather(net, features, theta, n, batch, spe, net->perm, net->step, s);
     forward(net, batch, s);
     backward(net, batch, s);
-    AdamArgs aa{};
-    aa.p = net->p; aa.g = net->g; aa.m = net->m; aa.v = net->v; aa.pb = net->pb; aa.step = net->step;
-    aa.lr = lr; aa.b1 = 0.9f; aa.b2 = 0.999f; aa.eps = 1e-8f;
-    hipLaunchKernelGGL(k_adam, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, aa);
+    FinishArgs f = finish_args(net, batch);
+    f.adam = 1;
+    f.p = net->p; f.m = net->m; f.v = net->v; f.pb = net->pb; f.step = net->step;
+    f.lr = lr; f.b1 = 0.9f; f.b2 = 0.999f; f.eps = 1e-8f;
+    hipLaunchKernelGGL(k_grad_finish, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, net->step, loss_log, net->loss_acc);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (ce != hipSuccess) return set_error(ABC_EHIP, "training graph capture: %s", hipGetErrorString(ce));

@@ -275,7 +275,8 @@ def _weighted_summary(theta: np.ndarray, w: np.ndarray):
 
 def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2, 3, 4),
                        seeds_b=(2, 3, 4), max_runs: int = 48, resolution: float = 4.0,
-                       min_ess: float = 1e4, rel: float = 0.05):
+                       min_ess: float = 1e4, rel: float = 0.05, time_limit_s: float = None,
+                       progress=None):
     """Posterior mean and sd of sampler B against sampler A, series by series
     (the learned-proposal criterion: per parameter |dmean| <= rel max(|mean_A|,
     sd_A) and |dsd| <= rel sd_A). run_a(seed, idxs) and run_b(seed, idxs) return
@@ -284,7 +285,11 @@ def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2
     until B's effective size is at least min_ess and the standard error of every
     difference is at most tolerance / resolution -- the criterion is then
     decided at `resolution` standard errors rather than at Monte Carlo noise --
-    or until max_runs runs. Returns per-series records."""
+    or until max_runs runs (or time_limit_s seconds of pooling). progress(text),
+    if given, is called after every pooling pass. Returns per-series records."""
+    import time
+
+    t_start = time.perf_counter()
     m = len(sers)
     pools = {"a": [[[], []] for _ in range(m)], "b": [[[], []] for _ in range(m)]}
     next_seed = {"a": list(seeds_a), "b": list(seeds_b)}
@@ -340,7 +345,12 @@ def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2
                 need_a.append(j)
         if not need_a and not need_b:
             break
+        if time_limit_s is not None and time.perf_counter() - t_start > time_limit_s:
+            break
         pull("a", need_a)
         pull("b", need_b)
         todo = sorted(set(need_a) | set(need_b))
+        if progress:
+            progress("posterior check: %d series pooling, runs so far %d / %d (max), %.0f s"
+                     % (len(todo), max(runs["a"]), max(runs["b"]), time.perf_counter() - t_start))
     return out

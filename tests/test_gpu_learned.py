@@ -133,7 +133,7 @@ def test_learned_posterior_within_5pct_at_resolved_precision(env):
     sers = [P.observed_series(ss[j]) for j in pick]
     eps = [P.pilot_eps(ser, 2, n=100_000, q=1e-3, series=j) for j, ser in zip(pick, sers)]
     mix = net.forward(torch.stack([abc.series_features(s) for s in sers])).contiguous()
-    Qc = 4096
+    Qc = 2048  # candidates per run stay within 4 Qc (8192 rows) even where the band is dense
 
     def sampler(kw):
         def run(seed, idxs):
@@ -147,7 +147,8 @@ def test_learned_posterior_within_5pct_at_resolved_precision(env):
         return run
 
     res = P.compare_posteriors(sers, eps, sampler({}), sampler(dict(mix=mix, lam=0.5, inflate=8.0)),
-                               quota=Qc, max_runs=400)
+                               quota=Qc, max_runs=800, time_limit_s=150,
+                               progress=lambda t: print(t, flush=True))
     for j, r in zip(pick, res):
         print("series %d: mean/tol %.2f sd/tol %.2f, se/tol %.3f, ess %.0f / %.0f, runs %d / %d"
               % (j, r["mean_ratio"], r["sd_ratio"], r["se_over_tol"], r["ess_a"], r["ess_b"],
