@@ -602,6 +602,8 @@ def main():
     ap.add_argument("--quota", type=int, default=1000)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-only", action="store_true",
+                    help="only train the learned proposal's network and report its timings")
     ap.add_argument("--mdn-pairs", type=int, default=1_000_000)
     ap.add_argument("--mdn-epochs", type=int, default=20)
     ap.add_argument("--lam", type=float, default=0.5)
@@ -624,6 +626,27 @@ def main():
                     help="run one device copy of this many MiB first (scales HBM byte counters)")
     args = ap.parse_args()
 
+    if args.train_only:
+        import torch
+
+        from paper_2012_14332_amd import abc
+        from paper_2012_14332_amd import pipeline as PL
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        abc.lib()
+        net, loss_log, steps, train_ms, data_ms = PL.train_proposal(
+            n_pairs=args.mdn_pairs, epochs=args.mdn_epochs, batch=4096, lr=1e-3, seed=6)
+        loss_log = loss_log.cpu().numpy()
+        net.close()
+        # one step's products at batch 4096: three forward, five backward
+        flop = 2 * 4096 * (96 * 256 + 256 * 256 + 256 * 136) * 3
+        print(json.dumps({"workload": "learned-proposal training: %d pairs, %d epochs, batch 4096"
+                          % (args.mdn_pairs, args.mdn_epochs), "steps": steps, "train_ms": train_ms,
+                          "step_us": 1e3 * train_ms / max(steps, 1), "data_ms": data_ms,
+                          "gemm_gflop_per_step": flop / 1e9,
+                          "loss_first_last": [float(loss_log[:10].mean()), float(loss_log[-10:].mean())]}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the ABC path is built for one device's share "
               "(see the sharding notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)

@@ -466,7 +466,9 @@ ABC_API abc_status abc_series_features(const abc_series* ser, float* out96, void
 ABC_API abc_status abc_mdn_fit_standardizer(abc_mdn* net, const float* features, int64_t n,
                                             void* stream);
 
-/* Network outputs [n][136] (device, float32) for unstandardised features [n][96]. */
+/* Network outputs [n][136] (device, float32) for unstandardised features [n][96].
+ * Every entry point below that takes features [n][96] requires them 16-byte
+ * aligned (ABC_EINVAL otherwise): the first layer reads them four at a time. */
 ABC_API abc_status abc_mdn_forward(abc_mdn* net, const float* features, int64_t n, float* out,
                                    void* stream);
 

@@ -169,18 +169,62 @@ __global__ __launch_bounds__(256) void k_colstats(const float* x, int64_t n, int
 }
 
 // ----------------------------------------------------------------------------
+// batch rows: with a step counter, batch row b of training step st is dataset
+// row (a_e j + c_e) mod n of epoch e's affine permutation (e = st / steps per
+// epoch, j = (st mod steps per epoch) batch + b); without one, row b itself.
+// Features are standardised per column, (x - mean) / sd, and theta by the
+// prior's centre and sd, as they are read.
+// ----------------------------------------------------------------------------
+struct RowMap {
+    const float* features;   // [n][96] raw features
+    const float* theta;      // [n][8] or null
+    int64_t n;
+    int batch, steps_per_epoch;
+    const int64_t* perm_ab;  // [epochs][2]
+    const int32_t* step;     // device step counter, or null
+    const float* fmean;
+    const float* fsd;
+    float tc[8], ts[8];
+};
+
+__device__ __forceinline__ int64_t map_row(const RowMap& r, int st, int b)
+{
+    if (!r.step) return b;
+    const int e = st / r.steps_per_epoch;
+    const int64_t j = (int64_t)(st % r.steps_per_epoch) * r.batch + b;
+    return (r.perm_ab[2 * e] * j + r.perm_ab[2 * e + 1]) % r.n;  // a, j < n < 2^31: no overflow
+}
+
+// batch row b of step st, assembled by 128 threads (t = 0..127): standardised
+// features to X [batch][96] as bf16, standardised theta to T [batch][8]
+__device__ __forceinline__ void gather_row(const RowMap& rm, int st, int b, int t, bf16* X, float* T)
+{
+    const int64_t row = map_row(rm, st, b);
+    if (t < NN_IN) X[(int64_t)b * NN_IN + t] = f2bf((rm.features[row * NN_IN + t] - rm.fmean[t]) / rm.fsd[t]);
+    if (rm.theta && t < NN_D) T[(int64_t)b * NN_D + t] = (rm.theta[row * NN_D + t] - rm.tc[t]) / rm.ts[t];
+}
+
+// one workgroup of 128 threads per batch row, at the counter's step; clears
+// loss_acc (nullable) for the batch's loss sum
+__global__ __launch_bounds__(128) void k_gather(RowMap rm, bf16* X, float* T, float* loss_acc)
+{
+    if (loss_acc && blockIdx.x == 0 && threadIdx.x == 0) *loss_acc = 0.0f;
+    gather_row(rm, rm.step ? *rm.step : 0, blockIdx.x, threadIdx.x, X, T);
+}
+
+// ----------------------------------------------------------------------------
 // BF16 MFMA GEMM: C[M][N] = op(A)[M][K] op(B)[K][N], float32 accumulation.
 // op(A)[m][k] = A[m lda + k] (TA = false) or A[k lda + m] (TA = true);
 // op(B)[k][n] = B[k ldb + n] (TB = false) or B[n ldb + k] (TB = true).
 // 64x64 workgroup tile, 4 wavefronts of 32x32, v_mfma_f32_16x16x32_bf16
-// fragments, K staged through LDS in steps of 32. Epilogues:
+// fragments, K staged through LDS in tiles of 64. Epilogues:
 //   EPI_STORE    C (float32), optional + bias[n]
 //   EPI_GELU     Z = acc + bias -> C (float32), H = gelu(Z) as bf16
 //   EPI_DGELU    acc * gelu'(Zin) -> C (float32) and H (bf16)
 // grid.z splits K into equal ranges; split z writes C + z * split_stride.
 // ----------------------------------------------------------------------------
 constexpr int EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2;
-constexpr int G_BM = 64, G_BN = 64, G_BK = 32, G_LD = G_BK + 8;
+constexpr int G_BM = 64, G_BN = 64, G_BK = 64, G_LD = G_BK + 8;
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
@@ -199,106 +243,104 @@ struct GemmArgs {
     int ldh;
     const float* Zin;
     float* cs;  // EPI_DGELU: column-sum partials [row tiles][N], or null
+    int gx, gy;          // tile grid (columns, rows); grid.z = splits
+    int32_t* step_inc;   // non-null: tile (0, 0, 0) advances this counter by one
 };
 
-// Staging of one K tile (BK = 32) into registers, then LDS. VEC: every
-// operand row, column count and K range is a multiple of 8 elements and
-// 16-byte aligned, so each thread holds one 8-element vector of A and one of B
-// per K tile (one global load each); otherwise eight scalars each.
+// Staging of one K tile (BK = 64) into registers, then LDS. Each thread holds
+// G_NV = 2 eight-element vectors of A and of B per tile; vector v = tid + 256 h.
+// Where K is contiguous in memory (A untransposed, B transposed) vector v is
+// row v / 8, k = 8 (v % 8); where rows are contiguous it is k = v / 8, rows
+// 8 (v % 8) + 0..7. VEC: every operand row, column count and K range is a
+// multiple of 8 elements and 16-byte aligned, so a vector is one global load;
+// otherwise it is eight scalar loads of the same elements.
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int G_NV = G_BM * G_BK / 8 / 256;
 
 template <bool TA, bool TB, bool VEC>
 struct TileRegs {
-    us8 a, b;
+    us8 a[G_NV], b[G_NV];
+
+    // element (r, k) of the tile for a K-contiguous (KC) or row-contiguous operand
+    template <bool KC>
+    __device__ static __forceinline__ void vec_pos(int v, int& r, int& k)
+    {
+        if (KC) { r = v >> 3; k = (v & 7) * 8; }
+        else { k = v >> 3; r = (v & 7) * 8; }
+    }
+
+    template <bool KC>
+    __device__ static __forceinline__ us8 load_vec(const bf16* X, int ld, int rows, int r, int k, int kend)
+    {
+        us8 out = {0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (VEC) {
+            if (r < rows && k < kend)
+                out = KC ? *reinterpret_cast<const us8*>(X + (int64_t)r * ld + k)
+                         : *reinterpret_cast<const us8*>(X + (int64_t)k * ld + r);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int rr = KC ? r : r + q, kk = KC ? k + q : k;
+                if (rr < rows && kk < kend)
+                    out[q] = KC ? reinterpret_cast<const unsigned short*>(X)[(int64_t)rr * ld + kk]
+                                : reinterpret_cast<const unsigned short*>(X)[(int64_t)kk * ld + rr];
+            }
+        }
+        return out;
+    }
 
     __device__ __forceinline__ void load(const GemmArgs& g, int tid, int m0, int n0, int k0, int kend)
     {
-        const us8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-        if constexpr (VEC) {
-            if (!TA) {
-                const int gm = m0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
-                a = (gm < g.M && gk < kend) ? *reinterpret_cast<const us8*>(g.A + (int64_t)gm * g.lda + gk)
-                                            : zero;
-            } else {
-                const int gm = m0 + (tid & 7) * 8, gk = k0 + (tid >> 3);
-                a = (gm < g.M && gk < kend) ? *reinterpret_cast<const us8*>(g.A + (int64_t)gk * g.lda + gm)
-                                            : zero;
-            }
-            if (TB) {
-                const int gn = n0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
-                b = (gn < g.N && gk < kend) ? *reinterpret_cast<const us8*>(g.B + (int64_t)gn * g.ldb + gk)
-                                            : zero;
-            } else {
-                const int gn = n0 + (tid & 7) * 8, gk = k0 + (tid >> 3);
-                b = (gn < g.N && gk < kend) ? *reinterpret_cast<const us8*>(g.B + (int64_t)gk * g.ldb + gn)
-                                            : zero;
-            }
-        } else {
-            // element e = 8 tid + q of the 64 x 32 tile, in the operand's memory order
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = 8 * tid + q;
-                int mm, kk;
-                if (TA) { kk = e / G_BM; mm = e % G_BM; }
-                else { mm = e / G_BK; kk = e % G_BK; }
-                const int gm = m0 + mm, gk = k0 + kk;
-                a[q] = (gm < g.M && gk < kend) ? (TA ? g.A[(int64_t)gk * g.lda + gm] : g.A[(int64_t)gm * g.lda + gk])
-                                               : (unsigned short)0;
-                int nn;
-                if (TB) { nn = e / G_BK; kk = e % G_BK; }
-                else { kk = e / G_BN; nn = e % G_BN; }
-                const int gn = n0 + nn, gk2 = k0 + kk;
-                b[q] = (gn < g.N && gk2 < kend) ? (TB ? g.B[(int64_t)gn * g.ldb + gk2] : g.B[(int64_t)gk2 * g.ldb + gn])
-                                                : (unsigned short)0;
-            }
+        for (int h = 0; h < G_NV; ++h) {
+            const int v = tid + 256 * h;
+            int r, k;
+            vec_pos<!TA>(v, r, k);
+            a[h] = load_vec<!TA>(g.A, g.lda, g.M, m0 + r, k0 + k, kend);
+            vec_pos<TB>(v, r, k);
+            b[h] = load_vec<TB>(g.B, g.ldb, g.N, n0 + r, k0 + k, kend);
+        }
+    }
+
+    template <bool KC>
+    __device__ static __forceinline__ void store_vec(bf16 (*S)[G_LD], int v, const us8& x)
+    {
+        int r, k;
+        vec_pos<KC>(v, r, k);
+        if (KC) {
+            *reinterpret_cast<us8*>(&S[r][k]) = x;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) reinterpret_cast<unsigned short*>(&S[r + q][k])[0] = x[q];
         }
     }
 
     __device__ __forceinline__ void store(bf16 (*As)[G_LD], bf16 (*Bs)[G_LD], int tid) const
     {
-        if constexpr (VEC) {
-            if (!TA) {
-                *reinterpret_cast<us8*>(&As[tid >> 2][(tid & 3) * 8]) = a;
-            } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) As[(tid & 7) * 8 + q][tid >> 3] = a[q];
-            }
-            if (TB) {
-                *reinterpret_cast<us8*>(&Bs[tid >> 2][(tid & 3) * 8]) = b;
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) Bs[(tid & 7) * 8 + q][tid >> 3] = b[q];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = 8 * tid + q;
-                if (TA) As[e % G_BM][e / G_BM] = a[q];
-                else As[e / G_BK][e % G_BK] = a[q];
-                if (TB) Bs[e / G_BK][e % G_BK] = b[q];
-                else Bs[e % G_BN][e / G_BN] = b[q];
-            }
+        for (int h = 0; h < G_NV; ++h) {
+            store_vec<!TA>(As, tid + 256 * h, a[h]);
+            store_vec<TB>(Bs, tid + 256 * h, b[h]);
         }
     }
 };
 
-// 64 x 64 workgroup tile, four wavefronts of 32 x 32, K tiles of 32 on
-// gfx950's v_mfma_f32_16x16x32_bf16: lane l supplies row (l & 15) of A and
-// column (l & 15) of B at k = 8 (l >> 4) + 0..7, one 16-byte LDS read per
-// operand fragment, and receives C[4 (l >> 4) + r][l & 15]. The next K tile is
-// loaded into registers while the current one is multiplied. With
-// EPI_DGELU and cs != null, workgroup (x, y) also writes the float32 column
-// sums of its 64 output rows to cs[y][n] (the bias gradient's partials).
+// One 64 x 64 output tile (bx, by) of K split bz: four wavefronts of 32 x 32,
+// K tiles of 64 (two MFMA steps) on gfx950's v_mfma_f32_16x16x32_bf16: lane l
+// supplies row (l & 15) of A and column (l & 15) of B at k = 8 (l >> 4) + 0..7,
+// one 16-byte LDS read per operand fragment, and receives C[4 (l >> 4) + r][l & 15].
+// The next K tile is loaded into registers while the current one is
+// multiplied. With EPI_DGELU and cs != null, tile (bx, by) also writes the
+// float32 column sums of its 64 output rows to cs[by][n] (the bias gradient's
+// partials).
 template <bool TA, bool TB, int EPI, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz, bf16 (*As)[G_LD],
+                                          bf16 (*Bs)[G_LD], float (*cs_sh)[G_BN])
 {
-    __shared__ __align__(16) bf16 As[G_BM][G_LD];
-    __shared__ __align__(16) bf16 Bs[G_BN][G_LD];  // [n][k]
-    __shared__ float cs_sh[2][G_BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * G_BM, n0 = blockIdx.x * G_BN;
-    const int kbeg = blockIdx.z * g.k_per_split;
+    const int m0 = by * G_BM, n0 = bx * G_BN;
+    const int kbeg = bz * g.k_per_split;
     int kend = kbeg + g.k_per_split;
     if (kend > g.K) kend = g.K;
     const int wy = wave >> 1, wx = wave & 1;
@@ -308,28 +350,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
+    if (g.step_inc && bx == 0 && by == 0 && bz == 0 && tid == 0) *g.step_inc += 1;
     TileRegs<TA, TB, VEC> regs;
     regs.load(g, tid, m0, n0, kbeg, kend);
     for (int k0 = kbeg; k0 < kend; k0 += G_BK) {
         regs.store(As, Bs, tid);
         __syncthreads();
         if (k0 + G_BK < kend) regs.load(g, tid, m0, n0, k0 + G_BK, kend);  // next tile in flight
-        const int kq = 8 * (lane >> 4);
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            a[i] = *reinterpret_cast<const bf16x8*>(&As[wy * 32 + i * 16 + (lane & 15)][kq]);
+        for (int kk = 0; kk < G_BK; kk += 32) {
+            const int kq = kk + 8 * (lane >> 4);
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wx * 32 + j * 16 + (lane & 15)][kq]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[wy * 32 + i * 16 + (lane & 15)][kq]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wx * 32 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
-    float* C = g.C + (int64_t)blockIdx.z * g.split_stride;
+    float* C = g.C + (int64_t)bz * g.split_stride;
     float csum[2] = {0.0f, 0.0f};  // this lane's column sums (j = 0, 1) over its rows
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -370,71 +416,77 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
         }
         __syncthreads();
         if (tid < G_BN && n0 + tid < g.N)
-            g.cs[(int64_t)blockIdx.y * g.N + n0 + tid] = cs_sh[0][tid] + cs_sh[1][tid];
+            g.cs[(int64_t)by * g.N + n0 + tid] = cs_sh[0][tid] + cs_sh[1][tid];
     }
 }
 
-// ----------------------------------------------------------------------------
-// batch assembly: rows perm(j) = (a_e j + c_e) mod n of the epoch's affine
-// permutation, features standardised to bf16, theta standardised (float)
-// ----------------------------------------------------------------------------
-struct GatherArgs {
-    const float* features;   // [n][96]
-    const float* theta;      // [n][8]
-    int64_t n;
-    int batch;
-    int steps_per_epoch;
-    const int64_t* perm_ab;  // [epochs][2]
-    const int32_t* step;     // device step counter (null: rows 0..batch-1 in order)
-    const float* fmean;
-    const float* fsd;
-    float tc[8], ts[8];
-    bf16* X;                 // [batch][96]
-    float* T;                // [batch][8]
-};
-
-__global__ void k_gather(GatherArgs a)
+template <bool TA, bool TB, int EPI, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 {
-    const int b = blockIdx.x;
-    int64_t row = b;
-    if (a.step) {
-        const int st = *a.step;
-        const int e = st / a.steps_per_epoch;
-        const int64_t j = (int64_t)(st % a.steps_per_epoch) * a.batch + b;
-        const int64_t pa = a.perm_ab[2 * e], pc = a.perm_ab[2 * e + 1];
-        row = (pa * j + pc) % a.n;  // pa, j < n < 2^31: no overflow
+    __shared__ __align__(16) bf16 As[G_BM][G_LD];
+    __shared__ __align__(16) bf16 Bs[G_BN][G_LD];  // [n][k]
+    __shared__ float cs_sh[2][G_BN];
+    gemm_tile<TA, TB, EPI, VEC>(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bs, cs_sh);
+}
+
+// Two independent products in one launch (both VEC): workgroups [0, nb1) take
+// the tiles of the first in (x, y, z) order, the rest those of the second.
+template <bool TA1, bool TB1, int EPI1, bool TA2, bool TB2, int EPI2>
+__global__ __launch_bounds__(256) void k_gemm_pair(GemmArgs g1, GemmArgs g2, int nb1)
+{
+    __shared__ __align__(16) bf16 As[G_BM][G_LD];
+    __shared__ __align__(16) bf16 Bs[G_BN][G_LD];
+    __shared__ float cs_sh[2][G_BN];
+    int b = blockIdx.x;
+    if (b < nb1) {
+        gemm_tile<TA1, TB1, EPI1, true>(g1, b % g1.gx, (b / g1.gx) % g1.gy, b / (g1.gx * g1.gy), As, Bs, cs_sh);
+    } else {
+        b -= nb1;
+        gemm_tile<TA2, TB2, EPI2, true>(g2, b % g2.gx, (b / g2.gx) % g2.gy, b / (g2.gx * g2.gy), As, Bs, cs_sh);
     }
-    for (int q = threadIdx.x; q < 96; q += blockDim.x)
-        a.X[(int64_t)b * 96 + q] = f2bf((a.features[row * 96 + q] - a.fmean[q]) / a.fsd[q]);
-    if (a.theta && threadIdx.x < 8)
-        a.T[(int64_t)b * 8 + threadIdx.x] = (a.theta[row * 8 + threadIdx.x] - a.tc[threadIdx.x]) / a.ts[threadIdx.x];
 }
 
 // ----------------------------------------------------------------------------
 // mixture negative log-likelihood and its gradient w.r.t. the 136 outputs
-// (divided by the batch size); loss_acc[0] += sum of NLL / batch
+// (divided by the batch size); the loss (sum of NLL / batch) is accumulated
+// atomically
 // ----------------------------------------------------------------------------
-// One workgroup of four wavefronts per LOSS_ROWS rows, a wavefront per row at
-// a time; cs != null: the workgroup also writes the float32 column sums of
-// its rows' gradient, cs[blockIdx][136] (the output bias's gradient partials).
-constexpr int LOSS_ROWS = 64;
+// One workgroup of LOSS_WAVES wavefronts per LOSS_ROWS rows, a wavefront per
+// row at a time; cs != null: the workgroup also writes the float32 column sums
+// of its rows' gradient, cs[blockIdx][136] (the output bias's gradient partials).
+constexpr int LOSS_ROWS = 64, LOSS_WAVES = 16, LOSS_RPW = LOSS_ROWS / LOSS_WAVES;
 
-__global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float* T, int n,
+__global__ __launch_bounds__(64 * LOSS_WAVES) void k_mdn_loss(const float* out, const float* T, int n,
                                                   float* dout, bf16* dout_b, float* loss_acc,
-                                                  float* cs)
+                                                  const int32_t* step, float* loss_log, float* cs)
 {
     // lane = k NN_D + j holds component k, dimension j
     static_assert(NN_K * NN_D == 64, "one lane per (component, dimension)");
-    __shared__ float red[4];
-    __shared__ float csh[4][NN_OUT];
+    __shared__ float red[LOSS_WAVES];
+    __shared__ float csh[LOSS_WAVES][NN_OUT];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k = lane / NN_D, j = lane % NN_D;
     const float inv_n = 1.0f / (float)n;
     float nll_sum = 0.0f, c_mu = 0.0f, c_ls = 0.0f, c_k = 0.0f;
-    for (int q = 0; q < LOSS_ROWS / 4; ++q) {
-        const int r = blockIdx.x * LOSS_ROWS + wv * (LOSS_ROWS / 4) + q;
-        if (r >= n) break;  // uniform over the wavefront
+    // the wavefront's rows: every load first (rows beyond n read row 0 and
+    // are skipped below), then the arithmetic row by row
+    const int rbase = blockIdx.x * LOSS_ROWS + wv * LOSS_RPW;
+    float lg[LOSS_RPW][NN_K], mu_r[LOSS_RPW], raw_r[LOSS_RPW], t_r[LOSS_RPW];
+#pragma unroll
+    for (int q = 0; q < LOSS_RPW; ++q) {
+        const int r = rbase + q < n ? rbase + q : 0;
         const float* o = out + (int64_t)r * NN_OUT;
+#pragma unroll
+        for (int c = 0; c < NN_K; ++c) lg[q][c] = o[c];
+        mu_r[q] = o[NN_K + lane];
+        raw_r[q] = o[NN_K + NN_K * NN_D + lane];
+        t_r[q] = T[(int64_t)r * NN_D + j];
+    }
+#pragma unroll
+    for (int q = 0; q < LOSS_RPW; ++q) {
+        const int r = rbase + q;
+        if (r >= n) break;  // uniform over the wavefront
+        const float* o = lg[q];
         float* g = dout + (int64_t)r * NN_OUT;
         bf16* gb = dout_b + (int64_t)r * NN_OUT;
         // log-softmax of the mixture logits (every lane, same values)
@@ -446,16 +498,18 @@ __global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float*
         for (int c = 0; c < NN_K; ++c) se += expf(o[c] - lmax);
         const float lse_logits = lmax + logf(se);
         // this lane's Gaussian factor
-        const float mu = o[NN_K + lane];
-        const float raw = o[NN_K + NN_K * NN_D + lane];
+        const float mu = mu_r[q];
+        const float raw = raw_r[q];
         const float ls = fminf(fmaxf(raw, LOGSIG_LO), LOGSIG_HI);
         const float si = expf(-ls);
-        const float u = (T[(int64_t)r * NN_D + j] - mu) * si;
+        const float u = (t_r[q] - mu) * si;
         float term = -0.5f * u * u - ls;
         term += __shfl_xor(term, 1, 64);
         term += __shfl_xor(term, 2, 64);
         term += __shfl_xor(term, 4, 64);
-        const float logit = o[k];
+        float logit = o[0];  // o[k] by selects: k varies over the lanes
+#pragma unroll
+        for (int c = 1; c < NN_K; ++c) logit = k == c ? o[c] : logit;
         const float Lk = logit - lse_logits - 0.5f * NN_D * 1.83787706640934548356f + term;
         // log-sum-exp over the components (the 8 lane groups)
         float Lmax = Lk;
@@ -491,24 +545,37 @@ __global__ __launch_bounds__(256) void k_mdn_loss(const float* out, const float*
         if (j == 0) csh[wv][k] = c_k;
     }
     __syncthreads();
-    // one atomic per workgroup for the logged loss (its value only)
-    if (threadIdx.x == 0 && loss_acc) atomicAdd(loss_acc, (red[0] + red[1] + red[2] + red[3]) / (float)n);
+    // one atomic per workgroup for the loss (its value only): into the log
+    // entry of the counter's step when training, else into loss_acc
+    float* dst = loss_log ? loss_log + *step : loss_acc;
+    if (threadIdx.x == 0 && dst) {
+        float t = 0.0f;
+        for (int w = 0; w < LOSS_WAVES; ++w) t += red[w];
+        atomicAdd(dst, t / (float)n);
+    }
     if (cs && threadIdx.x < NN_OUT) {
         const int c = threadIdx.x;
-        cs[(int64_t)blockIdx.x * NN_OUT + c] = ((csh[0][c] + csh[1][c]) + csh[2][c]) + csh[3][c];
+        float t = 0.0f;
+        for (int w = 0; w < LOSS_WAVES; ++w) t += csh[w][c];
+        cs[(int64_t)blockIdx.x * NN_OUT + c] = t;
     }
 }
 
 // ----------------------------------------------------------------------------
 // Adam (Kingma & Ba) on the float32 master parameters, then the bf16 copies
-// of the weights; the step counter advances after every update
+// of the weights
 // ----------------------------------------------------------------------------
 // The gradient of every parameter from its partials, added in fixed order:
 // a weight entry from the split-K partials of its layer's product (split
 // order), a bias entry from the column-sum partials of its layer (row-block
-// order). With adam, the same thread then applies Adam (Kingma & Ba) to the
-// float32 master parameter and refreshes its bf16 copy; the step counter
-// advances afterwards (k_step_inc).
+// order). With adam, the same thread then applies Adam to the float32 master
+// parameter, at the update count the step counter holds (the first backward
+// launch has advanced it), and refreshes its bf16 copy. With gather_rows > 0
+// the workgroups after the parameters' assemble the next step's batch (two
+// rows each) while the partials are summed: the step's products are done
+// with X and T.
+constexpr int FIN_PARAM_BLOCKS = (int)((NN_PARAMS + 255) / 256);
+
 struct FinishArgs {
     const float* part1;   // [splits][96][256]
     const float* part2;   // [splits][256][256]
@@ -526,10 +593,21 @@ struct FinishArgs {
     bf16* pb;
     const int32_t* step;
     float lr, b1, b2, eps;
+    int gather_rows;      // batch rows to assemble for the next step (0: none)
+    int64_t steps_total;  // no batch is assembled once the counter reaches it
+    RowMap rm;
+    bf16* X;
+    float* T;
 };
 
-__global__ void k_grad_finish(FinishArgs a)
+__global__ __launch_bounds__(256) void k_grad_finish(FinishArgs a)
 {
+    if (blockIdx.x >= FIN_PARAM_BLOCKS) {
+        const int st = *a.step;
+        const int b = 2 * (blockIdx.x - FIN_PARAM_BLOCKS) + (threadIdx.x >> 7);
+        if (st < a.steps_total && b < a.gather_rows) gather_row(a.rm, st, b, threadIdx.x & 127, a.X, a.T);
+        return;
+    }
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= NN_PARAMS) return;
     const float* src;
@@ -554,7 +632,7 @@ __global__ void k_grad_finish(FinishArgs a)
     for (; z < cnt; ++z) gsum += src[(int64_t)z * stride];
     a.g[e] = gsum;
     if (!a.adam) return;
-    const int st = *a.step + 1;
+    const int st = *a.step;  // updates so far, this one included
     const float m = a.b1 * a.m[e] + (1.0f - a.b1) * gsum;
     const float v = a.b2 * a.v[e] + (1.0f - a.b2) * gsum * gsum;
     a.m[e] = m;
@@ -564,14 +642,6 @@ __global__ void k_grad_finish(FinishArgs a)
     const float p = a.p[e] - a.lr * mh / (sqrtf(vh) + a.eps);
     a.p[e] = p;
     a.pb[e] = f2bf(p);
-}
-
-__global__ void k_step_inc(int32_t* step, float* loss_log, const float* loss_acc)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (loss_log) loss_log[*step] = *loss_acc;
-        *step += 1;
-    }
 }
 
 __global__ void k_zero_f32(float* p, int64_t n)
@@ -646,23 +716,49 @@ __global__ __launch_bounds__(256) void k_mdn_sample(SampleArgs a)
 static int k_per_split_for(int K) { return K >= 512 ? 128 : ((K + G_BK - 1) / G_BK) * G_BK; }
 static int splits_for(int K) { const int kps = k_per_split_for(K); return (K + kps - 1) / kps; }
 
-// kps = K range per split (0: the whole K in one split)
+// kps = K range per split (0: the whole K in one split); returns whether the
+// operands allow the vector loads
+template <bool TA, bool TB>
+static bool gemm_prep(GemmArgs& g, int kps)
+{
+    g.k_per_split = kps > 0 ? kps : ((g.K + G_BK - 1) / G_BK) * G_BK;
+    g.split_stride = (int64_t)g.M * g.N;
+    g.gx = (g.N + G_BN - 1) / G_BN;
+    g.gy = (g.M + G_BM - 1) / G_BM;
+    return g.M % 8 == 0 && g.N % 8 == 0 && g.K % 8 == 0 && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
+           g.k_per_split % 8 == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15u) == 0 &&
+           (reinterpret_cast<uintptr_t>(g.B) & 15u) == 0;
+}
+
+static int splits_of(const GemmArgs& g) { return (g.K + g.k_per_split - 1) / g.k_per_split; }
+
 template <bool TA, bool TB, int EPI>
 static void gemm(const GemmArgs& g0, int kps, hipStream_t s)
 {
     GemmArgs g = g0;
-    g.k_per_split = kps > 0 ? kps : ((g.K + G_BK - 1) / G_BK) * G_BK;
-    const int splits = (g.K + g.k_per_split - 1) / g.k_per_split;
-    g.split_stride = (int64_t)g.M * g.N;
-    const dim3 grid((g.N + G_BN - 1) / G_BN, (g.M + G_BM - 1) / G_BM, splits);
-    const bool vec = g.M % 8 == 0 && g.N % 8 == 0 && g.K % 8 == 0 && g.lda % 8 == 0 &&
-                     g.ldb % 8 == 0 && g.k_per_split % 8 == 0 &&
-                     (reinterpret_cast<uintptr_t>(g.A) & 15u) == 0 &&
-                     (reinterpret_cast<uintptr_t>(g.B) & 15u) == 0;
+    const bool vec = gemm_prep<TA, TB>(g, kps);
+    const dim3 grid(g.gx, g.gy, splits_of(g));
     if (vec)
         hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI, true>), grid, dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI, false>), grid, dim3(256), 0, s, g);
+}
+
+// two independent products in one launch where both allow vector loads
+// (the first one's tiles are dispatched first), else one launch each
+template <bool TA1, bool TB1, int EPI1, bool TA2, bool TB2, int EPI2>
+static void gemm_pair(const GemmArgs& a0, int kps1, const GemmArgs& b0, int kps2, hipStream_t s)
+{
+    GemmArgs a = a0, b = b0;
+    const bool va = gemm_prep<TA1, TB1>(a, kps1), vb = gemm_prep<TA2, TB2>(b, kps2);
+    if (!va || !vb) {
+        gemm<TA1, TB1, EPI1>(a0, kps1, s);
+        gemm<TA2, TB2, EPI2>(b0, kps2, s);
+        return;
+    }
+    const int na = a.gx * a.gy * splits_of(a), nb = b.gx * b.gy * splits_of(b);
+    hipLaunchKernelGGL((k_gemm_pair<TA1, TB1, EPI1, TA2, TB2, EPI2>), dim3(na + nb), dim3(256), 0, s, a, b,
+                       na);
 }
 
 }  // namespace abc
@@ -737,24 +833,27 @@ abc_status ensure_ws(abc_mdn* n, int rows)
     return ABC_OK;
 }
 
-void launch_gather(abc_mdn* net, const float* features, const float* theta, int64_t n_rows,
-                   int batch, int steps_per_epoch, const int64_t* perm, const int32_t* step,
-                   hipStream_t s)
+// the batch's rows: rows 0..batch-1 in order without a step counter
+RowMap row_map(const abc_mdn* net, const float* features, const float* theta, int64_t n_rows,
+               int batch, int steps_per_epoch, const int64_t* perm, const int32_t* step)
 {
-    GatherArgs ga{};
-    ga.features = features;
-    ga.theta = theta;
-    ga.n = n_rows;
-    ga.batch = batch;
-    ga.steps_per_epoch = steps_per_epoch;
-    ga.perm_ab = perm;
-    ga.step = step;
-    ga.fmean = net->fmean;
-    ga.fsd = net->fsd;
-    for (int j = 0; j < 8; ++j) { ga.tc[j] = net->tc[j]; ga.ts[j] = net->ts[j]; }
-    ga.X = net->X;
-    ga.T = net->T;
-    hipLaunchKernelGGL(k_gather, dim3(batch), dim3(128), 0, s, ga);
+    RowMap r{};
+    r.features = features;
+    r.theta = theta;
+    r.n = n_rows;
+    r.batch = batch;
+    r.steps_per_epoch = steps_per_epoch;
+    r.perm_ab = perm;
+    r.step = step;
+    r.fmean = net->fmean;
+    r.fsd = net->fsd;
+    for (int j = 0; j < 8; ++j) { r.tc[j] = net->tc[j]; r.ts[j] = net->ts[j]; }
+    return r;
+}
+
+void launch_gather(abc_mdn* net, const RowMap& rm, int rows, float* loss_acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather, dim3(rows), dim3(128), 0, s, rm, net->X, net->T, loss_acc);
 }
 
 void forward(abc_mdn* net, int n, hipStream_t s)
@@ -777,42 +876,43 @@ void forward(abc_mdn* net, int n, hipStream_t s)
 }
 
 // loss and the gradient partials of the mean NLL (forward must have run); the
-// gradient itself is formed by k_grad_finish
-void backward(abc_mdn* net, int n, hipStream_t s)
+// gradient itself is formed by k_grad_finish. The weight gradient of a layer
+// and the next layer's input gradient do not depend on each other and share
+// a launch. Training (step != null): the loss goes to loss_log[step] and the
+// first backward launch advances the step counter (no kernel of this launch
+// reads it).
+void backward(abc_mdn* net, int n, int32_t* step, float* loss_log, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mdn_loss, dim3((n + LOSS_ROWS - 1) / LOSS_ROWS), dim3(256), 0, s, net->OUT,
-                       net->T, n, net->dOUT, net->dOUTb, net->loss_acc, net->cs3);
+    hipLaunchKernelGGL(k_mdn_loss, dim3((n + LOSS_ROWS - 1) / LOSS_ROWS), dim3(64 * LOSS_WAVES), 0, s, net->OUT,
+                       net->T, n, net->dOUT, net->dOUTb, net->loss_acc, step, step ? loss_log : nullptr, net->cs3);
     const int kps = k_per_split_for(n);
-    // dW3 = H2^T dOUT (db3: the loss kernel's column partials)
-    GemmArgs g{};
-    g.M = NN_H; g.N = NN_OUT; g.K = n;
-    g.A = net->H2; g.lda = NN_H; g.B = net->dOUTb; g.ldb = NN_OUT;
-    g.C = net->part3; g.ldc = NN_OUT;
-    gemm<true, false, EPI_STORE>(g, kps, s);
-    // dZ2 = (dOUT W3^T) gelu'(Z2), with the column partials of db2
-    g = GemmArgs{};
-    g.M = n; g.N = NN_H; g.K = NN_OUT;
-    g.A = net->dOUTb; g.lda = NN_OUT; g.B = net->pb + OFF_W3; g.ldb = NN_OUT;
-    g.C = net->dZ2; g.ldc = NN_H; g.Zin = net->Z2; g.H = net->dZ2b; g.ldh = NN_H; g.cs = net->cs2;
-    gemm<false, true, EPI_DGELU>(g, 0, s);
-    // dW2 = H1^T dZ2
-    g = GemmArgs{};
-    g.M = NN_H; g.N = NN_H; g.K = n;
-    g.A = net->H1; g.lda = NN_H; g.B = net->dZ2b; g.ldb = NN_H;
-    g.C = net->part2; g.ldc = NN_H;
-    gemm<true, false, EPI_STORE>(g, kps, s);
-    // dZ1 = (dZ2 W2^T) gelu'(Z1), with the column partials of db1
-    g = GemmArgs{};
-    g.M = n; g.N = NN_H; g.K = NN_H;
-    g.A = net->dZ2b; g.lda = NN_H; g.B = net->pb + OFF_W2; g.ldb = NN_H;
-    g.C = net->dZ1; g.ldc = NN_H; g.Zin = net->Z1; g.H = net->dZ1b; g.ldh = NN_H; g.cs = net->cs1;
-    gemm<false, true, EPI_DGELU>(g, 0, s);
+    // dZ2 = (dOUT W3^T) gelu'(Z2), with the column partials of db2; dW3 = H2^T dOUT
+    // (db3: the loss kernel's column partials)
+    GemmArgs d{}, w{};
+    d.M = n; d.N = NN_H; d.K = NN_OUT;
+    d.A = net->dOUTb; d.lda = NN_OUT; d.B = net->pb + OFF_W3; d.ldb = NN_OUT;
+    d.C = net->dZ2; d.ldc = NN_H; d.Zin = net->Z2; d.H = net->dZ2b; d.ldh = NN_H; d.cs = net->cs2;
+    d.step_inc = step;
+    w.M = NN_H; w.N = NN_OUT; w.K = n;
+    w.A = net->H2; w.lda = NN_H; w.B = net->dOUTb; w.ldb = NN_OUT;
+    w.C = net->part3; w.ldc = NN_OUT;
+    gemm_pair<false, true, EPI_DGELU, true, false, EPI_STORE>(d, 0, w, kps, s);
+    // dZ1 = (dZ2 W2^T) gelu'(Z1), with the column partials of db1; dW2 = H1^T dZ2
+    d = GemmArgs{};
+    w = GemmArgs{};
+    d.M = n; d.N = NN_H; d.K = NN_H;
+    d.A = net->dZ2b; d.lda = NN_H; d.B = net->pb + OFF_W2; d.ldb = NN_H;
+    d.C = net->dZ1; d.ldc = NN_H; d.Zin = net->Z1; d.H = net->dZ1b; d.ldh = NN_H; d.cs = net->cs1;
+    w.M = NN_H; w.N = NN_H; w.K = n;
+    w.A = net->H1; w.lda = NN_H; w.B = net->dZ2b; w.ldb = NN_H;
+    w.C = net->part2; w.ldc = NN_H;
+    gemm_pair<false, true, EPI_DGELU, true, false, EPI_STORE>(d, 0, w, kps, s);
     // dW1 = X^T dZ1
-    g = GemmArgs{};
-    g.M = NN_IN; g.N = NN_H; g.K = n;
-    g.A = net->X; g.lda = NN_IN; g.B = net->dZ1b; g.ldb = NN_H;
-    g.C = net->part1; g.ldc = NN_H;
-    gemm<true, false, EPI_STORE>(g, kps, s);
+    w = GemmArgs{};
+    w.M = NN_IN; w.N = NN_H; w.K = n;
+    w.A = net->X; w.lda = NN_IN; w.B = net->dZ1b; w.ldb = NN_H;
+    w.C = net->part1; w.ldc = NN_H;
+    gemm<true, false, EPI_STORE>(w, kps, s);
 }
 
 FinishArgs finish_args(abc_mdn* net, int n)
@@ -962,11 +1062,11 @@ extern "C" abc_status abc_mdn_forward(abc_mdn* net, const float* features, int64
                                       void* stream)
 {
     ABC_REQUIRE(net && features && out && n >= 1 && n <= (1 << 20), "bad forward arguments");
+    ABC_REQUIRE((reinterpret_cast<uintptr_t>(features) & 15u) == 0, "features must be 16-byte aligned");
     abc_status rc = ensure_ws(net, (int)n);
     if (rc) return rc;
     const hipStream_t s = as_stream(stream);
-    // rows in order; theta is not needed (zero rows keep the gather simple)
-    launch_gather(net, features, nullptr, n, (int)n, 1, nullptr, nullptr, s);
+    launch_gather(net, row_map(net, features, nullptr, n, (int)n, 1, nullptr, nullptr), (int)n, nullptr, s);
     forward(net, (int)n, s);
     ABC_HIP(hipMemcpyAsync(out, net->OUT, (size_t)n * NN_OUT * sizeof(float), hipMemcpyDeviceToDevice, s));
     return check_launch("abc_mdn_forward");
@@ -976,15 +1076,15 @@ extern "C" abc_status abc_mdn_loss_grad(abc_mdn* net, const float* features, con
                                         int64_t n, float* loss, float* grad, void* stream)
 {
     ABC_REQUIRE(net && features && theta && n >= 1 && n <= (1 << 20), "bad arguments");
+    ABC_REQUIRE((reinterpret_cast<uintptr_t>(features) & 15u) == 0, "features must be 16-byte aligned");
     abc_status rc = ensure_ws(net, (int)n);
     if (rc) return rc;
     const hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, net->loss_acc, (int64_t)1);
-    launch_gather(net, features, theta, n, (int)n, 1, nullptr, nullptr, s);
+    launch_gather(net, row_map(net, features, theta, n, (int)n, 1, nullptr, nullptr), (int)n, net->loss_acc, s);
     forward(net, (int)n, s);
-    backward(net, (int)n, s);
+    backward(net, (int)n, nullptr, nullptr, s);
     const FinishArgs f = finish_args(net, (int)n);
-    hipLaunchKernelGGL(k_grad_finish, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_grad_finish, dim3(FIN_PARAM_BLOCKS), dim3(256), 0, s, f);
     if (loss) ABC_HIP(hipMemcpyAsync(loss, net->loss_acc, sizeof(float), hipMemcpyDeviceToDevice, s));
     if (grad) ABC_HIP(hipMemcpyAsync(grad, net->g, NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s));
     return check_launch("abc_mdn_loss_grad");
@@ -996,6 +1096,7 @@ extern "C" abc_status abc_mdn_train(abc_mdn* net, const float* features, const f
                                     float* train_ms, void* stream)
 {
     ABC_REQUIRE(net && features && theta, "NULL argument");
+    ABC_REQUIRE((reinterpret_cast<uintptr_t>(features) & 15u) == 0, "features must be 16-byte aligned");
     ABC_REQUIRE(n >= batch && batch >= 64 && batch <= 65536 && n < (1ll << 31), "need 64 <= batch <= n < 2^31");
     ABC_REQUIRE(epochs >= 1 && epochs <= 10000, "epochs out of range");
     ABC_REQUIRE(isfinite(lr) && lr > 0.0f, "lr must be positive");
@@ -1036,24 +1137,30 @@ extern "C" abc_status abc_mdn_train(abc_mdn* net, const float* features, const f
     ABC_HIP(hipStreamWaitEvent(s, ev, 0));
     ABC_HIP(hipMemcpyAsync(net->perm, ab.data(), ab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     ABC_HIP(hipMemsetAsync(net->step, 0, sizeof(int32_t), s));
+    if (loss_log) ABC_HIP(hipMemsetAsync(loss_log, 0, (size_t)steps * sizeof(float), s));
     hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, net->m, NN_PARAMS);
     hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, net->v, NN_PARAMS);
+    // the first batch; every step's finish kernel assembles the next one
+    const RowMap rm = row_map(net, features, theta, n, batch, spe, net->perm, net->step);
+    launch_gather(net, rm, batch, nullptr, s);
     ABC_HIP(hipStreamSynchronize(s));
 
     // one training step, captured once and replayed
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ABC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, net->loss_acc, (int64_t)1);
-    launch_gather(net, features, theta, n, batch, spe, net->perm, net->step, s);
     forward(net, batch, s);
-    backward(net, batch, s);
+    backward(net, batch, net->step, loss_log, s);
     FinishArgs f = finish_args(net, batch);
     f.adam = 1;
     f.p = net->p; f.m = net->m; f.v = net->v; f.pb = net->pb; f.step = net->step;
     f.lr = lr; f.b1 = 0.9f; f.b2 = 0.999f; f.eps = 1e-8f;
-    hipLaunchKernelGGL(k_grad_finish, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, net->step, loss_log, net->loss_acc);
+    f.gather_rows = batch;
+    f.steps_total = steps;
+    f.rm = rm;
+    f.X = net->X;
+    f.T = net->T;
+    hipLaunchKernelGGL(k_grad_finish, dim3(FIN_PARAM_BLOCKS + (batch + 1) / 2), dim3(256), 0, s, f);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (ce != hipSuccess) return set_error(ABC_EHIP, "training graph capture: %s", hipGetErrorString(ce));
     struct GF { hipGraph_t g; hipGraphExec_t e; ~GF() { if (e) (void)hipGraphExecDestroy(e); if (g) (void)hipGraphDestroy(g); } } gf{graph, nullptr};

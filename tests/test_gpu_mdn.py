@@ -127,6 +127,78 @@ def test_training_reduces_loss(A):
     net.close()
 
 
+def _affine_perms(n, epochs, seed):
+    """(a_e, c_e) of each epoch as abc_mdn_train draws them: splitmix64 from
+    the shuffle seed, a_e uniform over the units mod n other than 0, c_e
+    uniform mod n."""
+    M = (1 << 64) - 1
+    st = (seed * 0x9E3779B97F4A7C15 + 0x632BE59BD9B4E019) & M
+    out = []
+
+    def nxt():
+        nonlocal st
+        st = (st + 0x9E3779B97F4A7C15) & M
+        z = st
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    for _ in range(epochs):
+        while True:
+            a = nxt() % n
+            if a != 0 and math.gcd(a, n) == 1:
+                break
+        out.append((a, nxt() % n))
+    return out
+
+
+def test_training_steps_are_adam_on_each_batch(A):
+    """The replayed training step against its definition: step k uses batch
+    rows (a_e j + c_e) mod n, j = (k mod steps per epoch) batch + 0..batch-1, of
+    epoch e = k / steps per epoch, logs that batch's loss, and makes one Adam
+    update (t = k + 1) with the gradient loss_grad gives on that batch. The
+    gradients are the same kernels on the same rows, so only the float32 Adam
+    arithmetic may differ (contraction, powf): a wrong batch, update count or
+    order moves parameters by ~lr."""
+    n, batch, epochs, lr, seed = 192, 64, 2, 1e-3, 5
+    feats, theta, _ = A.simulate_features(n, seed=9)
+    net = A.Mdn(3)
+    net.fit_standardizer(feats)
+    p = net.get_params().cpu().numpy()
+    log, steps, _ = net.train(feats, theta, epochs=epochs, batch=batch, lr=lr, shuffle_seed=seed)
+    p_train = net.get_params().cpu().numpy()
+    log = log.cpu().numpy()
+    assert steps == epochs * (n // batch)
+    ref_net = A.Mdn(3)
+    ref_net.fit_standardizer(feats)
+    b1, b2, eps, lr32 = np.float32(0.9), np.float32(0.999), np.float32(1e-8), np.float32(lr)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    spe = n // batch
+    perms = _affine_perms(n, epochs, seed)
+    for k in range(steps):
+        a, c = perms[k // spe]
+        j = (k % spe) * batch + np.arange(batch, dtype=np.int64)
+        rows = torch.from_numpy((a * j + c) % n).cuda()
+        ref_net.set_params(torch.from_numpy(p))
+        loss, g = ref_net.loss_grad(feats[rows], theta[rows])
+        loss = float(loss.item())
+        assert abs(log[k] - loss) <= 1e-5 * abs(loss), (k, log[k], loss)
+        g = g.cpu().numpy()
+        t = k + 1
+        m = b1 * m + (np.float32(1) - b1) * g
+        v = b2 * v + (np.float32(1) - b2) * g * g
+        mh = m / (np.float32(1) - b1 ** np.float32(t))
+        vh = v / (np.float32(1) - b2 ** np.float32(t))
+        p = (p - lr32 * mh / (np.sqrt(vh) + eps)).astype(np.float32)
+    # a parameter whose float32 value differs by an ulp can round to another
+    # bf16 copy, which moves later gradients by a bf16 ulp: a few 1e-6 at most
+    err = np.abs(p_train - p)
+    assert np.median(err) <= 1e-7 and err.max() <= 5e-5, (np.median(err), err.max(), int(err.argmax()))
+    net.close()
+    ref_net.close()
+
+
 def test_sampler_weights_and_importance_identity(A):
     rng = np.random.default_rng(3)
     mix_row = (rng.standard_normal(136) * 0.4).astype(np.float32)
