@@ -639,8 +639,9 @@ def main():
             n_pairs=args.mdn_pairs, epochs=args.mdn_epochs, batch=4096, lr=1e-3, seed=6)
         loss_log = loss_log.cpu().numpy()
         net.close()
-        # one step's products at batch 4096: three forward, five backward
-        flop = 2 * 4096 * (96 * 256 + 256 * 256 + 256 * 136) * 3
+        # one step's products at batch 4096: three forward (x W1, h1 W2, h2 W3)
+        # and five backward (dW3, dZ2, dW2, dZ1, dW1; no gradient w.r.t. x)
+        flop = 2 * 4096 * (2 * 96 * 256 + 3 * 256 * 256 + 3 * 256 * 136)
         print(json.dumps({"workload": "learned-proposal training: %d pairs, %d epochs, batch 4096"
                           % (args.mdn_pairs, args.mdn_epochs), "steps": steps, "train_ms": train_ms,
                           "step_us": 1e3 * train_ms / max(steps, 1), "data_ms": data_ms,

@@ -28,6 +28,8 @@ constexpr int NN_IN = 96, NN_H = 256, NN_K = 8, NN_D = 8, NN_OUT = 136;
 constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + NN_IN * NN_H, OFF_W2 = OFF_B1 + NN_H,
                   OFF_B2 = OFF_W2 + NN_H * NN_H, OFF_W3 = OFF_B2 + NN_H,
                   OFF_B3 = OFF_W3 + NN_H * NN_OUT, NN_PARAMS = OFF_B3 + NN_OUT;
+// the bf16 copies: every parameter, then W3's transpose W3T [136][256]
+constexpr int64_t OFF_W3T = NN_PARAMS, NN_PB = OFF_W3T + NN_H * NN_OUT;
 constexpr float LOGSIG_LO = -7.0f, LOGSIG_HI = 3.0f;
 static_assert(NN_K == MIX_K && NN_D == MIX_D && NN_OUT == MIX_OUT && LOGSIG_LO == MIX_LOGSIG_LO &&
                   LOGSIG_HI == MIX_LOGSIG_HI,
@@ -45,6 +47,17 @@ __device__ __forceinline__ bf16 f2bf(float x)
 }
 
 __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+// the bf16 copy of parameter e, and of its W3T entry for W3
+__device__ __forceinline__ void put_bf16(bf16* pb, int64_t e, float p)
+{
+    const bf16 h = f2bf(p);
+    pb[e] = h;
+    if (e >= OFF_W3 && e < OFF_B3) {
+        const int64_t q = e - OFF_W3;  // W3 [256][136]: q = k 136 + c
+        pb[OFF_W3T + (q % NN_OUT) * NN_H + q / NN_OUT] = h;
+    }
+}
 
 __device__ __forceinline__ float gelu_f(float z)
 {
@@ -220,11 +233,15 @@ __global__ __launch_bounds__(128) void k_gather(RowMap rm, bf16* X, float* T, fl
 // fragments, K staged through LDS in tiles of 64. Epilogues:
 //   EPI_STORE    C (float32), optional + bias[n]
 //   EPI_GELU     Z = acc + bias -> C (float32), H = gelu(Z) as bf16
-//   EPI_DGELU    acc * gelu'(Zin) -> C (float32) and H (bf16)
+//   EPI_DGELU    acc * gelu'(Zin) -> H (bf16; Zin has H's row stride)
 // grid.z splits K into equal ranges; split z writes C + z * split_stride.
 // ----------------------------------------------------------------------------
 constexpr int EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2;
 constexpr int G_BM = 64, G_BN = 64, G_BK = 64, G_LD = G_BK + 8;
+constexpr int G_NT = 4, G_KMAX = G_NT * G_BK;  // K range of one workgroup: at most 4 tiles
+// the products that are not split over K (forward, input gradients) reduce
+// over a layer width
+static_assert(NN_IN <= G_KMAX && NN_H <= G_KMAX && NN_OUT <= G_KMAX, "layer widths fit one K range");
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
@@ -335,8 +352,8 @@ struct TileRegs {
 // float32 column sums of its 64 output rows to cs[by][n] (the bias gradient's
 // partials).
 template <bool TA, bool TB, int EPI, bool VEC>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz, bf16 (*As)[G_LD],
-                                          bf16 (*Bs)[G_LD], float (*cs_sh)[G_BN])
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz, bf16 (*Ab)[G_BM][G_LD],
+                                          bf16 (*Bb)[G_BN][G_LD], float (*cs_sh)[G_BN])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = by * G_BM, n0 = bx * G_BN;
@@ -351,12 +368,42 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
     if (g.step_inc && bx == 0 && by == 0 && bz == 0 && tid == 0) *g.step_inc += 1;
-    TileRegs<TA, TB, VEC> regs;
-    regs.load(g, tid, m0, n0, kbeg, kend);
-    for (int k0 = kbeg; k0 < kend; k0 += G_BK) {
-        regs.store(As, Bs, tid);
+    // every K tile of the range is requested before the first is used: one
+    // memory round trip per workgroup instead of one per tile
+    TileRegs<TA, TB, VEC> regs[G_NT];
+#pragma unroll
+    for (int t = 0; t < G_NT; ++t) regs[t].load(g, tid, m0, n0, kbeg + t * G_BK, kend);
+    // the epilogue's bias and (EPI_DGELU) Zin values are requested with the operands
+    float bias[2] = {0.0f, 0.0f};
+    if (EPI != EPI_DGELU && g.bias) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wx * 32 + j * 16 + (lane & 15);
+            bias[j] = n < g.N ? g.bias[n] : 0.0f;
+        }
+    }
+    float zin[2][2][4];
+    if (EPI == EPI_DGELU) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wy * 32 + i * 16 + 4 * (lane >> 4) + r;
+                    const int n = n0 + wx * 32 + j * 16 + (lane & 15);
+                    zin[i][j][r] = (m < g.M && n < g.N) ? g.Zin[(int64_t)m * g.ldh + n] : 0.0f;
+                }
+    }
+#pragma unroll
+    for (int t = 0; t < G_NT; ++t) {
+        if (kbeg + t * G_BK >= kend) break;  // uniform
+        // two LDS buffers: the barrier after this store also orders every
+        // wavefront's reads of buffer t & 1 two tiles ago before it
+        bf16 (*As)[G_LD] = Ab[t & 1];
+        bf16 (*Bs)[G_LD] = Bb[t & 1];
+        regs[t].store(As, Bs, tid);
         __syncthreads();
-        if (k0 + G_BK < kend) regs.load(g, tid, m0, n0, k0 + G_BK, kend);  // next tile in flight
 #pragma unroll
         for (int kk = 0; kk < G_BK; kk += 32) {
             const int kq = kk + 8 * (lane >> 4);
@@ -373,7 +420,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
     float* C = g.C + (int64_t)bz * g.split_stride;
     float csum[2] = {0.0f, 0.0f};  // this lane's column sums (j = 0, 1) over its rows
@@ -388,15 +434,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][j][r];
                 if (EPI == EPI_STORE) {
-                    if (g.bias) v += g.bias[n];
+                    v += bias[j];
                     C[(int64_t)m * g.ldc + n] = v;
                 } else if (EPI == EPI_GELU) {
-                    v += g.bias[n];
+                    v += bias[j];
                     C[(int64_t)m * g.ldc + n] = v;
                     g.H[(int64_t)m * g.ldh + n] = f2bf(gelu_f(v));
                 } else {
-                    v *= gelu_grad_f(g.Zin[(int64_t)m * g.ldc + n]);
-                    C[(int64_t)m * g.ldc + n] = v;
+                    v *= gelu_grad_f(zin[i][j][r]);
                     g.H[(int64_t)m * g.ldh + n] = f2bf(v);
                     csum[j] += v;
                 }
@@ -423,8 +468,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int
 template <bool TA, bool TB, int EPI, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 {
-    __shared__ __align__(16) bf16 As[G_BM][G_LD];
-    __shared__ __align__(16) bf16 Bs[G_BN][G_LD];  // [n][k]
+    __shared__ __align__(16) bf16 As[2][G_BM][G_LD];
+    __shared__ __align__(16) bf16 Bs[2][G_BN][G_LD];  // [n][k]
     __shared__ float cs_sh[2][G_BN];
     gemm_tile<TA, TB, EPI, VEC>(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bs, cs_sh);
 }
@@ -434,8 +479,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 template <bool TA1, bool TB1, int EPI1, bool TA2, bool TB2, int EPI2>
 __global__ __launch_bounds__(256) void k_gemm_pair(GemmArgs g1, GemmArgs g2, int nb1)
 {
-    __shared__ __align__(16) bf16 As[G_BM][G_LD];
-    __shared__ __align__(16) bf16 Bs[G_BN][G_LD];
+    __shared__ __align__(16) bf16 As[2][G_BM][G_LD];
+    __shared__ __align__(16) bf16 Bs[2][G_BN][G_LD];
     __shared__ float cs_sh[2][G_BN];
     int b = blockIdx.x;
     if (b < nb1) {
@@ -447,117 +492,224 @@ __global__ __launch_bounds__(256) void k_gemm_pair(GemmArgs g1, GemmArgs g2, int
 }
 
 // ----------------------------------------------------------------------------
-// mixture negative log-likelihood and its gradient w.r.t. the 136 outputs
-// (divided by the batch size); the loss (sum of NLL / batch) is accumulated
-// atomically
+// Output layer and loss in one pass: out = h2 W3 + b3 for 64 rows per
+// workgroup, kept in LDS, then the mixture negative log-likelihood of each
+// row and its gradient w.r.t. the 136 outputs (divided by the batch size, as
+// bf16: the operand of both products that consume it).
+// The loss (sum of NLL / batch) is accumulated atomically.
 // ----------------------------------------------------------------------------
-// One workgroup of LOSS_WAVES wavefronts per LOSS_ROWS rows, a wavefront per
-// row at a time; cs != null: the workgroup also writes the float32 column sums
-// of its rows' gradient, cs[blockIdx][136] (the output bias's gradient partials).
-constexpr int LOSS_ROWS = 64, LOSS_WAVES = 16, LOSS_RPW = LOSS_ROWS / LOSS_WAVES;
+// Product: the workgroup's 64 rows of h2 and all of W3 (as its bf16
+// transpose W3T [136][256], K contiguous) are loaded in one round trip and
+// staged in LDS; wavefront w multiplies rows 16 w..16 w + 15 by the 9 column
+// fragments (136 columns, padded to 144 with zeros) on
+// v_mfma_f32_16x16x32_bf16 and writes them, plus b3, to its own LDS rows.
+// Loss: 8 rows at a time per wavefront, lane 8 r + k holding row r's mixture
+// component k (its logit, 8 means, 8 log sds, and the row's 8 targets), so
+// the per-row sums over components are 8-lane shuffles and no lane repeats
+// another's transcendentals. cs != null: the workgroup also writes the
+// float32 column sums of its rows' gradient, cs[blockIdx][136] (the output
+// bias's gradient partials).
+constexpr int OL_ROWS = 64, OL_WAVES = 4, OL_LD = NN_H + 8, OL_NP = 144, OL_OLD = NN_OUT + 4;
+static_assert(NN_K == 8 && NN_D == 8 && NN_OUT == 136 && NN_H == 256, "output layer layout");
 
-__global__ __launch_bounds__(64 * LOSS_WAVES) void k_mdn_loss(const float* out, const float* T, int n,
-                                                  float* dout, bf16* dout_b, float* loss_acc,
-                                                  const int32_t* step, float* loss_log, float* cs)
+__device__ __forceinline__ float sum8(float v)  // over the 8 lanes of a row
 {
-    // lane = k NN_D + j holds component k, dimension j
-    static_assert(NN_K * NN_D == 64, "one lane per (component, dimension)");
-    __shared__ float red[LOSS_WAVES];
-    __shared__ float csh[LOSS_WAVES][NN_OUT];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int k = lane / NN_D, j = lane % NN_D;
-    const float inv_n = 1.0f / (float)n;
-    float nll_sum = 0.0f, c_mu = 0.0f, c_ls = 0.0f, c_k = 0.0f;
-    // the wavefront's rows: every load first (rows beyond n read row 0 and
-    // are skipped below), then the arithmetic row by row
-    const int rbase = blockIdx.x * LOSS_ROWS + wv * LOSS_RPW;
-    float lg[LOSS_RPW][NN_K], mu_r[LOSS_RPW], raw_r[LOSS_RPW], t_r[LOSS_RPW];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+
+__device__ __forceinline__ float max8(float v)
+{
+    v = fmaxf(v, __shfl_xor(v, 1, 64));
+    v = fmaxf(v, __shfl_xor(v, 2, 64));
+    v = fmaxf(v, __shfl_xor(v, 4, 64));
+    return v;
+}
+
+__device__ __forceinline__ float sum_rows(float v)  // over the 8 rows (lane bits 3..5)
+{
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Orders one wavefront's LDS writes before its lanes read what other lanes
+// wrote: a wavefront-scope fence pair around a wave barrier.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * OL_WAVES) void k_out_loss(const bf16* H2, const bf16* W3T, const float* b3,
+                                                          const float* T, int n, bf16* dout_b,
+                                                          float* loss_acc, const int32_t* step,
+                                                          float* loss_log, float* cs)
+{
+    __shared__ __align__(16) bf16 As[OL_ROWS][OL_LD];
+    __shared__ __align__(16) bf16 Bs[OL_NP][OL_LD];    // [n][k]
+    __shared__ __align__(16) float Os[OL_ROWS][OL_OLD];
+    __shared__ float red[OL_WAVES];
+    __shared__ float csh[OL_WAVES][NN_OUT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m0 = blockIdx.x * OL_ROWS;
+    constexpr int KV = NN_H / 8;                              // 8-element vectors per row
+    constexpr int NA = OL_ROWS * KV / 256, NB = NN_OUT * KV / 256;  // 8 and 17 per thread
+    static_assert(OL_ROWS * KV % 256 == 0 && NN_OUT * KV % 256 == 0, "whole vectors per thread");
+    const us8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    us8 va[NA], vb[NB];
 #pragma unroll
-    for (int q = 0; q < LOSS_RPW; ++q) {
-        const int r = rbase + q < n ? rbase + q : 0;
-        const float* o = out + (int64_t)r * NN_OUT;
-#pragma unroll
-        for (int c = 0; c < NN_K; ++c) lg[q][c] = o[c];
-        mu_r[q] = o[NN_K + lane];
-        raw_r[q] = o[NN_K + NN_K * NN_D + lane];
-        t_r[q] = T[(int64_t)r * NN_D + j];
+    for (int h = 0; h < NA; ++h) {
+        const int v = tid + 256 * h, r = v / KV, kv = v % KV;
+        va[h] = m0 + r < n ? *reinterpret_cast<const us8*>(H2 + (int64_t)(m0 + r) * NN_H + kv * 8) : zero;
     }
 #pragma unroll
-    for (int q = 0; q < LOSS_RPW; ++q) {
-        const int r = rbase + q;
-        if (r >= n) break;  // uniform over the wavefront
-        const float* o = lg[q];
-        float* g = dout + (int64_t)r * NN_OUT;
-        bf16* gb = dout_b + (int64_t)r * NN_OUT;
-        // log-softmax of the mixture logits (every lane, same values)
-        float lmax = -INFINITY;
+    for (int h = 0; h < NB; ++h) {
+        const int v = tid + 256 * h;
+        vb[h] = *reinterpret_cast<const us8*>(W3T + (int64_t)(v / KV) * NN_H + (v % KV) * 8);
+    }
+    // the epilogue's biases and the loss's targets are requested with the operands
+    float bias[OL_NP / 16];
 #pragma unroll
-        for (int c = 0; c < NN_K; ++c) lmax = fmaxf(lmax, o[c]);
-        float se = 0.0f;
+    for (int f = 0; f < OL_NP / 16; ++f) {
+        const int c = 16 * f + (lane & 15);
+        bias[f] = c < NN_OUT ? b3[c] : 0.0f;
+    }
+    const int k = lane & 7;
+    float4 tv[2][2];
 #pragma unroll
-        for (int c = 0; c < NN_K; ++c) se += expf(o[c] - lmax);
-        const float lse_logits = lmax + logf(se);
-        // this lane's Gaussian factor
-        const float mu = mu_r[q];
-        const float raw = raw_r[q];
-        const float ls = fminf(fmaxf(raw, LOGSIG_LO), LOGSIG_HI);
-        const float si = expf(-ls);
-        const float u = (t_r[q] - mu) * si;
-        float term = -0.5f * u * u - ls;
-        term += __shfl_xor(term, 1, 64);
-        term += __shfl_xor(term, 2, 64);
-        term += __shfl_xor(term, 4, 64);
-        float logit = o[0];  // o[k] by selects: k varies over the lanes
+    for (int grp = 0; grp < 2; ++grp) {
+        const int row = m0 + 16 * wv + 8 * grp + (lane >> 3);
+        const float4* t4 = reinterpret_cast<const float4*>(T + (int64_t)(row < n ? row : 0) * NN_D);
+        tv[grp][0] = t4[0];
+        tv[grp][1] = t4[1];
+    }
 #pragma unroll
-        for (int c = 1; c < NN_K; ++c) logit = k == c ? o[c] : logit;
-        const float Lk = logit - lse_logits - 0.5f * NN_D * 1.83787706640934548356f + term;
-        // log-sum-exp over the components (the 8 lane groups)
-        float Lmax = Lk;
-        Lmax = fmaxf(Lmax, __shfl_xor(Lmax, 8, 64));
-        Lmax = fmaxf(Lmax, __shfl_xor(Lmax, 16, 64));
-        Lmax = fmaxf(Lmax, __shfl_xor(Lmax, 32, 64));
-        float sr = expf(Lk - Lmax);
-        sr += __shfl_xor(sr, 8, 64);
-        sr += __shfl_xor(sr, 16, 64);
-        sr += __shfl_xor(sr, 32, 64);
-        const float lse = Lmax + logf(sr);
-        nll_sum += -lse;
-        const float resp = expf(Lk - lse);
-        const float gmu = -resp * u * si * inv_n;
-        const float gls = (raw > LOGSIG_LO && raw < LOGSIG_HI) ? -resp * (u * u - 1.0f) * inv_n : 0.0f;
-        g[NN_K + lane] = gmu;
-        gb[NN_K + lane] = f2bf(gmu);
-        g[NN_K + NN_K * NN_D + lane] = gls;
-        gb[NN_K + NN_K * NN_D + lane] = f2bf(gls);
-        c_mu += gmu;
-        c_ls += gls;
-        if (j == 0) {
-            const float gk = (expf(logit - lse_logits) - resp) * inv_n;
-            g[k] = gk;
-            gb[k] = f2bf(gk);
-            c_k += gk;
+    for (int h = 0; h < NA; ++h) {
+        const int v = tid + 256 * h;
+        *reinterpret_cast<us8*>(&As[v / KV][(v % KV) * 8]) = va[h];
+    }
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
+        const int v = tid + 256 * h;
+        *reinterpret_cast<us8*>(&Bs[v / KV][(v % KV) * 8]) = vb[h];
+    }
+    static_assert((OL_NP - NN_OUT) * KV == 256, "one padding vector per thread");
+    *reinterpret_cast<us8*>(&Bs[NN_OUT + tid / KV][(tid % KV) * 8]) = zero;
+    __syncthreads();
+    float4_t acc[OL_NP / 16];
+#pragma unroll
+    for (int f = 0; f < OL_NP / 16; ++f) acc[f] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < NN_H; kk += 32) {
+        const int kq = kk + 8 * (lane >> 4);
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&As[16 * wv + (lane & 15)][kq]);
+#pragma unroll
+        for (int f = 0; f < OL_NP / 16; ++f) {
+            const bf16x8 bf = *reinterpret_cast<const bf16x8*>(&Bs[16 * f + (lane & 15)][kq]);
+            acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[f], 0, 0, 0);
         }
     }
-    if (lane == 0) red[wv] = nll_sum;
+#pragma unroll
+    for (int f = 0; f < OL_NP / 16; ++f) {
+        const int c = 16 * f + (lane & 15);
+        if (c < NN_OUT) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Os[16 * wv + 4 * (lane >> 4) + r][c] = acc[f][r] + bias[f];
+        }
+    }
+    wave_lds_sync();  // from here on the wavefront reads only its own rows
+
+    const float inv_n = 1.0f / (float)n;
+    float nll = 0.0f, ck = 0.0f, cm[8], cl[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cm[j] = cl[j] = 0.0f;
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+        const int rl = 16 * wv + 8 * grp + (lane >> 3);
+        const int row = m0 + rl;
+        const bool live = row < n;
+        const float* o = &Os[rl][0];
+        const float4* mu4 = reinterpret_cast<const float4*>(o + NN_K + NN_D * k);
+        const float4* raw4 = reinterpret_cast<const float4*>(o + NN_K + NN_K * NN_D + NN_D * k);
+        const float logit = o[k];
+        const float4 m0v = mu4[0], m1v = mu4[1], r0v = raw4[0], r1v = raw4[1], t0v = tv[grp][0], t1v = tv[grp][1];
+        const float mu[8] = {m0v.x, m0v.y, m0v.z, m0v.w, m1v.x, m1v.y, m1v.z, m1v.w};
+        const float raw[8] = {r0v.x, r0v.y, r0v.z, r0v.w, r1v.x, r1v.y, r1v.z, r1v.w};
+        const float t[8] = {t0v.x, t0v.y, t0v.z, t0v.w, t1v.x, t1v.y, t1v.z, t1v.w};
+        // log-softmax of the row's logits
+        const float lmax = max8(logit);
+        const float lse_logits = lmax + logf(sum8(expf(logit - lmax)));
+        // component k's log density: sum over dimensions of -u^2 / 2 - log sd
+        float u[8], si[8], term = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float ls = fminf(fmaxf(raw[j], LOGSIG_LO), LOGSIG_HI);
+            si[j] = expf(-ls);
+            u[j] = (t[j] - mu[j]) * si[j];
+            term += -0.5f * u[j] * u[j] - ls;
+        }
+        const float Lk = logit - lse_logits - 0.5f * NN_D * 1.83787706640934548356f + term;
+        // log-sum-exp over the components
+        const float Lmax = max8(Lk);
+        const float lse = Lmax + logf(sum8(expf(Lk - Lmax)));
+        const float resp = expf(Lk - lse);
+        const float gk = live ? (expf(logit - lse_logits) - resp) * inv_n : 0.0f;
+        float gmu[8], gls[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            gmu[j] = live ? -resp * u[j] * si[j] * inv_n : 0.0f;
+            gls[j] = (live && raw[j] > LOGSIG_LO && raw[j] < LOGSIG_HI) ? -resp * (u[j] * u[j] - 1.0f) * inv_n
+                                                                         : 0.0f;
+        }
+        if (live) {
+            bf16* gb = dout_b + (int64_t)row * NN_OUT;
+            gb[k] = f2bf(gk);
+            us8 bm, bl;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) { bm[j] = f2bf(gmu[j]); bl[j] = f2bf(gls[j]); }
+            *reinterpret_cast<us8*>(gb + NN_K + NN_D * k) = bm;
+            *reinterpret_cast<us8*>(gb + NN_K + NN_K * NN_D + NN_D * k) = bl;
+        }
+        if (live && k == 0) nll += -lse;
+        ck += gk;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) { cm[j] += gmu[j]; cl[j] += gls[j]; }
+    }
+    // the wavefront's loss (rows in lane order) and column sums (8 rows, fixed tree)
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) nll += __shfl_xor(nll, off, 64);
+    if (lane == 0) red[wv] = nll;
     if (cs) {
-        csh[wv][NN_K + lane] = c_mu;
-        csh[wv][NN_K + NN_K * NN_D + lane] = c_ls;
-        if (j == 0) csh[wv][k] = c_k;
+        ck = sum_rows(ck);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) { cm[j] = sum_rows(cm[j]); cl[j] = sum_rows(cl[j]); }
+        if (lane < 8) {
+            csh[wv][k] = ck;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                csh[wv][NN_K + NN_D * k + j] = cm[j];
+                csh[wv][NN_K + NN_K * NN_D + NN_D * k + j] = cl[j];
+            }
+        }
     }
     __syncthreads();
     // one atomic per workgroup for the loss (its value only): into the log
     // entry of the counter's step when training, else into loss_acc
     float* dst = loss_log ? loss_log + *step : loss_acc;
-    if (threadIdx.x == 0 && dst) {
-        float t = 0.0f;
-        for (int w = 0; w < LOSS_WAVES; ++w) t += red[w];
-        atomicAdd(dst, t / (float)n);
+    if (tid == 0 && dst) {
+        float s = 0.0f;
+        for (int w = 0; w < OL_WAVES; ++w) s += red[w];
+        atomicAdd(dst, s / (float)n);
     }
-    if (cs && threadIdx.x < NN_OUT) {
-        const int c = threadIdx.x;
-        float t = 0.0f;
-        for (int w = 0; w < LOSS_WAVES; ++w) t += csh[w][c];
-        cs[(int64_t)blockIdx.x * NN_OUT + c] = t;
+    if (cs && tid < NN_OUT) {
+        float s = 0.0f;
+        for (int w = 0; w < OL_WAVES; ++w) s += csh[w][tid];
+        cs[(int64_t)blockIdx.x * NN_OUT + tid] = s;
     }
 }
 
@@ -619,6 +771,9 @@ __global__ __launch_bounds__(256) void k_grad_finish(FinishArgs a)
     else if (e < OFF_W3) { src = a.cs2 + (e - OFF_B2); stride = NN_H; cnt = a.tiles; }
     else if (e < OFF_B3) { src = a.part3 + (e - OFF_W3); stride = (int64_t)NN_H * NN_OUT; cnt = a.splits; }
     else { src = a.cs3 + (e - OFF_B3); stride = NN_OUT; cnt = a.lblocks; }
+    // Adam's state is requested before the partials are summed
+    float m0 = 0.0f, v0 = 0.0f, p0 = 0.0f;
+    if (a.adam) { m0 = a.m[e]; v0 = a.v[e]; p0 = a.p[e]; }
     // in order, loads issued eight ahead of the adds
     float gsum = 0.0f;
     int z = 0;
@@ -633,15 +788,15 @@ __global__ __launch_bounds__(256) void k_grad_finish(FinishArgs a)
     a.g[e] = gsum;
     if (!a.adam) return;
     const int st = *a.step;  // updates so far, this one included
-    const float m = a.b1 * a.m[e] + (1.0f - a.b1) * gsum;
-    const float v = a.b2 * a.v[e] + (1.0f - a.b2) * gsum * gsum;
+    const float m = a.b1 * m0 + (1.0f - a.b1) * gsum;
+    const float v = a.b2 * v0 + (1.0f - a.b2) * gsum * gsum;
     a.m[e] = m;
     a.v[e] = v;
     const float mh = m / (1.0f - powf(a.b1, (float)st));
     const float vh = v / (1.0f - powf(a.b2, (float)st));
-    const float p = a.p[e] - a.lr * mh / (sqrtf(vh) + a.eps);
+    const float p = p0 - a.lr * mh / (sqrtf(vh) + a.eps);
     a.p[e] = p;
-    a.pb[e] = f2bf(p);
+    put_bf16(a.pb, e, p);
 }
 
 __global__ void k_zero_f32(float* p, int64_t n)
@@ -650,10 +805,10 @@ __global__ void k_zero_f32(float* p, int64_t n)
     if (e < n) p[e] = 0.0f;
 }
 
-__global__ void k_to_bf16(const float* p, int64_t n, bf16* out)
+__global__ void k_params_bf16(const float* p, bf16* pb)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) out[e] = f2bf(p[e]);
+    if (e < NN_PARAMS) put_bf16(pb, e, p[e]);
 }
 
 // initialisation (domain 3 stream): W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), b = 0
@@ -712,8 +867,15 @@ __global__ __launch_bounds__(256) void k_mdn_sample(SampleArgs a)
 }
 
 // K range per split for the weight-gradient products (reduction over the
-// batch): 128 rows per split once K >= 512, else no split.
-static int k_per_split_for(int K) { return K >= 512 ? 128 : ((K + G_BK - 1) / G_BK) * G_BK; }
+// batch): 128 rows per split once K >= 512, else K in ranges of at most
+// G_KMAX.
+static int k_per_split_for(int K)
+{
+    if (K >= 512) return 128;
+    const int tiles = (K + G_BK - 1) / G_BK;
+    const int splits = (tiles + G_NT - 1) / G_NT;
+    return ((tiles + splits - 1) / splits) * G_BK;
+}
 static int splits_for(int K) { const int kps = k_per_split_for(K); return (K + kps - 1) / kps; }
 
 // kps = K range per split (0: the whole K in one split); returns whether the
@@ -778,8 +940,7 @@ struct abc_mdn {
     float lo[8], hi[8], tc[8], ts[8];
     int ws = 0;  // workspace rows
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *dOUTb = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
-    float *T = nullptr, *Z1 = nullptr, *Z2 = nullptr, *OUT = nullptr, *dOUT = nullptr,
-          *dZ2 = nullptr, *dZ1 = nullptr;
+    float *T = nullptr, *Z1 = nullptr, *Z2 = nullptr, *OUT = nullptr;
     // split-K partials of the three weight gradients, column-sum partials of
     // the three bias gradients
     float *part1 = nullptr, *part2 = nullptr, *part3 = nullptr, *cs1 = nullptr, *cs2 = nullptr,
@@ -792,12 +953,12 @@ namespace {
 void free_ws(abc_mdn* n)
 {
     void* ptrs[] = {n->X, n->H1, n->H2, n->dOUTb, n->dZ2b, n->dZ1b, n->T, n->Z1, n->Z2,
-                    n->OUT, n->dOUT, n->dZ2, n->dZ1, n->part1, n->part2, n->part3,
+                    n->OUT, n->part1, n->part2, n->part3,
                     n->cs1, n->cs2, n->cs3};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     n->X = n->H1 = n->H2 = n->dOUTb = n->dZ2b = n->dZ1b = nullptr;
-    n->T = n->Z1 = n->Z2 = n->OUT = n->dOUT = n->dZ2 = n->dZ1 = nullptr;
+    n->T = n->Z1 = n->Z2 = n->OUT = nullptr;
     n->part1 = n->part2 = n->part3 = n->cs1 = n->cs2 = n->cs3 = nullptr;
     n->ws = 0;
 }
@@ -816,18 +977,15 @@ abc_status ensure_ws(abc_mdn* n, int rows)
     ALLOC(n->Z2, r * NN_H * sizeof(float));
     ALLOC(n->H2, r * NN_H * sizeof(bf16));
     ALLOC(n->OUT, r * NN_OUT * sizeof(float));
-    ALLOC(n->dOUT, r * NN_OUT * sizeof(float));
     ALLOC(n->dOUTb, r * NN_OUT * sizeof(bf16));
-    ALLOC(n->dZ2, r * NN_H * sizeof(float));
     ALLOC(n->dZ2b, r * NN_H * sizeof(bf16));
-    ALLOC(n->dZ1, r * NN_H * sizeof(float));
     ALLOC(n->dZ1b, r * NN_H * sizeof(bf16));
     ALLOC(n->part1, (size_t)splits * NN_IN * NN_H * sizeof(float));
     ALLOC(n->part2, (size_t)splits * NN_H * NN_H * sizeof(float));
     ALLOC(n->part3, (size_t)splits * NN_H * NN_OUT * sizeof(float));
     ALLOC(n->cs1, (size_t)((rows + G_BM - 1) / G_BM) * NN_H * sizeof(float));
     ALLOC(n->cs2, (size_t)((rows + G_BM - 1) / G_BM) * NN_H * sizeof(float));
-    ALLOC(n->cs3, (size_t)((rows + LOSS_ROWS - 1) / LOSS_ROWS) * NN_OUT * sizeof(float));
+    ALLOC(n->cs3, (size_t)((rows + OL_ROWS - 1) / OL_ROWS) * NN_OUT * sizeof(float));
 #undef ALLOC
     n->ws = rows;
     return ABC_OK;
@@ -856,7 +1014,8 @@ void launch_gather(abc_mdn* net, const RowMap& rm, int rows, float* loss_acc, hi
     hipLaunchKernelGGL(k_gather, dim3(rows), dim3(128), 0, s, rm, net->X, net->T, loss_acc);
 }
 
-void forward(abc_mdn* net, int n, hipStream_t s)
+// the hidden layers: Z1, H1, Z2, H2 from X
+void forward_hidden(abc_mdn* net, int n, hipStream_t s)
 {
     GemmArgs g{};
     g.M = n; g.N = NN_H; g.K = NN_IN;
@@ -868,30 +1027,37 @@ void forward(abc_mdn* net, int n, hipStream_t s)
     g.A = net->H1; g.lda = NN_H; g.B = net->pb + OFF_W2; g.ldb = NN_H;
     g.C = net->Z2; g.ldc = NN_H; g.bias = net->p + OFF_B2; g.H = net->H2; g.ldh = NN_H;
     gemm<false, false, EPI_GELU>(g, 0, s);
-    g = GemmArgs{};
+}
+
+// the network outputs OUT (inference)
+void forward_out(abc_mdn* net, int n, hipStream_t s)
+{
+    GemmArgs g{};
     g.M = n; g.N = NN_OUT; g.K = NN_H;
     g.A = net->H2; g.lda = NN_H; g.B = net->pb + OFF_W3; g.ldb = NN_OUT;
     g.C = net->OUT; g.ldc = NN_OUT; g.bias = net->p + OFF_B3;
     gemm<false, false, EPI_STORE>(g, 0, s);
 }
 
-// loss and the gradient partials of the mean NLL (forward must have run); the
-// gradient itself is formed by k_grad_finish. The weight gradient of a layer
+// output layer, loss and the gradient partials of the mean NLL
+// (forward_hidden must have run); the gradient itself is formed by
+// k_grad_finish. The weight gradient of a layer
 // and the next layer's input gradient do not depend on each other and share
 // a launch. Training (step != null): the loss goes to loss_log[step] and the
 // first backward launch advances the step counter (no kernel of this launch
 // reads it).
 void backward(abc_mdn* net, int n, int32_t* step, float* loss_log, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mdn_loss, dim3((n + LOSS_ROWS - 1) / LOSS_ROWS), dim3(64 * LOSS_WAVES), 0, s, net->OUT,
-                       net->T, n, net->dOUT, net->dOUTb, net->loss_acc, step, step ? loss_log : nullptr, net->cs3);
+    hipLaunchKernelGGL(k_out_loss, dim3((n + OL_ROWS - 1) / OL_ROWS), dim3(64 * OL_WAVES), 0, s, net->H2,
+                       net->pb + OFF_W3T, net->p + OFF_B3, net->T, n, net->dOUTb, net->loss_acc, step,
+                       step ? loss_log : nullptr, net->cs3);
     const int kps = k_per_split_for(n);
     // dZ2 = (dOUT W3^T) gelu'(Z2), with the column partials of db2; dW3 = H2^T dOUT
     // (db3: the loss kernel's column partials)
     GemmArgs d{}, w{};
     d.M = n; d.N = NN_H; d.K = NN_OUT;
     d.A = net->dOUTb; d.lda = NN_OUT; d.B = net->pb + OFF_W3; d.ldb = NN_OUT;
-    d.C = net->dZ2; d.ldc = NN_H; d.Zin = net->Z2; d.H = net->dZ2b; d.ldh = NN_H; d.cs = net->cs2;
+    d.Zin = net->Z2; d.H = net->dZ2b; d.ldh = NN_H; d.cs = net->cs2;
     d.step_inc = step;
     w.M = NN_H; w.N = NN_OUT; w.K = n;
     w.A = net->H2; w.lda = NN_H; w.B = net->dOUTb; w.ldb = NN_OUT;
@@ -902,7 +1068,7 @@ void backward(abc_mdn* net, int n, int32_t* step, float* loss_log, hipStream_t s
     w = GemmArgs{};
     d.M = n; d.N = NN_H; d.K = NN_H;
     d.A = net->dZ2b; d.lda = NN_H; d.B = net->pb + OFF_W2; d.ldb = NN_H;
-    d.C = net->dZ1; d.ldc = NN_H; d.Zin = net->Z1; d.H = net->dZ1b; d.ldh = NN_H; d.cs = net->cs1;
+    d.Zin = net->Z1; d.H = net->dZ1b; d.ldh = NN_H; d.cs = net->cs1;
     w.M = NN_H; w.N = NN_H; w.K = n;
     w.A = net->H1; w.lda = NN_H; w.B = net->dZ2b; w.ldb = NN_H;
     w.C = net->part2; w.ldc = NN_H;
@@ -922,7 +1088,7 @@ FinishArgs finish_args(abc_mdn* net, int n)
     f.splits = splits_for(n);
     f.cs1 = net->cs1; f.cs2 = net->cs2; f.cs3 = net->cs3;
     f.tiles = (n + G_BM - 1) / G_BM;
-    f.lblocks = (n + LOSS_ROWS - 1) / LOSS_ROWS;
+    f.lblocks = (n + OL_ROWS - 1) / OL_ROWS;
     f.g = net->g;
     return f;
 }
@@ -949,7 +1115,7 @@ extern "C" abc_status abc_mdn_create(const abc_prior* prior, uint64_t init_seed,
     }
     hipError_t e = hipSuccess;
     e = e ? e : hipMalloc((void**)&n->p, NN_PARAMS * sizeof(float));
-    e = e ? e : hipMalloc((void**)&n->pb, NN_PARAMS * sizeof(bf16));
+    e = e ? e : hipMalloc((void**)&n->pb, NN_PB * sizeof(bf16));
     e = e ? e : hipMalloc((void**)&n->m, NN_PARAMS * sizeof(float));
     e = e ? e : hipMalloc((void**)&n->v, NN_PARAMS * sizeof(float));
     e = e ? e : hipMalloc((void**)&n->g, NN_PARAMS * sizeof(float));
@@ -962,7 +1128,7 @@ extern "C" abc_status abc_mdn_create(const abc_prior* prior, uint64_t init_seed,
         return set_error(ABC_EHIP, "abc_mdn_create: %s", hipGetErrorString(e));
     }
     hipLaunchKernelGGL(k_mdn_init, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, 0, n->p, init_seed);
-    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, 0, n->p, NN_PARAMS, n->pb);
+    hipLaunchKernelGGL(k_params_bf16, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, 0, n->p, n->pb);
     hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, 0, n->m, NN_PARAMS);
     hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, 0, n->v, NN_PARAMS);
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(NN_IN), 0, 0, n->fmean, NN_IN);
@@ -1000,9 +1166,8 @@ extern "C" abc_status abc_mdn_params(abc_mdn* n, float** params, float** grads)
 extern "C" abc_status abc_mdn_sync_params(abc_mdn* n, void* stream)
 {
     ABC_REQUIRE(n != nullptr, "net is NULL");
-    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, as_stream(stream), n->p,
-                       NN_PARAMS, n->pb);
-    return check_launch("k_to_bf16");
+    hipLaunchKernelGGL(k_params_bf16, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, as_stream(stream), n->p, n->pb);
+    return check_launch("k_params_bf16");
 }
 
 extern "C" abc_status abc_mdn_simulate_features(const abc_prior* prior, uint64_t seed,
@@ -1067,7 +1232,8 @@ extern "C" abc_status abc_mdn_forward(abc_mdn* net, const float* features, int64
     if (rc) return rc;
     const hipStream_t s = as_stream(stream);
     launch_gather(net, row_map(net, features, nullptr, n, (int)n, 1, nullptr, nullptr), (int)n, nullptr, s);
-    forward(net, (int)n, s);
+    forward_hidden(net, (int)n, s);
+    forward_out(net, (int)n, s);
     ABC_HIP(hipMemcpyAsync(out, net->OUT, (size_t)n * NN_OUT * sizeof(float), hipMemcpyDeviceToDevice, s));
     return check_launch("abc_mdn_forward");
 }
@@ -1081,7 +1247,7 @@ extern "C" abc_status abc_mdn_loss_grad(abc_mdn* net, const float* features, con
     if (rc) return rc;
     const hipStream_t s = as_stream(stream);
     launch_gather(net, row_map(net, features, theta, n, (int)n, 1, nullptr, nullptr), (int)n, net->loss_acc, s);
-    forward(net, (int)n, s);
+    forward_hidden(net, (int)n, s);
     backward(net, (int)n, nullptr, nullptr, s);
     const FinishArgs f = finish_args(net, (int)n);
     hipLaunchKernelGGL(k_grad_finish, dim3(FIN_PARAM_BLOCKS), dim3(256), 0, s, f);
@@ -1149,7 +1315,7 @@ extern "C" abc_status abc_mdn_train(abc_mdn* net, const float* features, const f
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ABC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    forward(net, batch, s);
+    forward_hidden(net, batch, s);
     backward(net, batch, net->step, loss_log, s);
     FinishArgs f = finish_args(net, batch);
     f.adam = 1;
@@ -1215,7 +1381,7 @@ extern "C" abc_status abc_mdn_set_params(abc_mdn* net, const float* src, void* s
     ABC_REQUIRE(net && src, "NULL argument");
     const hipStream_t s = as_stream(stream);
     ABC_HIP(hipMemcpyAsync(net->p, src, NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, net->p, NN_PARAMS, net->pb);
+    hipLaunchKernelGGL(k_params_bf16, dim3(blocks_for(NN_PARAMS)), dim3(256), 0, s, net->p, net->pb);
     return check_launch("abc_mdn_set_params");
 }
 
