@@ -50,7 +50,7 @@ FP32_PEAK_TFLOPS = 157.3
 SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/csrc/multi.hip",
                "paper_2012_14332_amd/csrc/bound.hpp", "paper_2012_14332_amd/csrc/model.hpp",
                "paper_2012_14332_amd/csrc/philox.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_f32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_simulate_multi_f32_traffic.json")
 
 
 def note(text):
@@ -79,7 +79,7 @@ def traffic_per_launch():
     return rec.get("bytes_per_launch")
 
 
-VALU_FILE = os.path.join(ROOT, "profiles", "k_simulate_f32_valu.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_simulate_multi_f32_valu.json")
 
 
 def valu_counters():
@@ -799,17 +799,31 @@ def main():
     avg_ms = float(np.mean(sim_ms))
     days_per_launch = eff_days / launches
     samples_per_launch = N * len(countries) // (launches // args.steps)
-    # algorithmic work of one launch over its average duration (HIP events on
-    # the launch stream): FP32 FLOP against the FP32 vector peak, and VALU issue
-    # (transcendentals weighted by their measured cost) against the issue peak
+    # One launch over its average duration (HIP events on the launch stream).
+    # Algorithmic work from the assembly count (FP32 FLOP, VALU issue in lane
+    # quad-cycles with transcendentals at their measured 2); measured work
+    # from the committed PMC summary of the same kernel and workload (FP32
+    # FLOP = 64 (add + mul + trans + 2 fma), issued quad-cycles =
+    # SQ_ACTIVE_INST_VALU), scaled per sample-day to this launch.
     flop_launch = FP32_FLOP_PER_SAMPLE_DAY * days_per_launch + FP32_FLOP_PER_SAMPLE * samples_per_launch
     issue_launch = ISSUE_QC_PER_SAMPLE_DAY * days_per_launch + ISSUE_QC_PER_SAMPLE * samples_per_launch
-    flops = flop_launch / (avg_ms * 1e-3) / 1e12
-    issue = issue_launch / (avg_ms * 1e-3) / 1e12
-    # the FP32 FLOP rate this instruction mix reaches at 100% VALU issue
-    mix_ceiling = flop_launch / issue_launch * ISSUE_PEAK_T
-    valu_pmc = valu_counters()
-    traffic = traffic_per_launch()
+    flops_alg = flop_launch / (avg_ms * 1e-3) / 1e12
+    issue_alg = issue_launch / (avg_ms * 1e-3) / 1e12
+    valu_pmc = valu_counters() if not args.per_series_launches else None
+    traffic = traffic_per_launch() if not args.per_series_launches else None
+    if valu_pmc:
+        flop_meas = valu_pmc["fp32_flop_per_sample_day"] * days_per_launch
+        qc_meas = valu_pmc["valu_lane_qc_per_sample_day"] * days_per_launch
+        flops = flop_meas / (avg_ms * 1e-3) / 1e12
+        issue_meas = qc_meas / (avg_ms * 1e-3) / 1e12
+        # the FP32 FLOP rate this instruction mix reaches with every VALU
+        # issue slot busy
+        mix_ceiling = flop_meas / qc_meas * ISSUE_PEAK_T
+        flop_source = "PMC counters (profiles/k_simulate_multi_f32_valu.json)"
+    else:
+        flops, issue_meas = flops_alg, None
+        mix_ceiling = flop_launch / issue_launch * ISSUE_PEAK_T
+        flop_source = "static assembly count (counters not taken for these sources)"
     per_country = {}
     for c, s in enumerate(countries):
         last = [k for k in keep if k[0] == c][-1]
@@ -859,20 +873,26 @@ def main():
             "unit": "TFLOP/s",
             "frac": flops / FP32_PEAK_TFLOPS,
             "traffic": traffic,
-            "flop_per_sample_day": FP32_FLOP_PER_SAMPLE_DAY,
-            "flop_per_sample": FP32_FLOP_PER_SAMPLE,
+            "achieved_source": flop_source,
             "sample_days_per_launch": days_per_launch,
             "samples_per_launch": samples_per_launch,
             "launch_ms": avg_ms,
-            # the same work in VALU issue: the kernel is bound by instruction
-            # issue, and FP32 arithmetic is a fraction of its instruction mix
+            # the kernel is bound by VALU issue; FP32 arithmetic is a
+            # fraction of its instruction mix (Philox integer work, conversions)
             "mix_ceiling_tflops": mix_ceiling,
             "mix_ceiling_frac": mix_ceiling / FP32_PEAK_TFLOPS,
             "frac_of_mix_ceiling": flops / mix_ceiling,
-            "issue": {"unit": "T lane quad-cycles/s", "achieved": issue, "peak": ISSUE_PEAK_T,
-                      "frac": issue / ISSUE_PEAK_T,
+            "issue": {"unit": "T lane quad-cycles/s", "peak": ISSUE_PEAK_T,
+                      "measured": issue_meas,
+                      "busy_frac": issue_meas / ISSUE_PEAK_T if issue_meas else None,
+                      "algorithmic": issue_alg,
+                      "algorithmic_frac": issue_alg / ISSUE_PEAK_T,
+                      "algorithmic_share_of_issued": issue_alg / issue_meas if issue_meas else None,
                       "qc_per_sample_day": ISSUE_QC_PER_SAMPLE_DAY,
                       "qc_per_sample": ISSUE_QC_PER_SAMPLE},
+            "algorithmic_fp32": {"achieved": flops_alg, "frac": flops_alg / FP32_PEAK_TFLOPS,
+                                 "flop_per_sample_day": FP32_FLOP_PER_SAMPLE_DAY,
+                                 "flop_per_sample": FP32_FLOP_PER_SAMPLE},
             "valu_counters": valu_pmc,
         },
         "per_country": per_country,
