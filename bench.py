@@ -35,16 +35,18 @@ METRIC = "accepted ABC samples/s at fixed ε (sim-days/s, VALU %); plain vs lear
 # words; 13 register moves not counted).
 FP32_FLOP_PER_SAMPLE_DAY = 73     # FMA 2, add / multiply / transcendental 1
 FP32_FLOP_PER_SAMPLE = 25
-# VALU issue cost in quad-cycles (one wave64 instruction on a 16-lane SIMD):
-# a transcendental takes 2, every other instruction here 1 (measured on
-# MI355X with a probe of independent chains: v_log/v_exp/v_sqrt/v_rcp/v_sin
-# 2.0, v_fma_f32 1.0, v_mad_u64_u32 + v_xor 2.0, no co-issue of an FMA with
-# a transcendental).
-ISSUE_QC_PER_SAMPLE_DAY = 158 + 22
-ISSUE_QC_PER_SAMPLE = 120
+# VALU issue in instruction slots: a SIMD issues one wave64 VALU instruction
+# per quad-cycle. A transcendental occupies its wave for 2 quad-cycles (a
+# single-wave probe: v_log/v_exp/v_sqrt/v_rcp/v_sin 2.0, v_fma_f32 and
+# v_mad_u64_u32 1.0), but with several waves per SIMD other waves issue
+# beside it (SQ_ACTIVE_INST_VALU, which counts it twice, exceeds the SIMD's
+# quad-cycles at eight waves per SIMD), so the issue model counts every
+# instruction once and the transcendental unit as a resource of its own.
+ISSUE_PER_SAMPLE_DAY = 158
+ISSUE_PER_SAMPLE = 120
 # The batched round kernel's day step has no bound lookup either.
-BATCH_ISSUE_QC_PER_SAMPLE_DAY = ISSUE_QC_PER_SAMPLE_DAY
-# Issue peak in lane quad-cycles/s: 256 CUs x 4 SIMDs x 64 lanes x 2.4e9 / 4.
+BATCH_ISSUE_PER_SAMPLE_DAY = ISSUE_PER_SAMPLE_DAY
+# Issue peak in lane-instructions/s: 256 CUs x 4 SIMDs x 64 lanes x 2.4e9 / 4.
 ISSUE_PEAK_T = 256 * 4 * 64 * 2.4e9 / 4 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 SIM_SOURCES = ["paper_2012_14332_amd/csrc/simulate.hip", "paper_2012_14332_amd/csrc/multi.hip",
@@ -233,11 +235,11 @@ def batched_leg(args):
         "rounds": st["rounds"],
         "graph_replays": st["graph_replays"],
         "rounds_ms": st["rounds_ms"],
-        # algorithmic VALU issue (lane quad-cycles) of the round kernels over the
+        # algorithmic VALU issue (lane-instructions) of the round kernels over the
         # replays' wall time (host waits between replays included, so a lower
         # bound on the kernel's own fraction)
-        "issue_frac_rounds_lower_bound": (BATCH_ISSUE_QC_PER_SAMPLE_DAY * st["sample_days"] +
-                                          ISSUE_QC_PER_SAMPLE * used) /
+        "issue_frac_rounds_lower_bound": (BATCH_ISSUE_PER_SAMPLE_DAY * st["sample_days"] +
+                                          ISSUE_PER_SAMPLE * used) /
                                          (st["rounds_ms"] * 1e-3) / (ISSUE_PEAK_T * 1e12),
         "refill_min": tune.get("refill"),
         "rechecked_fp64": st["rechecked"],
@@ -666,9 +668,12 @@ def main():
     if args.launch:
         abc.set_launch_config(*[int(x) for x in args.launch.split(",")])
     elif not args.per_series_launches:
-        # the three countries' observed rows and bound tables fill most of a
-        # workgroup's LDS: one 1024-thread workgroup per CU
-        abc.set_launch_config(1, 1024, 1)
+        # two 1024-thread workgroups per CU (eight wavefronts per SIMD at the
+        # kernel's 57 VGPRs); each gets half the LDS, so the bound tables are
+        # coarser in time than at one workgroup per CU, but the step is
+        # fastest here (same-box sweep of (spl, block, workgroups/CU): ms per
+        # step 1.73 at (1, 1024, 2), 1.78 at (1, 512, 2), 1.99 at (1, 1024, 1))
+        abc.set_launch_config(1, 1024, 2)
     if args.refill_min:
         abc.set_refill_min(args.refill_min)
     if args.copy_calibration_mib:
@@ -713,9 +718,13 @@ def main():
             sC.wait_event(compacted[(par, c)])
             abc.recheck_band(r.ser, r.seed, r.eps, r.band_w, idx, th, d, cnt, series=c)
             mean, cov = abc.posterior_moments(th, n_dev=cnt)
-        # kept for the accepted counts and the last-step check; the binding
-        # marks every tensor it hands to stream C as in use there
-        keep.append((c, idx, th, cnt, mean, cov, d))
+        # each step's accepted count, and the latest rows for the last-step
+        # check; earlier outputs are released (the binding marks every tensor
+        # it hands to a stream as in use there, so the caching allocator
+        # reuses a block only after that stream's work on it), which keeps a
+        # steady-state step free of device allocations
+        keep["cnt"].append((c, cnt))
+        keep["last"][c] = (idx, cnt, mean)
 
     def step(s, keep, ev):
         first = first0 + s * N
@@ -757,16 +766,16 @@ def main():
 
     def timed_region(s0, ev):
         """K steps from step s0, bracketed by device synchronisation."""
-        keep = []
+        keep = {"cnt": [], "last": {}}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(s0, s0 + args.steps):
             step(s, keep, ev)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, sum(int(k[3].item()) for k in keep), keep
+        return wall, sum(int(k[1].item()) for k in keep["cnt"]), keep
 
-    keep = []
+    keep = {"cnt": [], "last": {}}
     for s in range(args.warmup):
         step(s, keep, None)
     torch.cuda.synchronize()
@@ -786,10 +795,10 @@ def main():
     last_first = first0 + (args.warmup + args.steps - 1) * N
     same_rows = True
     for c, r in enumerate(runs):
-        k = [k for k in keep if k[0] == c][-1]
+        idx_c, cnt_c, _ = keep["last"][c]
         ref = r.run(last_first)
-        n_ref, n_got = int(ref.count.item()), int(k[3].item())
-        same_rows &= n_ref == n_got and torch.equal(ref.idx[:n_ref], k[1][:n_got])
+        n_ref, n_got = int(ref.count.item()), int(cnt_c.item())
+        same_rows &= n_ref == n_got and torch.equal(ref.idx[:n_ref], idx_c[:n_got])
     torch.cuda.synchronize()
     sim_ms = [a.elapsed_time(b) for a, b, _ in ev]
     eff_days = int(days.item())
@@ -800,24 +809,27 @@ def main():
     days_per_launch = eff_days / launches
     samples_per_launch = N * len(countries) // (launches // args.steps)
     # One launch over its average duration (HIP events on the launch stream).
-    # Algorithmic work from the assembly count (FP32 FLOP, VALU issue in lane
-    # quad-cycles with transcendentals at their measured 2); measured work
-    # from the committed PMC summary of the same kernel and workload (FP32
-    # FLOP = 64 (add + mul + trans + 2 fma), issued quad-cycles =
-    # SQ_ACTIVE_INST_VALU), scaled per sample-day to this launch.
+    # Algorithmic work from the assembly count (FP32 FLOP, VALU instructions);
+    # measured work from the committed PMC summary of the same kernel, workload
+    # and launch shape (FP32 FLOP = 64 (add + mul + trans + 2 fma), issued
+    # lane-instructions = 64 SQ_INSTS_VALU), scaled per sample-day to this
+    # launch.
     flop_launch = FP32_FLOP_PER_SAMPLE_DAY * days_per_launch + FP32_FLOP_PER_SAMPLE * samples_per_launch
-    issue_launch = ISSUE_QC_PER_SAMPLE_DAY * days_per_launch + ISSUE_QC_PER_SAMPLE * samples_per_launch
+    issue_launch = ISSUE_PER_SAMPLE_DAY * days_per_launch + ISSUE_PER_SAMPLE * samples_per_launch
     flops_alg = flop_launch / (avg_ms * 1e-3) / 1e12
     issue_alg = issue_launch / (avg_ms * 1e-3) / 1e12
+    shape = list(abc.get_launch_config())
     valu_pmc = valu_counters() if not args.per_series_launches else None
+    if valu_pmc and valu_pmc.get("launch_config") != shape:
+        valu_pmc = None  # taken at another launch shape
     traffic = traffic_per_launch() if not args.per_series_launches else None
     if valu_pmc:
         flop_meas = valu_pmc["fp32_flop_per_sample_day"] * days_per_launch
-        qc_meas = valu_pmc["valu_lane_qc_per_sample_day"] * days_per_launch
+        qc_meas = valu_pmc["valu_lane_inst_per_sample_day"] * days_per_launch
         flops = flop_meas / (avg_ms * 1e-3) / 1e12
         issue_meas = qc_meas / (avg_ms * 1e-3) / 1e12
         # the FP32 FLOP rate this instruction mix reaches with every VALU
-        # issue slot busy
+        # issue slot of the device busy
         mix_ceiling = flop_meas / qc_meas * ISSUE_PEAK_T
         flop_source = "PMC counters (profiles/k_simulate_multi_f32_valu.json)"
     else:
@@ -826,11 +838,10 @@ def main():
         flop_source = "static assembly count (counters not taken for these sources)"
     per_country = {}
     for c, s in enumerate(countries):
-        last = [k for k in keep if k[0] == c][-1]
-        n_c = sum(int(k[3].item()) for k in keep if k[0] == c)
+        n_c = sum(int(k[1].item()) for k in keep["cnt"] if k[0] == c)
         per_country[s.name] = {"eps": eps[c], "accepted": n_c,
                                "posterior_mean_last_step": [round(float(x), 5) for x in
-                                                            last[4].cpu().numpy()]}
+                                                            keep["last"][c][2].cpu().numpy()]}
     out = {
         "metric": METRIC,
         "value": accepted / wall,
@@ -882,14 +893,15 @@ def main():
             "mix_ceiling_tflops": mix_ceiling,
             "mix_ceiling_frac": mix_ceiling / FP32_PEAK_TFLOPS,
             "frac_of_mix_ceiling": flops / mix_ceiling,
-            "issue": {"unit": "T lane quad-cycles/s", "peak": ISSUE_PEAK_T,
+            "issue": {"unit": "T lane-instructions/s", "peak": ISSUE_PEAK_T,
                       "measured": issue_meas,
                       "busy_frac": issue_meas / ISSUE_PEAK_T if issue_meas else None,
                       "algorithmic": issue_alg,
                       "algorithmic_frac": issue_alg / ISSUE_PEAK_T,
                       "algorithmic_share_of_issued": issue_alg / issue_meas if issue_meas else None,
-                      "qc_per_sample_day": ISSUE_QC_PER_SAMPLE_DAY,
-                      "qc_per_sample": ISSUE_QC_PER_SAMPLE},
+                      "trans_unit_busy_frac": valu_pmc.get("trans_unit_busy_frac") if valu_pmc else None,
+                      "inst_per_sample_day": ISSUE_PER_SAMPLE_DAY,
+                      "inst_per_sample": ISSUE_PER_SAMPLE},
             "algorithmic_fp32": {"achieved": flops_alg, "frac": flops_alg / FP32_PEAK_TFLOPS,
                                  "flop_per_sample_day": FP32_FLOP_PER_SAMPLE_DAY,
                                  "flop_per_sample": FP32_FLOP_PER_SAMPLE},

@@ -237,11 +237,11 @@ struct BLane {
     RatesF r;
     PhiloxDays ph;
     int64_t i;
-    int32_t t, T, obs_off, series;
+    int32_t t;  // the day the slot simulates next; 0: no sample (idle)
+    int32_t T, obs_off, series;
     float invP, exit2;
     uint32_t b1;
     float acc;
-    bool active;
 };
 
 template <int SPL, bool MIX>
@@ -271,7 +271,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
     if (C == 0) return;
 
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    // the wavefront index is uniform over the wave: kept scalar, so is the
+    // queue arithmetic derived from it
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     BSlot* ring = ring_all + wv * BT_RING;
     const int64_t wg = (int64_t)blockIdx.x * nwaves_blk + wv;
     const int64_t nw = (int64_t)gridDim.x * nwaves_blk;
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
     int64_t filled_j = -1;   // chunk currently in the ring
     BLane L[SPL];
 #pragma unroll
-    for (int k = 0; k < SPL; ++k) L[k].active = false;
+    for (int k = 0; k < SPL; ++k) L[k].t = 0;
     uint32_t days_done = 0;
 
     while (true) {
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
         // start of the next
 #pragma unroll
         for (int k = 0; k < SPL; ++k) {
-            uint64_t m = __ballot(!L[k].active);
+            uint64_t m = __ballot(L[k].t == 0);
             if (__popcll(m) < a.refill_min) continue;  // let a few more lanes finish first
             while (m != 0ull && q_base < Q) {
                 const int64_t j = q_base >> 6;
@@ -337,7 +339,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                 }
                 const int avail = 64 - (int)(q_base & 63);
                 const bool inm = (m >> lane) & 1ull;
-                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                // lanes of m below this one
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 const bool take = inm && rank < avail;
                 if (take) {
                     const BSlot sl = ring[(q_base & 63) + rank];
@@ -358,7 +362,6 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                         l.exit2 = d.exit2;
                         l.b1 = d.b1;
                         l.acc = 0.0f;
-                        l.active = true;
                     }
                 }
                 const int cnt = __popcll(m);
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
         }
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < SPL; ++k) any |= L[k].active;
+        for (int k = 0; k < SPL; ++k) any |= L[k].t != 0;
         // a refill can land every idle lane on the unused tail of a series'
         // last chunk; the wave ends only when the queue is exhausted too
         if (__ballot(any) == 0ull && q_base >= Q) break;
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
 #pragma unroll
         for (int k = 0; k < SPL; ++k) {
             BLane& l = L[k];
-            if (!l.active) continue;
+            if (l.t == 0) continue;
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | (a.domain << 4), l.b1, a.key);
             Noise32 z;
@@ -404,7 +407,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                         if (dd <= ds.eps_lo) atomicAdd(&a.state[l.series].certain, 1);
                     }
                 }
-                l.active = false;
+                l.t = 0;
             } else {
                 l.t = t + 1;
             }

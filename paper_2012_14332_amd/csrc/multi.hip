@@ -82,12 +82,14 @@ struct MLane {
     RatesF r;
     PhiloxDays ph;
     int64_t k;
-    int32_t t;
+    int32_t t;  // the day the lane simulates next; 0: no sample (idle)
     float acc, comp;
-    bool active;
     int32_t ls;
-    // the lane's series, cached at the start of each sample
-    int32_t T, obs_off, tab_r, tab_d, lb_sh;
+    // the lane's series, cached at the start of each sample (tr, td: its
+    // bound tables for R and D, tr null without one)
+    int32_t T, obs_off, lb_sh;
+    const float* tr;
+    const float* td;
     float invP, exitb;
     uint32_t b1;
 };
@@ -148,7 +150,9 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
 
     __builtin_amdgcn_s_setprio(1);
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    // the wavefront index is uniform over the wave: kept scalar, so is
+    // everything of the queue derived from it
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     MSlot* ring = ring_all + wv * RING;
     const int64_t wg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -196,14 +200,14 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
     uint32_t qb = 0;
     uint32_t filled = 0xFFFFFFFFu;
     MLane l;
-    l.active = false;
+    l.t = 0;
     uint32_t days_done = 0;
 
     while (true) {
         // refill: the idle lanes take the next queue positions in lane order,
         // once at least refill_min of them are idle; a pass may span the end
         // of one chunk and the start of the next
-        bool want = !l.active;
+        bool want = l.t == 0;
         uint64_t m = __ballot(want);
         if (__popcll(m) >= a.refill_min) {
             while (m != 0ull && qb < Q) {
@@ -229,12 +233,13 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
                     l.ph.c1base = sl.c1base; l.ph.g3 = sl.g3; l.ph.h3 = sl.h3; l.ph.f3 = sl.f3;
                     l.k = cur_base + (int64_t)pos;
                     l.ls = cur_ls;
-                    l.T = e.T; l.obs_off = e.obs_off; l.tab_r = e.tab_r; l.tab_d = e.tab_d;
+                    l.T = e.T; l.obs_off = e.obs_off;
+                    l.tr = e.tab_r >= 0 ? tabs + e.tab_r : nullptr;
+                    l.td = tabs + e.tab_d;
                     l.lb_sh = e.lb_sh; l.invP = e.invP; l.exitb = e.exitb; l.b1 = e.b1;
                     l.t = 1;
                     l.acc = 0.0f;
                     l.comp = 0.0f;
-                    l.active = true;
                 }
                 want = want && !take;
                 const uint32_t cnt = (uint32_t)__popcll(m);
@@ -242,8 +247,8 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
                 m = __ballot(want);
             }
         }
-        if (__ballot(l.active) == 0ull && qb >= Q) break;
-        if (l.active) {
+        if (__ballot(l.t != 0) == 0ull && qb >= Q) break;
+        if (l.t != 0) {
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | wdom, l.b1, a.key);
             Noise32 z;
@@ -271,17 +276,17 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
                 }
             }
             float lb = 0.0f;
-            if (DIST == 0 && l.tab_r >= 0) {
+            if (DIST == 0 && l.tr != nullptr) {
                 const int row = (t >> l.lb_sh) * LB_Q;
                 const int qr = (int)fmaf(lx[1], 2.0f, -0x1p-12f);
                 const int qd = (int)fmaf(lx[2], 2.0f, -0x1p-12f);
-                lb = tabs[l.tab_r + row + qr] + tabs[l.tab_d + row + qd];
+                lb = l.tr[row + qr] + l.td[row + qd];
             }
             const bool exited = l.acc + lb > l.exitb;
             if (exited || t == l.T) {
                 const float dd = exited ? INFINITY : finish_distance_f32(l.acc, dscale);
                 ser[l.ls].dist[l.k] = dd;
-                l.active = false;
+                l.t = 0;
                 days_done += (uint32_t)t;
             } else {
                 l.t = t + 1;

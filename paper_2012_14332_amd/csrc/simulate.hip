@@ -113,9 +113,8 @@ struct Lane {
     RatesF r;
     PhiloxDays ph;
     int64_t k;     // sample offset within the launch
-    int32_t t;     // next day to simulate
+    int32_t t;     // next day to simulate; 0: no sample (idle)
     float acc, comp;
-    bool active;
 };
 
 template <int NOISE, int DIST, bool KAHAN, bool PRIOR, int SPL>
@@ -154,7 +153,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     // the waves whose static share of the launch it would delay).
     __builtin_amdgcn_s_setprio(1);
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    // the wavefront index is uniform over the wave: kept scalar, so is the
+    // queue arithmetic derived from it
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Slot* ring = ring_all + wv * RING;
     const int64_t wg = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
     uint32_t filled = 0xFFFFFFFFu; // chunk currently in the ring
     Lane L[SPL];
 #pragma unroll
-    for (int j = 0; j < SPL; ++j) L[j].active = false;
+    for (int j = 0; j < SPL; ++j) L[j].t = 0;
     uint32_t days_done = 0;
 
     while (true) {
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
         // may span the end of one chunk and the start of the next
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
-            uint64_t m = __ballot(!L[j].active);
+            uint64_t m = __ballot(L[j].t == 0);
             if (__popcll(m) < a.refill_min) continue;  // let a few more lanes finish first
             while (m != 0ull && qb < Q) {
                 const uint32_t jc = qb >> 6;
@@ -203,7 +204,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
                 }
                 const uint32_t avail = 64u - (qb & 63u);
                 const bool inm = (m >> lane) & 1ull;
-                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                // lanes of m below this one
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 const bool take = inm && rank < avail;
                 if (take) {
                     const Slot sl = ring[(qb & 63u) + rank];
@@ -221,7 +224,6 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
                         l.t = 1;
                         l.acc = 0.0f;
                         l.comp = 0.0f;
-                        l.active = true;
                     }
                 }
                 const uint32_t cnt = (uint32_t)__popcll(m);
@@ -231,14 +233,14 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
         }
         bool any = false;
 #pragma unroll
-        for (int j = 0; j < SPL; ++j) any |= L[j].active;
+        for (int j = 0; j < SPL; ++j) any |= L[j].t != 0;
         if (__ballot(any) == 0ull && qb >= Q) break;
 
         // one day of every active slot
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
             Lane& l = L[j];
-            if (!l.active) continue;
+            if (l.t == 0) continue;
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | wdom, ps.b1, a.key);
             Noise32 z;
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_simulate_f32(SimArgs a)
                 const float dd = exited ? INFINITY : finish_distance_f32(l.acc, dscale);
                 a.dist[l.k] = dd;
                 if (a.dist64) a.dist64[l.k] = (double)dd;
-                l.active = false;
+                l.t = 0;
                 days_done += (uint32_t)t;
             } else {
                 l.t = t + 1;
