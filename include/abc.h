@@ -654,8 +654,9 @@ ABC_API abc_status abc_smc_run(const abc_series* ser, const abc_model* model,
                                void* stream);
 
 /* Library scratch. Calls that need device scratch (compaction tiles, moment
- * partials, band flags, selection histograms, SMC work space) take it from a
- * library-owned buffer kept per (device, stream): the first calls on a stream
+ * partials, band flags, selection histograms, SMC work space, the batched
+ * quota run's buffers) or a small pinned host buffer take it from
+ * library-owned buffers kept per (device, stream): the first calls on a stream
  * allocate it (growing it synchronises that stream once), later calls reuse it
  * without allocating, so a steady-state call never waits for the device.
  * Calls on one stream are ordered and may share it; calls on one stream from

@@ -605,11 +605,6 @@ using namespace abc;
 
 namespace {
 
-struct DevBuf {
-    void* p = nullptr;
-    ~DevBuf() { if (p) (void)hipFree(p); }
-};
-
 template <int SPL>
 void launch_round(const BatchArgs& a, unsigned grid, int block, size_t lds, hipStream_t s)
 {
@@ -722,25 +717,38 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     int npow_cap = 1;
     while (npow_cap < cand_cap) npow_cap <<= 1;
 
-    // device buffers (freed on return)
-    DevBuf b_desc, b_state, b_table, b_obs, b_ptrs, b_cidx, b_cdist, b_flag, b_days, b_mixtab, b_order;
-    ABC_HIP(hipMalloc(&b_desc.p, sizeof(SeriesDesc) * m));
-    ABC_HIP(hipMalloc(&b_state.p, sizeof(SeriesState) * m));
-    ABC_HIP(hipMalloc(&b_table.p, sizeof(RoundTable)));
-    ABC_HIP(hipMalloc(&b_obs.p, sizeof(float) * (size_t)obs_words));
-    ABC_HIP(hipMalloc(&b_ptrs.p, sizeof(const int32_t*) * m));
-    ABC_HIP(hipMalloc(&b_cidx.p, sizeof(int64_t) * (size_t)m * cand_cap));
-    ABC_HIP(hipMalloc(&b_cdist.p, sizeof(float) * (size_t)m * cand_cap));
-    ABC_HIP(hipMalloc(&b_flag.p, sizeof(int32_t)));
-    ABC_HIP(hipMalloc(&b_days.p, sizeof(unsigned long long)));
-    int32_t* flag_host = nullptr;
-    ABC_HIP(hipHostMalloc((void**)&flag_host, sizeof(int32_t), hipHostMallocDefault));
-    struct HostFree {
-        int32_t* p;
-        ~HostFree() { if (p) (void)hipHostFree(p); }
-    } host_free{flag_host};
-
+    // Device buffers from the library's scratch arena on the caller's stream
+    // (the call's own stream below starts after the caller's earlier work and
+    // the caller's stream waits for it before the call returns, so the next
+    // call on that stream reuses them safely); the completion flag lives in
+    // the arena's pinned host buffer of the same stream.
     hipStream_t user = as_stream(stream);
+    struct Carve {
+        size_t off = 0;
+        size_t take(size_t bytes) { const size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; }
+    } carve;
+    const size_t o_desc = carve.take(sizeof(SeriesDesc) * m);
+    const size_t o_state = carve.take(sizeof(SeriesState) * m);
+    const size_t o_table = carve.take(sizeof(RoundTable));
+    const size_t o_obs = carve.take(sizeof(float) * (size_t)obs_words);
+    const size_t o_ptrs = carve.take(sizeof(const int32_t*) * m);
+    const size_t o_cidx = carve.take(sizeof(int64_t) * (size_t)m * cand_cap);
+    const size_t o_cdist = carve.take(sizeof(float) * (size_t)m * cand_cap);
+    const size_t o_flag = carve.take(sizeof(int32_t));
+    const size_t o_days = carve.take(sizeof(unsigned long long));
+    const size_t o_order = carve.take(sizeof(int32_t) * m);
+    const size_t o_mixtab = carve.take(prop ? sizeof(MixTable) * m : 0);
+    const size_t o_re = carve.take(sizeof(int32_t) * m);
+    void* arena = nullptr;
+    if ((rc = stream_scratch(user, carve.off, &arena, SCRATCH_BATCH))) return rc;
+    char* base = static_cast<char*>(arena);
+    struct View { void* p; } b_desc{base + o_desc}, b_state{base + o_state}, b_table{base + o_table},
+        b_obs{base + o_obs}, b_ptrs{base + o_ptrs}, b_cidx{base + o_cidx}, b_cdist{base + o_cdist},
+        b_flag{base + o_flag}, b_days{base + o_days}, b_order{base + o_order}, b_mixtab{base + o_mixtab},
+        b_re{base + o_re};
+    int32_t* flag_host = nullptr;
+    if ((rc = stream_pinned(user, sizeof(int32_t), reinterpret_cast<void**>(&flag_host)))) return rc;
+
     hipStream_t s;
     ABC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     struct StreamFree {
@@ -761,7 +769,6 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     std::vector<int32_t> order(m);
     for (int q = 0; q < m; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return series[x].T > series[y].T; });
-    ABC_HIP(hipMalloc(&b_order.p, sizeof(int32_t) * m));
     ABC_HIP(hipMemcpyAsync(b_order.p, order.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
     ABC_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope with this call
 
@@ -794,7 +801,6 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         a.prop.lambda = prop->lambda;
         a.prop.log_inflate = logf(prop->inflate);
         a.prop_domain = prop->domain;
-        ABC_HIP(hipMalloc(&b_mixtab.p, sizeof(MixTable) * m));
         a.tables = reinterpret_cast<const MixTable*>(b_mixtab.p);
         hipLaunchKernelGGL(k_batch_tables, dim3(m), dim3(MIX_K * MIX_D), 0, s, a.mix, a.prop,
                            reinterpret_cast<MixTable*>(b_mixtab.p));
@@ -869,8 +875,6 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     f.out_dist = out_dist;
     f.out_count = out_count;
     f.out_used = out_used;
-    DevBuf b_re;
-    ABC_HIP(hipMalloc(&b_re.p, sizeof(int32_t) * m));
     f.out_rechecked = reinterpret_cast<int32_t*>(b_re.p);
     const int npow = npow_cap;
     const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + sizeof(double) * 3 * maxT + 16;

@@ -95,7 +95,11 @@ abc_status device_info(DeviceInfo* out);
 constexpr int SCRATCH_LEAF = 0;
 constexpr int SCRATCH_SMC_WS = 1;
 constexpr int SCRATCH_SMC_SUMS = 2;
+constexpr int SCRATCH_BATCH = 3;  // the batched quota run's buffers (its work runs on a stream of its own, ordered after and before s)
 abc_status stream_scratch(hipStream_t s, size_t bytes, void** out, int slot = SCRATCH_LEAF);
+// The same for pinned host memory (one buffer per (device, stream)), for
+// small results a call reads back on the host.
+abc_status stream_pinned(hipStream_t s, size_t bytes, void** out);
 
 // Prior box -> (lo, width) with width = fl32(hi - lo), as the draw uses it.
 inline abc_status prior_lo_width(const abc_prior* prior, float lo[8], float width[8])

@@ -91,6 +91,35 @@ abc_status stream_scratch(hipStream_t s, size_t bytes, void** out, int slot)
     return ABC_OK;
 }
 
+static std::map<ScratchKey, ScratchBuf> g_pinned;
+
+abc_status stream_pinned(hipStream_t s, size_t bytes, void** out)
+{
+    int dev = 0;
+    ABC_HIP(hipGetDevice(&dev));
+    if (bytes == 0) bytes = 64;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchBuf& b = g_pinned[ScratchKey{dev, s, 0}];
+    if (b.bytes < bytes) {
+        size_t want = 4096;
+        while (want < bytes) want <<= 1;
+        if (b.p) {
+            ABC_HIP(hipStreamSynchronize(s));
+            ABC_HIP(hipHostFree(b.p));
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        const hipError_t e = hipHostMalloc(&b.p, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            return set_error(ABC_ENOMEM, "pinned scratch of %zu B: %s", want, hipGetErrorString(e));
+        }
+        b.bytes = want;
+    }
+    *out = b.p;
+    return ABC_OK;
+}
+
 }  // namespace abc
 
 extern "C" abc_status abc_release_scratch(void)
@@ -103,6 +132,14 @@ extern "C" abc_status abc_release_scratch(void)
         if (it->first.dev == dev) {
             if (it->second.p) ABC_HIP(hipFree(it->second.p));
             it = abc::g_scratch.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = abc::g_pinned.begin(); it != abc::g_pinned.end();) {
+        if (it->first.dev == dev) {
+            if (it->second.p) ABC_HIP(hipHostFree(it->second.p));
+            it = abc::g_pinned.erase(it);
         } else {
             ++it;
         }
