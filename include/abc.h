@@ -325,12 +325,12 @@ typedef struct {
 } abc_batch_series;
 
 typedef struct {
-    int64_t rounds;        /* rounds run (graph replays x rounds_per_graph) */
-    int64_t graph_replays;
+    int64_t rounds;        /* rounds run */
+    int64_t graph_replays; /* completion flags the host read */
     int64_t sample_days;   /* sample-days simulated (after early exits) */
     int64_t rechecked;     /* candidates decided in float64 */
     int32_t grid, block, spl, lds_bytes;
-    float rounds_ms;       /* wall time of the graph replays (host waits included) */
+    float rounds_ms;       /* wall time of the rounds (host waits included) */
 } abc_batch_stats;
 
 /*
@@ -340,9 +340,12 @@ typedef struct {
  * `quota` accepted samples. Each round hands round_size samples, split evenly,
  * to the series still below quota; series j consumes its stream indices
  * 0, 1, 2, ... as a prefix (theta drawn from `prior` on stream (seed, domain,
- * series[j].series)). The rounds are captured once as a hipGraph
- * (rounds_per_graph rounds per replay) and replayed; the host checks a
- * completion flag after each replay. At the end the candidates inside the
+ * series[j].series)). Each round is planned on the device from the counts of
+ * the rounds up to two before it, so consecutive rounds overlap (they
+ * alternate between two streams of the call); a completion flag follows
+ * every round and the host reads the flag of the round rounds_per_graph
+ * (clamped to [2, 6]) rounds back. Which samples are simulated, and so every
+ * output, does not depend on that setting. At the end the candidates inside the
  * band (eps (1 - band_w), eps (1 + band_w)] are decided in float64, and the
  * first `quota` accepted samples by index are written per series:
  *   out_idx   device int64 [m][quota]        out_theta device float32 [m][quota][8]
@@ -351,15 +354,15 @@ typedef struct {
  *   out_mean  device float64 [m][8]          out_cov   device float64 [m][8][8]
  * The result equals the first `quota` indices i with dist_i <= eps of the
  * plain path. Only the default model (flags = 0, any noise_scale) runs here.
- * m <= 256; quota <= 4096; the observed series of the batch must fit in LDS
- * (about 12 B per day of all series together plus the launch shape's ring),
- * otherwise ABC_EUNSUPPORTED asks to split the batch. max_samples bounds the
+ * m <= 256; quota <= 4096; the series descriptors (64 B each) and the launch
+ * shape's ring must fit in LDS (the observed series are read from device
+ * memory), otherwise ABC_EUNSUPPORTED. max_samples bounds the
  * samples per series; ABC_EOVERFLOW if some series then still lacks its quota
  * or produced more candidates (d <= eps (1 + band_w)) than cand_capacity rows
  * (0 = max(4 quota, 256), at most 16384, and the finalisation sorts them in LDS: about
  * 12 B per row must fit, so 8192 rows at most on gfx950); each round caps a series' share by its
- * candidate rate so far to stay within half the free capacity. Launch shape: abc_set_launch_config
- * (spl 1, 2 or 4). Blocks the calling host thread until done; the caller's
+ * candidate rate so far to keep the running round's and its own expected candidates within half
+ * the free capacity. Launch shape: abc_set_launch_config (spl 1, 2, 4 or 8). Blocks the calling host thread until done; the caller's
  * stream is ordered before and after the work. stats may be NULL.
  */
 ABC_API abc_status abc_batch_run(const abc_batch_series* series, int32_t m,

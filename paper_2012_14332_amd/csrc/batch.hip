@@ -1,12 +1,16 @@
 // Batched persistent rejection ABC over many observed series of uneven
 // length and population (Sec. 3.1 "iterate until the required number of
-// accepted samples"), run as hipGraph-captured rounds, and its C-ABI entry
+// accepted samples"), run as overlapping rounds on two streams, and its C-ABI entry
 // point abc_batch_run.
 //
-// Round structure (all on the device, captured once, replayed):
+// Round structure (all decisions on the device):
 //   k_batch_plan   one workgroup: series whose certain-accept count is below
 //                  the quota share the round's samples evenly; each gets the
-//                  next contiguous index range of its own stream.
+//                  next contiguous index range of its own stream. Plan p sees
+//                  the counts of rounds up to p - 2 only, so round p - 1 can
+//                  still run while it plans, and round p starts on the
+//                  workgroup slots round p - 1 frees at its end: the rounds
+//                  alternate between two streams and overlap their tails.
 //   k_batch_round  persistent grid: every wavefront walks a fixed share of
 //                  the round's 64-sample chunks with lane refill. Lanes carry
 //                  their own series (T, P, tolerance, stream words), and the
@@ -47,10 +51,18 @@ struct SeriesDesc {         // device, per series, constant over the run
     uint32_t pad;
 };
 
-struct SeriesState {        // device, per series, updated every round
-    int64_t next;           // next sample index of the stream
-    int32_t certain;        // accepts with d <= eps (1 - w) so far
-    int32_t cand;           // candidates with d <= eps (1 + w) so far (may exceed capacity)
+constexpr int BT_SLOTS = 3;  // round p counts into slot p % 3 until plan p + 2 folds it
+
+struct SeriesState {        // device, per series
+    int64_t next;           // next sample index of the stream (assigned to some round)
+    int64_t done;           // samples of the folded rounds
+    int32_t certain;        // accepts with d <= eps (1 - w) so far (every finished sample)
+    int32_t cand;           // candidate rows handed out so far (may exceed capacity)
+    int32_t certain_f;      // certain accepts of the folded rounds
+    int32_t cand_f;         // candidates of the folded rounds
+    int32_t rc_certain[BT_SLOTS];  // per-round counts, by slot
+    int32_t rc_cand[BT_SLOTS];
+    int64_t n_slot[BT_SLOTS];      // samples assigned to the round of each slot
 };
 
 struct RoundTable {
@@ -76,7 +88,8 @@ struct BatchArgs {
     float lo[8], width[8];
     const SeriesDesc* desc;
     SeriesState* state;
-    RoundTable* table;
+    RoundTable* table;      // this round's table (two, alternating with the round's parity)
+    int32_t round;          // round index p (its count slot is p % BT_SLOTS)
     const float* obs_table; // [obs_words]
     int64_t* cand_idx;      // [m][cand_cap]
     float* cand_dist;       // [m][cand_cap]
@@ -121,9 +134,8 @@ __global__ void k_batch_init(BatchArgs a)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < a.m) {
-        a.state[s].next = 0;
-        a.state[s].certain = 0;
-        a.state[s].cand = 0;
+        SeriesState z{};
+        a.state[s] = z;
     }
 }
 
@@ -151,11 +163,27 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
     const int tid = threadIdx.x;
     const int s = tid < a.m ? a.order[tid] : tid;
     const int lane = tid & 63, wave = tid >> 6;
+    const int p = a.round;
     bool active = false;
-    int64_t next = 0;
+    int64_t next = 0, done = 0, inflight = 0;
+    int32_t cand_f = 0;
     if (tid < a.m) {
-        next = a.state[s].next;
-        active = a.state[s].certain < a.quota && next < a.max_samples;
+        SeriesState& st = a.state[s];
+        if (p >= 2) {
+            // round p - 2 has finished (this plan runs after it): fold its counts
+            const int f = (p - 2) % BT_SLOTS;
+            st.certain_f += st.rc_certain[f];
+            st.cand_f += st.rc_cand[f];
+            st.done += st.n_slot[f];
+            st.rc_certain[f] = 0;
+            st.rc_cand[f] = 0;
+            st.n_slot[f] = 0;
+        }
+        next = st.next;
+        done = st.done;
+        cand_f = st.cand_f;
+        inflight = p >= 1 ? st.n_slot[(p - 1) % BT_SLOTS] : 0;  // round p - 1 may still run
+        active = st.certain_f < a.quota && next < a.max_samples;
     }
     const uint64_t bal = __ballot(active);
     const int rank_w = __popcll(bal & ((1ull << lane) - 1ull));
@@ -173,19 +201,22 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
         const int64_t rem = a.round_size % n_active;
         n_s = per + (rank < rem ? 1 : 0);
         if (n_s > a.max_samples - next) n_s = a.max_samples - next;
-        // keep the expected new candidates within half the free capacity,
-        // from the candidate rate seen so far (the schedule never changes
-        // which samples are accepted, only how many rounds it takes)
-        const int64_t cand = a.state[s].cand;
-        if (next > 0) {
-            const int64_t room = (int64_t)a.cand_cap - cand;
-            int64_t lim = room > 0 ? room * next / (2 * (cand + 1)) : 0;
+        // keep the expected candidates of the running round and this one
+        // together within half the free capacity, at the candidate rate of
+        // the finished rounds (the schedule never changes which samples are
+        // accepted, only how many rounds it takes)
+        if (done > 0) {
+            const double rate = ((double)cand_f + 1.0) / (double)done;
+            const double half = 0.5 * (double)((int64_t)a.cand_cap - cand_f) - rate * (double)inflight;
+            int64_t lim = half > 0.0 ? (int64_t)(half / rate) : 0;
             if (lim < 64) lim = 64;
             if (n_s > lim) n_s = lim;
-        } else if (n_s > (int64_t)a.cand_cap) {
-            // first round: no rate seen yet; at most the capacity, which no
-            // acceptance rate can overflow (one candidate per sample at most)
-            n_s = (int64_t)a.cand_cap;
+        } else {
+            // no finished round yet: every sample assigned so far may be a
+            // candidate, so the series' samples stay within the capacity,
+            // which no acceptance rate can overflow
+            const int64_t left = (int64_t)a.cand_cap - next;
+            if (n_s > left) n_s = left > 0 ? left : 0;
         }
     }
     const int chunks = (int)((n_s + 63) / 64);
@@ -212,6 +243,7 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
         t->chunk0[rank] = c0;
         a.state[s].next = next + n_s;
     }
+    if (tid < a.m) a.state[s].n_slot[p % BT_SLOTS] = n_s;
     if (tid == 0) {
         t->n_active = n_active;
         t->total_chunks = ctot;
@@ -251,10 +283,12 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
     __shared__ RoundTable tab_sh;  // copied once per workgroup
     const int nwaves_blk = blockDim.x >> 6;
     SeriesDesc* desc_sh = reinterpret_cast<SeriesDesc*>(lds_b);
-    float* obs_sh = reinterpret_cast<float*>(desc_sh + a.m);
-    BSlot* ring_all = reinterpret_cast<BSlot*>(obs_sh + ((a.obs_words + 3) & ~3));
+    // the observed rows stay in global memory (read through the caches): in
+    // LDS they would take 12 B per day of every series and leave room for
+    // one workgroup per CU
+    BSlot* ring_all = reinterpret_cast<BSlot*>(desc_sh + a.m);
 
-    // stage the round table, series descriptors and observed series
+    // stage the round table and the series descriptors
     {
         const int32_t* src = reinterpret_cast<const int32_t*>(a.table);
         int32_t* dst = reinterpret_cast<int32_t*>(&tab_sh);
@@ -263,7 +297,6 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
         int32_t* ddst = reinterpret_cast<int32_t*>(desc_sh);
         for (int q = threadIdx.x; q < a.m * (int)(sizeof(SeriesDesc) / 4); q += blockDim.x)
             ddst[q] = dsrc[q];
-        for (int q = threadIdx.x; q < a.obs_words; q += blockDim.x) obs_sh[q] = a.obs_table[q];
     }
     __syncthreads();
     const int C = tab_sh.total_chunks;
@@ -386,7 +419,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
             normals_f32(w, a.nc, z);
             day_step_f32<0>(l.s, l.r, l.invP, z);
             const int32_t X[3] = {l.s.A, l.s.R, l.s.D};
-            const float* ob = obs_sh + l.obs_off + t - 1;
+            const float* ob = a.obs_table + l.obs_off + t - 1;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float d = log2p1_count_f32(X[c]) - ob[c * l.T];
@@ -399,12 +432,17 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                     const float dd = finish_distance_f32(l.acc, 0.693147180559945309417f);
                     const SeriesDesc& ds = desc_sh[l.series];
                     if (dd <= ds.eps_hi) {
-                        const int pos = atomicAdd(&a.state[l.series].cand, 1);
+                        SeriesState& st = a.state[l.series];
+                        const int pos = atomicAdd(&st.cand, 1);
+                        atomicAdd(&st.rc_cand[a.round % BT_SLOTS], 1);
                         if (pos < a.cand_cap) {
                             a.cand_idx[(int64_t)l.series * a.cand_cap + pos] = l.i;
                             a.cand_dist[(int64_t)l.series * a.cand_cap + pos] = dd;
                         }
-                        if (dd <= ds.eps_lo) atomicAdd(&a.state[l.series].certain, 1);
+                        if (dd <= ds.eps_lo) {
+                            atomicAdd(&st.certain, 1);
+                            atomicAdd(&st.rc_certain[a.round % BT_SLOTS], 1);
+                        }
                     }
                 }
                 l.t = 0;
@@ -595,8 +633,8 @@ __global__ __launch_bounds__(256) void k_batch_moments(const float* theta, const
 
 static size_t batch_lds_bytes(int m, int obs_words, int block)
 {
-    return sizeof(SeriesDesc) * (size_t)m + sizeof(float) * (size_t)((obs_words + 3) & ~3) +
-           sizeof(BSlot) * BT_RING * (size_t)(block / 64);
+    (void)obs_words;  // the observed rows are read from global memory
+    return sizeof(SeriesDesc) * (size_t)m + sizeof(BSlot) * BT_RING * (size_t)(block / 64);
 }
 
 }  // namespace abc
@@ -729,12 +767,13 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     } carve;
     const size_t o_desc = carve.take(sizeof(SeriesDesc) * m);
     const size_t o_state = carve.take(sizeof(SeriesState) * m);
-    const size_t o_table = carve.take(sizeof(RoundTable));
+    constexpr int BT_EVR = 8;  // events and completion flags in a ring over the rounds
+    const size_t o_table = carve.take(2 * sizeof(RoundTable));
     const size_t o_obs = carve.take(sizeof(float) * (size_t)obs_words);
     const size_t o_ptrs = carve.take(sizeof(const int32_t*) * m);
     const size_t o_cidx = carve.take(sizeof(int64_t) * (size_t)m * cand_cap);
     const size_t o_cdist = carve.take(sizeof(float) * (size_t)m * cand_cap);
-    const size_t o_flag = carve.take(sizeof(int32_t));
+    const size_t o_flag = carve.take(sizeof(int32_t) * BT_EVR);
     const size_t o_days = carve.take(sizeof(unsigned long long));
     const size_t o_order = carve.take(sizeof(int32_t) * m);
     const size_t o_mixtab = carve.take(prop ? sizeof(MixTable) * m : 0);
@@ -747,7 +786,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         b_flag{base + o_flag}, b_days{base + o_days}, b_order{base + o_order}, b_mixtab{base + o_mixtab},
         b_re{base + o_re};
     int32_t* flag_host = nullptr;
-    if ((rc = stream_pinned(user, sizeof(int32_t), reinterpret_cast<void**>(&flag_host)))) return rc;
+    if ((rc = stream_pinned(user, sizeof(int32_t) * BT_EVR, reinterpret_cast<void**>(&flag_host)))) return rc;
 
     hipStream_t s;
     ABC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -814,38 +853,44 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     if ((rc = check_launch("k_batch setup"))) return rc;
     ABC_HIP(hipMemsetAsync(b_days.p, 0, sizeof(unsigned long long), s));
 
-    // capture rounds_per_graph rounds + the completion flag copy
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    ABC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int r = 0; r < rounds_per_graph; ++r) {
-        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(BT_MAX_SERIES), 0, s, a);
-        switch (spl) {
-        case 1: launch_round<1>(a, grid, block, lds, s); break;
-        case 2: launch_round<2>(a, grid, block, lds, s); break;
-        case 4: launch_round<4>(a, grid, block, lds, s); break;
-        case 8: launch_round<8>(a, grid, block, lds, s); break;
+    // Rounds alternate between two streams; plan p runs on s after plan
+    // p - 1 and after round p - 2, round p after plan p, so round p - 1 can
+    // still be finishing its last trajectories while round p starts. A
+    // completion flag (every series at quota or at max_samples, from the
+    // counts of all finished samples) follows each round; the host reads the
+    // flag of round p - L (L = rounds_per_graph, at least 2) after enqueueing
+    // round p. A flag that says done was computed after round q finished,
+    // possibly during round q + 1, so the counts were done by the end of
+    // round q + 1 and plans from q + 3 on assign no samples: the rounds up to
+    // q + 2 are all the result depends on, and with L >= 2 they have been
+    // enqueued by then.
+    hipStream_t rs[2] = {nullptr, nullptr};
+    struct RoundStreams {
+        hipStream_t* r;
+        ~RoundStreams() { for (int k = 0; k < 2; ++k) if (r[k]) (void)hipStreamDestroy(r[k]); }
+    } round_streams{rs};
+    for (int k = 0; k < 2; ++k) ABC_HIP(hipStreamCreateWithFlags(&rs[k], hipStreamNonBlocking));
+    hipEvent_t ev_plan[BT_EVR] = {}, ev_round[BT_EVR] = {};
+    struct RoundEvents {
+        hipEvent_t* a;
+        hipEvent_t* b;
+        ~RoundEvents() {
+            for (int k = 0; k < BT_EVR; ++k) {
+                if (a[k]) (void)hipEventDestroy(a[k]);
+                if (b[k]) (void)hipEventDestroy(b[k]);
+            }
         }
+    } round_events{ev_plan, ev_round};
+    for (int k = 0; k < BT_EVR; ++k) {
+        ABC_HIP(hipEventCreateWithFlags(&ev_plan[k], hipEventDisableTiming));
+        ABC_HIP(hipEventCreateWithFlags(&ev_round[k], hipEventDisableTiming));
     }
-    hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(BT_MAX_SERIES), 0, s, a);
-    (void)hipMemcpyAsync(flag_host, a.flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    hipError_t ce = hipStreamEndCapture(s, &graph);
-    if (ce != hipSuccess) return set_error(ABC_EHIP, "graph capture: %s", hipGetErrorString(ce));
-    struct GraphFree {
-        hipGraph_t g;
-        hipGraphExec_t e;
-        ~GraphFree() {
-            if (e) (void)hipGraphExecDestroy(e);
-            if (g) (void)hipGraphDestroy(g);
-        }
-    } graph_free{graph, nullptr};
-    ABC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    graph_free.e = exec;
-
-    const int64_t max_replays =
-        (max_samples * (int64_t)m + round_size - 1) / round_size / rounds_per_graph + 2;
-    int64_t replays = 0;
-    *flag_host = 0;
+    RoundTable* tables = reinterpret_cast<RoundTable*>(b_table.p);
+    int32_t* flags_dev = reinterpret_cast<int32_t*>(b_flag.p);
+    for (int k = 0; k < BT_EVR; ++k) flag_host[k] = 0;
+    const int L = rounds_per_graph < 2 ? 2 : (rounds_per_graph > BT_EVR - 2 ? BT_EVR - 2 : rounds_per_graph);
+    const int64_t max_rounds =
+        ((max_samples * (int64_t)m + round_size - 1) / round_size + 2) * 2 + 4;
     hipEvent_t t0, t1;
     ABC_HIP(hipEventCreate(&t0));
     ABC_HIP(hipEventCreate(&t1));
@@ -854,12 +899,40 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         ~TimerFree() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } timer_free{t0, t1};
     ABC_HIP(hipEventRecord(t0, s));
-    while (replays < max_replays) {
-        ABC_HIP(hipGraphLaunch(exec, s));
-        ABC_HIP(hipStreamSynchronize(s));
-        ++replays;
-        if (*flag_host) break;
+    int64_t rounds = 0, polls = 0, stop_at = -1;
+    while (rounds < max_rounds && (stop_at < 0 || rounds <= stop_at)) {
+        const int64_t p = rounds;
+        const int e = (int)(p % BT_EVR);
+        BatchArgs ap = a;
+        ap.table = tables + (p & 1);
+        ap.round = (int32_t)p;
+        ap.flag_dev = flags_dev + e;
+        if (p >= 2) ABC_HIP(hipStreamWaitEvent(s, ev_round[(p - 2) % BT_EVR], 0));
+        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(BT_MAX_SERIES), 0, s, ap);
+        ABC_HIP(hipEventRecord(ev_plan[e], s));
+        hipStream_t r = rs[p & 1];
+        ABC_HIP(hipStreamWaitEvent(r, ev_plan[e], 0));
+        switch (spl) {
+        case 1: launch_round<1>(ap, grid, block, lds, r); break;
+        case 2: launch_round<2>(ap, grid, block, lds, r); break;
+        case 4: launch_round<4>(ap, grid, block, lds, r); break;
+        case 8: launch_round<8>(ap, grid, block, lds, r); break;
+        }
+        hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(BT_MAX_SERIES), 0, r, ap);
+        ABC_HIP(hipMemcpyAsync(flag_host + e, ap.flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, r));
+        ABC_HIP(hipEventRecord(ev_round[e], r));
+        if ((rc = check_launch("k_batch round"))) return rc;
+        ++rounds;
+        if (p >= L && stop_at < 0) {
+            const int64_t q = p - L;
+            ABC_HIP(hipEventSynchronize(ev_round[q % BT_EVR]));
+            ++polls;
+            if (flag_host[q % BT_EVR]) stop_at = q + 2;
+        }
     }
+    // the last two rounds are on the two round streams
+    for (int64_t q = rounds - 2; q < rounds; ++q)
+        if (q >= 0) ABC_HIP(hipStreamWaitEvent(s, ev_round[q % BT_EVR], 0));
     ABC_HIP(hipEventRecord(t1, s));
     ABC_HIP(hipEventSynchronize(t1));
     float rounds_ms = 0.0f;
@@ -893,8 +966,8 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     ABC_HIP(hipEventRecord(ev, s));
     ABC_HIP(hipStreamWaitEvent(user, ev, 0));
     if (stats) {
-        stats->rounds = replays * rounds_per_graph;
-        stats->graph_replays = replays;
+        stats->rounds = rounds;
+        stats->graph_replays = polls;
         stats->sample_days = (int64_t)days;
         int64_t re = 0;
         for (int s2 = 0; s2 < m; ++s2) re += rech[s2];
@@ -913,9 +986,9 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
             return set_error(ABC_EOVERFLOW, "series %d: %lld of %d accepted within max_samples",
                              s2, (long long)cnt[s2], quota);
     }
-    if (!*flag_host)
-        return set_error(ABC_EOVERFLOW, "stopped after %lld graph replays before every quota was met",
-                         (long long)replays);
+    if (stop_at < 0 && (rounds == 0 || !flag_host[(rounds - 1) % BT_EVR]))
+        return set_error(ABC_EOVERFLOW, "stopped after %lld rounds before every quota was met",
+                         (long long)rounds);
     return ABC_OK;
 }
 
