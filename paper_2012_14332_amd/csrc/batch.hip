@@ -509,6 +509,93 @@ __device__ void bitonic_sort(int64_t* key, float* val, int n_pow2)
     }
 }
 
+// Float64 decision of the band rows (candidates with eps (1 - w) < d <=
+// eps (1 + w)): workgroup (s, g) of one wavefront scans block g of series s's
+// candidates and simulates its band rows in float64 side by side, up to
+// rows_max at a time (simulate_rows_f64_wave: each row's distance is the
+// double simulate_one_f64 gives). A decided row keeps its float64 distance
+// (as float); a rejected one gets idx INT64_MAX, which sorts it last.
+// Workgroups that meet no band row never stage the observed series.
+constexpr int BAND_GROUPS = 16;  // workgroups per series
+
+__global__ __launch_bounds__(64) void k_batch_band(FinalArgs f, int rows_max)
+{
+    extern __shared__ double lds_band[];
+    const BatchArgs& a = f.b;
+    const int s = blockIdx.x / BAND_GROUPS, g = blockIdx.x % BAND_GROUPS;
+    const SeriesDesc d = a.desc[s];
+    const int cand = a.state[s].cand;
+    const int n = cand < a.cand_cap ? cand : a.cand_cap;
+    const int per = (n + BAND_GROUPS - 1) / BAND_GROUPS;
+    const int q0 = g * per, q1 = q0 + per < n ? q0 + per : n;
+    if (q0 >= q1) return;
+    double* lobs = lds_band;
+    double* zs = lobs + 3 * d.T;
+    uint64_t* rix = reinterpret_cast<uint64_t*>(zs + (size_t)5 * ROW_WINDOW * rows_max);
+    int32_t* rq = reinterpret_cast<int32_t*>(rix + rows_max);
+    RowWalk* rw = reinterpret_cast<RowWalk*>(rq + 2 * rows_max);  // rq padded to 8 B per row
+    int32_t* xs = reinterpret_cast<int32_t*>(rw + rows_max);
+    float* rth = reinterpret_cast<float*>(xs + (size_t)3 * ROW_WINDOW * rows_max);
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int64_t* cidx = a.cand_idx + (int64_t)s * a.cand_cap;
+    float* cdist = a.cand_dist + (int64_t)s * a.cand_cap;
+    bool staged = false;
+    int nr = 0, nre = 0;
+    auto decide = [&]() {
+        if (!staged) {
+            stage_obs_f64<0>(f.obs[s], d.T, lobs);
+            staged = true;
+        }
+        __syncthreads();
+        const double d64 = simulate_rows_f64_wave<0, 0>(nr, rth, rix, a.key, d.series_id, a.domain, d.P,
+                                                       d.A0, d.R0, d.D0, d.T, (double)a.scale, lobs, zs,
+                                                       xs, rw);
+        if (lane < nr) {
+            const int q = rq[lane];
+            cdist[q] = (float)d64;
+            if (!(d64 <= (double)d.eps)) cidx[q] = INT64_MAX;
+        }
+        nre += nr;
+        nr = 0;
+        __syncthreads();  // the row slots are refilled next
+    };
+    for (int c0 = q0; c0 < q1; c0 += 64) {
+        const int q = c0 + lane;
+        const bool inb = q < q1 && cdist[q] > d.eps_lo;
+        uint64_t m = __ballot(inb);
+        while (m) {
+            uint64_t take = 0;
+            for (int room = rows_max - nr; room > 0 && m; --room) {
+                const uint64_t b = m & (~m + 1ull);
+                take |= b;
+                m ^= b;
+            }
+            if ((take >> lane) & 1ull) {
+                const int slot = nr + __popcll(take & below);
+                const int64_t k = cidx[q];
+                rq[slot] = q;
+                rix[slot] = (uint64_t)k;
+                float th[8];
+                (void)batch_theta(a, s, d, (uint64_t)k, th);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) rth[8 * slot + j] = th[j];
+            }
+            nr += __popcll(take);
+            if (nr == rows_max) decide();
+        }
+    }
+    if (nr > 0) decide();
+    if (lane == 0 && nre > 0 && f.out_rechecked) atomicAdd(&f.out_rechecked[s], nre);
+}
+
+static size_t band_lds_bytes(int maxT, int R)
+{
+    return sizeof(double) * 3 * (size_t)maxT +
+           (size_t)R * (sizeof(double) * 5 * ROW_WINDOW + sizeof(uint64_t) + 2 * sizeof(int32_t) +
+                        sizeof(RowWalk) + sizeof(int32_t) * 3 * ROW_WINDOW + sizeof(float) * 8);
+}
+
 __global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
 {
     extern __shared__ unsigned char lds_f8[];
@@ -521,30 +608,15 @@ __global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
     while (npow < n) npow <<= 1;
     int64_t* key = reinterpret_cast<int64_t*>(lds_f8);
     float* val = reinterpret_cast<float*>(key + npow);
-    double* obs64 = reinterpret_cast<double*>(val + npow + (npow & 1));
     __shared__ int nkeep;
-    __shared__ int nre;
-    if (threadIdx.x == 0) { nkeep = 0; nre = 0; }
-    for (int q = threadIdx.x; q < 3 * d.T; q += blockDim.x) obs64[q] = log1p((double)f.obs[s][q]);
-    __syncthreads();
-    // float64 decision inside the band; rejected rows get idx = INT64_MAX
+    if (threadIdx.x == 0) nkeep = 0;
+    // the band rows were decided in float64 by k_batch_band (rejected: idx INT64_MAX)
     for (int q = threadIdx.x; q < npow; q += blockDim.x) {
         int64_t k = INT64_MAX;
         float v = INFINITY;
         if (q < n) {
             k = a.cand_idx[(int64_t)s * a.cand_cap + q];
             v = a.cand_dist[(int64_t)s * a.cand_cap + q];
-            if (v > d.eps_lo) {
-                float th[8];
-                (void)batch_theta(a, s, d, (uint64_t)k, th);
-                const double d64 = simulate_one_f64<0, 0>(th, (uint64_t)k, a.key, d.series_id,
-                                                          a.domain, d.P, d.A0, d.R0, d.D0, d.T,
-                                                          (double)a.scale, obs64,
-                                                          (double)INFINITY);
-                v = (float)d64;
-                if (!(d64 <= (double)d.eps)) k = INT64_MAX;
-                atomicAdd(&nre, 1);
-            }
         }
         key[q] = k;
         val[q] = v;
@@ -567,7 +639,6 @@ __global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
     if (threadIdx.x == 0) {
         f.out_count[s] = cand > a.cand_cap ? -(int64_t)cand : (int64_t)nkeep;
         f.out_used[s] = a.state[s].next;
-        if (f.out_rechecked) f.out_rechecked[s] = nre;
     }
 }
 
@@ -743,8 +814,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     {
         int np = 1;
         while (np < (cand_capacity ? cand_capacity : cand_default)) np <<= 1;
-        const size_t lds_final = sizeof(int64_t) * np + sizeof(float) * (np + 1) +
-                                 sizeof(double) * 3 * (size_t)maxT + 16;
+        const size_t lds_final = sizeof(int64_t) * np + sizeof(float) * (np + 1) + 16;
         if (lds_final > (size_t)max_lds)
             return set_error(ABC_EINVAL, "cand_capacity %d needs %zu B of LDS to sort (> %d)",
                              cand_capacity ? cand_capacity : cand_default, lds_final, max_lds);
@@ -950,8 +1020,13 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     f.out_used = out_used;
     f.out_rechecked = reinterpret_cast<int32_t*>(b_re.p);
     const int npow = npow_cap;
-    const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + sizeof(double) * 3 * maxT + 16;
+    const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + 16;
     ABC_REQUIRE(lds_f <= (size_t)max_lds, "quota too large for the finalisation");
+    const int band_rows = ROWS_PER_WAVE_MAX;
+    const size_t lds_band = band_lds_bytes(maxT, band_rows);
+    ABC_REQUIRE(lds_band <= (size_t)max_lds, "horizon too long for the band decision");
+    ABC_HIP(hipMemsetAsync(b_re.p, 0, sizeof(int32_t) * m, s));
+    hipLaunchKernelGGL(k_batch_band, dim3((unsigned)m * BAND_GROUPS), dim3(64), lds_band, s, f, band_rows);
     hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(256), lds_f, s, f);
     hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, f.out_w, out_count,
                        quota, out_mean, out_cov);
