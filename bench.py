@@ -613,7 +613,7 @@ def main():
     ap.add_argument("--compare-quota", type=int, default=2048)
     ap.add_argument("--compare-seeds-plain", type=int, nargs="+", default=[2, 3, 4])
     ap.add_argument("--compare-seeds-learned", type=int, nargs="+", default=[2, 3, 4, 5])
-    ap.add_argument("--compare-max-runs", type=int, default=800)
+    ap.add_argument("--compare-max-runs", type=int, default=8000)
     ap.add_argument("--compare-time-s", type=float, default=240.0,
                     help="wall-time bound on the posterior check's pooling")
     ap.add_argument("--refill-min", type=int, default=0, help="lane-refill threshold (0 = default)")

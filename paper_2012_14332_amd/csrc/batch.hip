@@ -202,11 +202,16 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
         n_s = per + (rank < rem ? 1 : 0);
         if (n_s > a.max_samples - next) n_s = a.max_samples - next;
         // keep the expected candidates of the running round and this one
-        // together within half the free capacity, at the candidate rate of
-        // the finished rounds (the schedule never changes which samples are
-        // accepted, only how many rounds it takes)
+        // together within half the free capacity, at an upper bound of the
+        // candidate rate of the finished rounds: (sqrt(c + 1) + 2)^2 for c
+        // candidates, about four Poisson standard deviations above the count,
+        // so that a round sized from the few candidates of a short first
+        // round cannot overrun the capacity when they undercount the rate
+        // (the schedule never changes which samples are accepted, only how
+        // many rounds it takes)
         if (done > 0) {
-            const double rate = ((double)cand_f + 1.0) / (double)done;
+            const double cu = sqrt((double)cand_f + 1.0) + 2.0;
+            const double rate = cu * cu / (double)done;
             const double half = 0.5 * (double)((int64_t)a.cand_cap - cand_f) - rate * (double)inflight;
             int64_t lim = half > 0.0 ? (int64_t)(half / rate) : 0;
             if (lim < 64) lim = 64;
@@ -1054,9 +1059,16 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         stats->rounds_ms = rounds_ms;
     }
     for (int s2 = 0; s2 < m; ++s2) {
-        if (cnt[s2] < 0)
-            return set_error(ABC_EOVERFLOW, "series %d: %lld candidates exceed the capacity %d",
-                             s2, (long long)-cnt[s2], cand_cap);
+        if (cnt[s2] < 0) {
+            SeriesState st{};
+            (void)hipMemcpy(&st, a.state + s2, sizeof(st), hipMemcpyDeviceToHost);
+            return set_error(ABC_EOVERFLOW,
+                             "series %d: %lld candidates exceed the capacity %d (certain %d; folded: "
+                             "certain %d, candidates %d, samples %lld of %lld; %lld rounds, stop %lld)",
+                             s2, (long long)-cnt[s2], cand_cap, st.certain, st.certain_f, st.cand_f,
+                             (long long)st.done, (long long)st.next, (long long)rounds,
+                             (long long)stop_at);
+        }
         if (cnt[s2] < quota)
             return set_error(ABC_EOVERFLOW, "series %d: %lld of %d accepted within max_samples",
                              s2, (long long)cnt[s2], quota);

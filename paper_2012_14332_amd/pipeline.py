@@ -273,6 +273,45 @@ def _weighted_summary(theta: np.ndarray, w: np.ndarray):
     return m, sd, ess, se_m, se_sd
 
 
+class _Pool:
+    """Running form of _weighted_summary over runs added one at a time: the
+    weight sums and the weighted power sums of theta - c up to the fourth,
+    with c the first run's weighted mean (which keeps the central moments
+    free of cancellation), so a summary costs O(1) in the pooled runs."""
+
+    def __init__(self):
+        self.runs = 0
+        self.c = None
+
+    def add(self, theta: np.ndarray, w: np.ndarray):
+        w = np.asarray(w, np.float64)
+        theta = np.asarray(theta, np.float64)
+        if self.c is None:
+            self.c = (w[:, None] * theta).sum(0) / w.sum()
+            self.W = self.W2 = 0.0
+            self.S = np.zeros((4, theta.shape[1]))
+        y = theta - self.c
+        wy = w[:, None] * y
+        self.W += float(w.sum())
+        self.W2 += float((w * w).sum())
+        for k in range(4):
+            self.S[k] += wy.sum(0)
+            wy = wy * y
+        self.runs += 1
+
+    def summary(self):
+        s1, s2, s3, s4 = self.S / self.W
+        ess = self.W * self.W / self.W2
+        mu = s1
+        m2 = s2 - mu * mu
+        m4 = s4 - 4.0 * mu * s3 + 6.0 * mu * mu * s2 - 3.0 * mu ** 4
+        sd = np.sqrt(np.maximum(m2, 0.0) / max(1.0 - 1.0 / ess, 1e-12))
+        kurt = m4 / np.maximum(m2 * m2, 1e-300)
+        se_m = sd / np.sqrt(ess)
+        se_sd = sd * np.sqrt(np.maximum(kurt - 1.0, 0.0) / (4.0 * ess))
+        return self.c + mu, sd, ess, se_m, se_sd
+
+
 def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2, 3, 4),
                        seeds_b=(2, 3, 4), max_runs: int = 48, resolution: float = 4.0,
                        min_ess: float = 1e4, rel: float = 0.05, time_limit_s: float = None,
@@ -291,7 +330,7 @@ def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2
 
     t_start = time.perf_counter()
     m = len(sers)
-    pools = {"a": [[[], []] for _ in range(m)], "b": [[[], []] for _ in range(m)]}
+    pools = {"a": [_Pool() for _ in range(m)], "b": [_Pool() for _ in range(m)]}
     next_seed = {"a": list(seeds_a), "b": list(seeds_b)}
     # further runs take fresh seeds per side (so no series sees a seed twice)
     extra = {"a": 100, "b": 200}
@@ -309,8 +348,7 @@ def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2
             extra[side] += 1
         th, w = fn(seed, idxs)
         for q, j in enumerate(idxs):
-            pools[side][j][0].append(th[q])
-            pools[side][j][1].append(w[q])
+            pools[side][j].add(th[q], w[q])
             runs[side][j] += 1
 
     for _ in range(max(len(seeds_a), len(seeds_b))):
@@ -321,8 +359,8 @@ def compare_posteriors(sers, eps, run_a, run_b, *, quota: int = 4096, seeds_a=(2
     while todo:
         need_a, need_b = [], []
         for j in todo:
-            sa = _weighted_summary(np.concatenate(pools["a"][j][0]), np.concatenate(pools["a"][j][1]))
-            sb = _weighted_summary(np.concatenate(pools["b"][j][0]), np.concatenate(pools["b"][j][1]))
+            sa = pools["a"][j].summary()
+            sb = pools["b"][j].summary()
             tol_m = rel * np.maximum(np.abs(sa[0]), sa[1])
             tol_s = rel * sa[1]
             se_dm = np.sqrt(sa[3] ** 2 + sb[3] ** 2)

@@ -170,6 +170,31 @@ def test_batch_single_series_equals_plain_path(env):
     np.testing.assert_array_equal(out["idx"][0].cpu().numpy(), plain)
 
 
+def test_batch_one_series_large_rounds_stay_within_capacity(env):
+    """One series, rounds of 2^22 samples and a candidate capacity of three
+    times the quota: the first round is short (nothing is known of the rate
+    yet), and the rounds sized from its few candidates must not overrun the
+    capacity on seeds where those undercount the rate. Every seed completes,
+    and the accepted set does not depend on the round size."""
+    abc, P = env
+    s = W.uneven_series(64, 5)[13]
+    ser = P.observed_series(s)
+    eps = P.pilot_eps(ser, 9, n=100_000, q=2e-3, series=0)
+    quota = 1024
+    failed = []
+    for seed in range(100, 300):
+        try:
+            out = abc.batch_run([ser], [eps], seed, quota, round_size=1 << 22, cand_capacity=3 * quota)
+        except abc.AbcError as e:
+            failed.append((seed, str(e)))
+            continue
+        assert int(out["count"][0]) == quota
+        if seed < 103:
+            small = abc.batch_run([ser], [eps], seed, quota, round_size=1 << 16, cand_capacity=3 * quota)
+            assert torch.equal(small["idx"], out["idx"]) and torch.equal(small["count"], out["count"])
+    assert not failed, failed[:3]
+
+
 def test_batch_series_count_limit(env):
     """256 series (the most one batch takes; short ones, since every series'
     observations sit in LDS at once) and 257 rejected."""

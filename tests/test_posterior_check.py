@@ -59,3 +59,19 @@ def test_importance_weights_correct_a_tilted_proposal():
     assert all(res[0]["mean_ok"]) and all(res[0]["sd_ok"])
     unweighted = P.compare_posteriors([None], [None], _sampler(target), _sampler(prop), quota=4096)
     assert not all(unweighted[0]["mean_ok"])
+
+
+def test_running_pool_equals_the_pooled_summary():
+    # the running sums give the summary of the concatenated runs
+    rng = np.random.default_rng(3)
+    pool, ths, ws = P._Pool(), [], []
+    for r in range(7):
+        th = rng.standard_t(5, size=(500, 8)) * (1.0 + np.arange(8)) + 40.0
+        w = rng.gamma(0.5, size=500)
+        pool.add(th, w)
+        ths.append(th)
+        ws.append(w)
+    want = P._weighted_summary(np.concatenate(ths), np.concatenate(ws))
+    got = pool.summary()
+    for a, b in zip(got, want):
+        np.testing.assert_allclose(a, b, rtol=1e-9)
