@@ -491,6 +491,9 @@ struct FinalArgs {
     int64_t* out_count;  // [m]
     int64_t* out_used;   // [m] samples consumed
     int32_t* out_rechecked;
+    int32_t* band_n;     // [m] band rows of each series (zeroed before k_band_collect)
+    int32_t* band_q;     // [m][cand_cap] their positions in the candidate list
+    int32_t* band_next;  // chunk counter of k_batch_band (zeroed with band_n)
 };
 
 // bitonic sort of (idx, dist) pairs in LDS, ascending by idx
@@ -515,42 +518,103 @@ __device__ void bitonic_sort(int64_t* key, float* val, int n_pow2)
 }
 
 // Float64 decision of the band rows (candidates with eps (1 - w) < d <=
-// eps (1 + w)): workgroup (s, g) of one wavefront scans block g of series s's
-// candidates and simulates its band rows in float64 side by side, up to
-// rows_max at a time (simulate_rows_f64_wave: each row's distance is the
-// double simulate_one_f64 gives). A decided row keeps its float64 distance
-// (as float); a rejected one gets idx INT64_MAX, which sorts it last.
-// Workgroups that meet no band row never stage the observed series.
-constexpr int BAND_GROUPS = 16;  // workgroups per series
+// eps (1 + w)), in two kernels. k_band_collect lists each series' band rows
+// (positions in its candidate list, in any order: each row is decided on its
+// own). k_batch_band is a persistent grid of one-wavefront workgroups that
+// take chunks of up to rows_max rows of one series from a global counter and
+// simulate them in float64 side by side (simulate_rows_f64_wave: each row's
+// distance is the double simulate_one_f64 gives), so every walk but the last
+// of a series is full and no wavefront waits on another's series. A decided
+// row keeps its float64 distance (as float); a rejected one gets idx
+// INT64_MAX, which sorts it last.
+constexpr int COLLECT_GROUPS = 4;  // workgroups of 256 per series in the collection
 
-__global__ __launch_bounds__(64) void k_batch_band(FinalArgs f, int rows_max)
+__global__ __launch_bounds__(256) void k_band_collect(FinalArgs f)
 {
-    extern __shared__ double lds_band[];
     const BatchArgs& a = f.b;
-    const int s = blockIdx.x / BAND_GROUPS, g = blockIdx.x % BAND_GROUPS;
-    const SeriesDesc d = a.desc[s];
+    const int s = blockIdx.x / COLLECT_GROUPS, g = blockIdx.x % COLLECT_GROUPS;
     const int cand = a.state[s].cand;
     const int n = cand < a.cand_cap ? cand : a.cand_cap;
-    const int per = (n + BAND_GROUPS - 1) / BAND_GROUPS;
-    const int q0 = g * per, q1 = q0 + per < n ? q0 + per : n;
-    if (q0 >= q1) return;
+    const float lo = a.desc[s].eps_lo;
+    const float* cdist = a.cand_dist + (int64_t)s * a.cand_cap;
+    int32_t* bq = f.band_q + (int64_t)s * a.cand_cap;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int base = (g * 4 + (int)(threadIdx.x >> 6)) * 64; base < n; base += COLLECT_GROUPS * 256) {
+        const int q = base + lane;
+        const bool inb = q < n && cdist[q] > lo;
+        const uint64_t m = __ballot(inb);
+        if (m == 0ull) continue;
+        int pos = 0;
+        if (lane == 0) pos = atomicAdd(&f.band_n[s], __popcll(m));
+        pos = __shfl(pos, 0, 64);
+        if (inb) bq[pos + __popcll(m & below)] = q;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_batch_band(FinalArgs f, int rows_max, int max_T)
+{
+    extern __shared__ double lds_band[];
+    __shared__ int pre[BT_MAX_SERIES + 1];  // first chunk of each series
+    const BatchArgs& a = f.b;
+    const int lane = threadIdx.x;
+    // chunks of series s: ceil(band_n[s] / rows_max), laid out in series order
+    int total = 0;
+    for (int s0 = 0; s0 < a.m; s0 += 64) {
+        const int s = s0 + lane;
+        const int c = s < a.m ? (f.band_n[s] + rows_max - 1) / rows_max : 0;
+        int incl = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (s < a.m) pre[s + 1] = total + incl;
+        total += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) pre[0] = 0;
+    __syncthreads();
+    if (total == 0) return;
     double* lobs = lds_band;
-    double* zs = lobs + 3 * d.T;
+    double* zs = lobs + 3 * max_T;
     uint64_t* rix = reinterpret_cast<uint64_t*>(zs + (size_t)5 * ROW_WINDOW * rows_max);
     int32_t* rq = reinterpret_cast<int32_t*>(rix + rows_max);
     RowWalk* rw = reinterpret_cast<RowWalk*>(rq + 2 * rows_max);  // rq padded to 8 B per row
     int32_t* xs = reinterpret_cast<int32_t*>(rw + rows_max);
     float* rth = reinterpret_cast<float*>(xs + (size_t)3 * ROW_WINDOW * rows_max);
-    const int lane = threadIdx.x;
-    const uint64_t below = (1ull << lane) - 1ull;
-    int64_t* cidx = a.cand_idx + (int64_t)s * a.cand_cap;
-    float* cdist = a.cand_dist + (int64_t)s * a.cand_cap;
-    bool staged = false;
-    int nr = 0, nre = 0;
-    auto decide = [&]() {
-        if (!staged) {
+    int staged = -1;
+    for (;;) {
+        int c = 0;
+        if (lane == 0) c = atomicAdd(f.band_next, 1);
+        c = __shfl(c, 0, 64);
+        if (c >= total) break;
+        // the series whose chunks hold c: pre[s] <= c < pre[s + 1]
+        int lo = 0, hi = a.m;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= c) lo = mid;
+            else hi = mid;
+        }
+        const int s = lo;
+        const SeriesDesc d = a.desc[s];
+        const int j0 = (c - pre[s]) * rows_max;
+        const int nb = f.band_n[s];
+        const int nr = nb - j0 < rows_max ? nb - j0 : rows_max;
+        int64_t* cidx = a.cand_idx + (int64_t)s * a.cand_cap;
+        float* cdist = a.cand_dist + (int64_t)s * a.cand_cap;
+        if (staged != s) {
             stage_obs_f64<0>(f.obs[s], d.T, lobs);
-            staged = true;
+            staged = s;
+        }
+        if (lane < nr) {
+            const int q = f.band_q[(int64_t)s * a.cand_cap + j0 + lane];
+            const int64_t k = cidx[q];
+            rq[lane] = q;
+            rix[lane] = (uint64_t)k;
+            float th[8];
+            (void)batch_theta(a, s, d, (uint64_t)k, th);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) rth[8 * lane + j] = th[j];
         }
         __syncthreads();
         const double d64 = simulate_rows_f64_wave<0, 0>(nr, rth, rix, a.key, d.series_id, a.domain, d.P,
@@ -561,37 +625,9 @@ __global__ __launch_bounds__(64) void k_batch_band(FinalArgs f, int rows_max)
             cdist[q] = (float)d64;
             if (!(d64 <= (double)d.eps)) cidx[q] = INT64_MAX;
         }
-        nre += nr;
-        nr = 0;
-        __syncthreads();  // the row slots are refilled next
-    };
-    for (int c0 = q0; c0 < q1; c0 += 64) {
-        const int q = c0 + lane;
-        const bool inb = q < q1 && cdist[q] > d.eps_lo;
-        uint64_t m = __ballot(inb);
-        while (m) {
-            uint64_t take = 0;
-            for (int room = rows_max - nr; room > 0 && m; --room) {
-                const uint64_t b = m & (~m + 1ull);
-                take |= b;
-                m ^= b;
-            }
-            if ((take >> lane) & 1ull) {
-                const int slot = nr + __popcll(take & below);
-                const int64_t k = cidx[q];
-                rq[slot] = q;
-                rix[slot] = (uint64_t)k;
-                float th[8];
-                (void)batch_theta(a, s, d, (uint64_t)k, th);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) rth[8 * slot + j] = th[j];
-            }
-            nr += __popcll(take);
-            if (nr == rows_max) decide();
-        }
+        if (lane == 0 && f.out_rechecked) atomicAdd(&f.out_rechecked[s], nr);
+        __syncthreads();  // the observed rows and row slots are refilled next
     }
-    if (nr > 0) decide();
-    if (lane == 0 && nre > 0 && f.out_rechecked) atomicAdd(&f.out_rechecked[s], nre);
 }
 
 static size_t band_lds_bytes(int maxT, int R)
@@ -852,14 +888,15 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     const size_t o_days = carve.take(sizeof(unsigned long long));
     const size_t o_order = carve.take(sizeof(int32_t) * m);
     const size_t o_mixtab = carve.take(prop ? sizeof(MixTable) * m : 0);
-    const size_t o_re = carve.take(sizeof(int32_t) * m);
+    const size_t o_re = carve.take(sizeof(int32_t) * (2 * (size_t)m + 1));  // rechecked, band_n, counter
+    const size_t o_bq = carve.take(sizeof(int32_t) * (size_t)m * cand_cap);
     void* arena = nullptr;
     if ((rc = stream_scratch(user, carve.off, &arena, SCRATCH_BATCH))) return rc;
     char* base = static_cast<char*>(arena);
     struct View { void* p; } b_desc{base + o_desc}, b_state{base + o_state}, b_table{base + o_table},
         b_obs{base + o_obs}, b_ptrs{base + o_ptrs}, b_cidx{base + o_cidx}, b_cdist{base + o_cdist},
         b_flag{base + o_flag}, b_days{base + o_days}, b_order{base + o_order}, b_mixtab{base + o_mixtab},
-        b_re{base + o_re};
+        b_re{base + o_re}, b_bq{base + o_bq};
     int32_t* flag_host = nullptr;
     if ((rc = stream_pinned(user, sizeof(int32_t) * BT_EVR, reinterpret_cast<void**>(&flag_host)))) return rc;
 
@@ -1024,14 +1061,21 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     f.out_count = out_count;
     f.out_used = out_used;
     f.out_rechecked = reinterpret_cast<int32_t*>(b_re.p);
+    f.band_n = f.out_rechecked + m;
+    f.band_next = f.band_n + m;
+    f.band_q = reinterpret_cast<int32_t*>(b_bq.p);
     const int npow = npow_cap;
     const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + 16;
     ABC_REQUIRE(lds_f <= (size_t)max_lds, "quota too large for the finalisation");
     const int band_rows = ROWS_PER_WAVE_MAX;
     const size_t lds_band = band_lds_bytes(maxT, band_rows);
     ABC_REQUIRE(lds_band <= (size_t)max_lds, "horizon too long for the band decision");
-    ABC_HIP(hipMemsetAsync(b_re.p, 0, sizeof(int32_t) * m, s));
-    hipLaunchKernelGGL(k_batch_band, dim3((unsigned)m * BAND_GROUPS), dim3(64), lds_band, s, f, band_rows);
+    ABC_HIP(hipMemsetAsync(b_re.p, 0, sizeof(int32_t) * (2 * (size_t)m + 1), s));
+    hipLaunchKernelGGL(k_band_collect, dim3((unsigned)m * COLLECT_GROUPS), dim3(256), 0, s, f);
+    // one-wavefront workgroups: as many as the LDS holds per CU, at most 16
+    const int band_per_cu = std::min(16, std::max(1, (int)(163840 / (lds_band + sizeof(int) * (BT_MAX_SERIES + 1)))));
+    hipLaunchKernelGGL(k_batch_band, dim3((unsigned)(num_cu * band_per_cu)), dim3(64), lds_band, s, f,
+                       band_rows, maxT);
     hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(256), lds_f, s, f);
     hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, f.out_w, out_count,
                        quota, out_mean, out_cov);
