@@ -360,10 +360,11 @@ typedef struct {
  * samples per series; ABC_EOVERFLOW if some series then still lacks its quota
  * or produced more candidates (d <= eps (1 + band_w)) than cand_capacity rows
  * (0 = max(4 quota, 256), at most 16384, and the finalisation sorts them in LDS: about
- * 12 B per row must fit, so 8192 rows at most on gfx950); each round caps a series' share by its
- * candidate rate so far to keep the running round's and its own expected candidates within half
- * the free capacity. Launch shape: abc_set_launch_config (spl 1, 2, 4 or 8). Blocks the calling host thread until done; the caller's
- * stream is ordered before and after the work. stats may be NULL.
+ * 12 B per row must fit, so 8192 rows at most on gfx950). Each round caps a series' share so
+ * that the running round's and its own expected candidates stay within half the free capacity,
+ * at an upper bound of the candidate rate so far ((sqrt(c + 1) + 2)^2 candidates for c counted).
+ * Launch shape: abc_set_launch_config (spl 1, 2, 4 or 8). Blocks the calling host thread until
+ * done; the caller's stream is ordered before and after the work. stats may be NULL.
  */
 ABC_API abc_status abc_batch_run(const abc_batch_series* series, int32_t m,
                                  const abc_prior* prior, const abc_model* model, uint64_t seed,
