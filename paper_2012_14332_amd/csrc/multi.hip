@@ -94,22 +94,6 @@ struct MLane {
     uint32_t b1;
 };
 
-// Hand-off of a wavefront's last trajectories. A wavefront whose queue is
-// exhausted runs its remaining trajectories with the rest of its lanes idle;
-// once at most HO_MAX lanes are still running, it writes their state into its
-// own ring slots (free once the queue is done), publishes the count and ends,
-// and the wavefronts of the workgroup that still run take them into their
-// idle lanes. A trajectory continues from exactly the state it had, so every
-// distance is the same; the workgroup's last wavefront never hands off and
-// ends once no trajectory is left anywhere.
-constexpr int HO_MAX = 32;  // hand-off records a ring holds (6 x 16 B each)
-constexpr int HO_REC4 = 6;
-
-__device__ __forceinline__ int lds_load_relaxed(const int* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 template <int NOISE, int DIST, bool KAHAN>
 __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
 {
@@ -160,22 +144,6 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
                 stage[q] = log1p((double)sj.obs[sj.T + q]) * 1.44269504088896340736;
             __syncthreads();
             build_future_bound(stage, sj.T, sj.lb_sh, sj.ntb, (double)sj.exit_f32, tabs + sj.tab_off);
-        }
-    }
-    // hand-off state of the workgroup: wavefronts still in the loop, hand-offs
-    // being written, and per wavefront its records published / claimed
-    __shared__ int ho_live, ho_pending;
-    __shared__ int ho_n[16], ho_c[16];
-    {
-        const int nwb = (int)(blockDim.x >> 6);
-        if (threadIdx.x < 16u) {
-            ho_n[threadIdx.x] = 0;
-            ho_c[threadIdx.x] = 0;
-        }
-        if (threadIdx.x == 0) {
-            const int64_t left = a.nchunks - (int64_t)blockIdx.x * nwb;
-            ho_live = left <= 0 ? 0 : (left < nwb ? (int)left : nwb);
-            ho_pending = 0;
         }
     }
     __syncthreads();
@@ -234,8 +202,6 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
     MLane l;
     l.t = 0;
     uint32_t days_done = 0;
-    const int nwb = (int)(blockDim.x >> 6);
-    bool last = false;  // the workgroup's last wavefront: takes every hand-off
 
     while (true) {
         // refill: the idle lanes take the next queue positions in lane order,
@@ -243,98 +209,7 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
         // of one chunk and the start of the next
         bool want = l.t == 0;
         uint64_t m = __ballot(want);
-        if (qb >= Q) {
-            const uint64_t act = __ballot(l.t != 0);
-            if (!last && __popcll(act) <= HO_MAX) {
-                // leave unless this is the last wavefront still in the loop
-                int ok = 0;
-                if (lane == 0) {
-                    atomicAdd(&ho_pending, 1);
-                    if (atomicSub(&ho_live, 1) == 1) {
-                        atomicAdd(&ho_live, 1);
-                        atomicSub(&ho_pending, 1);
-                    } else {
-                        ok = 1;
-                    }
-                }
-                if (__shfl(ok, 0, 64)) {
-                    if (l.t != 0) {
-                        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
-                        uint4* rec = reinterpret_cast<uint4*>(ring) + rank * HO_REC4;
-                        const uint64_t k = (uint64_t)l.k;
-                        rec[0] = make_uint4((uint32_t)l.s.S, (uint32_t)l.s.I, (uint32_t)l.s.A, (uint32_t)l.s.R);
-                        rec[1] = make_uint4((uint32_t)l.s.D, (uint32_t)l.s.Ru, __float_as_uint(l.r.a0),
-                                            __float_as_uint(l.r.al));
-                        rec[2] = make_uint4(__float_as_uint(l.r.n), __float_as_uint(l.r.be),
-                                            __float_as_uint(l.r.ga), __float_as_uint(l.r.de));
-                        rec[3] = make_uint4(__float_as_uint(l.r.bh), l.ph.c1base, l.ph.g3, l.ph.h3);
-                        rec[4] = make_uint4(l.ph.f3, (uint32_t)k, (uint32_t)(k >> 32), (uint32_t)l.ls);
-                        rec[5] = make_uint4((uint32_t)l.t, __float_as_uint(l.acc), __float_as_uint(l.comp), 0u);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    if (lane == 0) {
-                        __hip_atomic_store(&ho_n[wv], __popcll(act), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                        atomicSub(&ho_pending, 1);
-                    }
-                    break;
-                }
-                last = true;
-            }
-            // queue done: idle lanes take trajectories other wavefronts handed off
-            if (m != 0ull) {
-                const bool has = lane < nwb && lds_load_relaxed(&ho_c[lane]) < lds_load_relaxed(&ho_n[lane]);
-                const uint64_t hb = __ballot(has);
-                if (hb != 0ull) {
-                    const int v = __builtin_amdgcn_readfirstlane(__builtin_ctzll(hb));
-                    const int wantn = __popcll(m);
-                    int base = 0, got = 0;
-                    if (lane == 0) {
-                        base = atomicAdd(&ho_c[v], wantn);
-                        const int avail = lds_load_relaxed(&ho_n[v]) - base;
-                        got = avail < wantn ? avail : wantn;
-                    }
-                    base = __shfl(base, 0, 64);
-                    got = __shfl(got, 0, 64);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    if (want && rank < got) {
-                        const uint4* rec = reinterpret_cast<const uint4*>(ring_all + v * RING) +
-                                           (base + rank) * HO_REC4;
-                        const uint4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4],
-                                    q5 = rec[5];
-                        l.s.S = (int32_t)q0.x; l.s.I = (int32_t)q0.y; l.s.A = (int32_t)q0.z;
-                        l.s.R = (int32_t)q0.w; l.s.D = (int32_t)q1.x; l.s.Ru = (int32_t)q1.y;
-                        l.r = RatesF{__uint_as_float(q1.z), __uint_as_float(q1.w), __uint_as_float(q2.x),
-                                     __uint_as_float(q2.y), __uint_as_float(q2.z), __uint_as_float(q2.w),
-                                     __uint_as_float(q3.x)};
-                        l.ph.c1base = q3.y; l.ph.g3 = q3.z; l.ph.h3 = q3.w; l.ph.f3 = q4.x;
-                        l.k = (int64_t)(((uint64_t)q4.z << 32) | q4.y);
-                        l.ls = (int32_t)q4.w;
-                        l.t = (int32_t)q5.x;
-                        l.acc = __uint_as_float(q5.y);
-                        l.comp = __uint_as_float(q5.z);
-                        const SerLds e = ser[l.ls];
-                        l.T = e.T; l.obs_off = e.obs_off;
-                        l.tr = e.tab_r >= 0 ? tabs + e.tab_r : nullptr;
-                        l.td = tabs + e.tab_d;
-                        l.lb_sh = e.lb_sh; l.invP = e.invP; l.exitb = e.exitb; l.b1 = e.b1;
-                    }
-                }
-            }
-            if (__ballot(l.t != 0) == 0ull) {
-                // only the last wavefront gets here: it ends once every
-                // hand-off has been published (none pending) and taken
-                const int pend = lds_load_relaxed(&ho_pending);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const bool has = lane < nwb && lds_load_relaxed(&ho_c[lane]) < lds_load_relaxed(&ho_n[lane]);
-                if (__shfl(pend, 0, 64) == 0 && __ballot(has) == 0ull) break;
-                continue;
-            }
-        } else if (__popcll(m) >= a.refill_min) {
+        if (__popcll(m) >= a.refill_min) {
             while (m != 0ull && qb < Q) {
                 const uint32_t jc = qb >> 6;
                 if (jc != filled) {
@@ -372,6 +247,7 @@ __global__ __launch_bounds__(1024) void k_simulate_multi_f32(MultiArgs a)
                 m = __ballot(want);
             }
         }
+        if (__ballot(l.t != 0) == 0ull && qb >= Q) break;
         if (l.t != 0) {
             const int t = l.t;
             const uint4 w = l.ph.day(((uint32_t)t << 8) | wdom, l.b1, a.key);
