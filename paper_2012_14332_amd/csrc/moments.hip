@@ -2,7 +2,7 @@
 // parameter averages of Table "t:trajectories", extended to the covariance
 // and to importance weights), and its C-ABI entry point abc_posterior_moments.
 //
-// Deterministic: the n rows are cut into G = min(512, ceil(n / 2048))
+// Deterministic: the n rows are cut into G = min(768, ceil(n / 2048))
 // contiguous ranges, a function of n alone. Workgroup b sums its range (each
 // thread every 256th row, in row order; theta read as two float4 per row)
 // into V1, V2, S1 = sum w (theta - c), S2 = sum w (theta - c)(theta - c)^T
@@ -21,14 +21,16 @@
 namespace abc {
 
 constexpr int MOM_BLOCK = 256;
-// Most row ranges (workgroups of the partial pass): at the partial pass's
-// register budget two wavefronts fit a SIMD, so 512 workgroups of four
-// wavefronts are one resident round on 256 CUs (768 left half the chip idle
-// for the last third of the pass).
-constexpr int MOM_GROUPS = 512;
+// Most row ranges (workgroups of the partial pass): with one step of rows
+// loaded ahead the pass takes 162 VGPRs, so three wavefronts fit a SIMD and
+// 768 workgroups of four wavefronts are one resident round on 256 CUs. Four
+// steps ahead took 202 VGPRs (two wavefronts, 512 workgroups) and moved 6-8 %
+// fewer bytes per second on 1e8 rows: the third wavefront hides more latency
+// than the deeper batch.
+constexpr int MOM_GROUPS = 768;
 constexpr int MOM_MIN_ROWS = 2048;  // fewest rows per range
 constexpr int MOM_NSUM = 2 + 8 + 36;
-constexpr int MOM_BATCH = 4;        // rows whose loads a thread issues together
+constexpr int MOM_BATCH = 1;        // steps of rows whose loads a thread issues together
 
 // number of row ranges for n rows (depends on n only)
 __host__ __device__ inline int64_t mom_groups(int64_t n)
