@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
 
 // ---------------------------------------------------------------------------
 // Two-pass compaction (abc_accept_compact). Each wavefront owns a unit of
-// CP_SPAN consecutive samples. Pass 1 streams the unit's distances once and,
+// consecutive samples (16 steps of 4096; fewer below CP_SHORT samples). Pass 1 streams the unit's distances once and,
 // with no dependency on any other wavefront, counts its accepted samples and
 // keeps the unit offsets of the first CP_SLOTS of them in sample order. A
 // single workgroup then forms the exclusive prefix of the unit counts, and
@@ -224,12 +224,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
 // kernel above; the streaming pass has no ticket and no look-back to wait on.
 // ---------------------------------------------------------------------------
 constexpr int CP_CHUNKS = 16;                        // 4096-sample steps per unit
-constexpr int64_t CP_SPAN = (int64_t)CT_WAVE_SPAN * CP_CHUNKS;  // 65536 samples
 constexpr int CP_SLOTS = 64;                         // accepted offsets kept per unit
 constexpr int CP_WAVES = 4;                          // wavefronts per workgroup
+// Below this many samples the units shrink (down to one step), so that a
+// short input spreads over many wavefronts instead of a few walking 16 steps
+// each; the order of the rows does not depend on the unit size.
+constexpr int64_t CP_SHORT = (int64_t)1 << 20;
 
 struct CpArgs {
     CompactArgs a;
+    int32_t chunks;  // 4096-sample steps per unit
+    int64_t span;    // samples per unit (CT_WAVE_SPAN chunks)
     int64_t units;
     uint32_t* cnt;   // [units]
     uint32_t* slot;  // [units][CP_SLOTS]
@@ -288,10 +293,10 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_cp_count(CpArgs p)
     const int lane = threadIdx.x & 63;
     const int64_t u = (int64_t)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
     if (u >= p.units) return;
-    const int64_t start = u * CP_SPAN;
+    const int64_t start = u * p.span;
     uint32_t* slot = p.slot + u * CP_SLOTS;
     int64_t total = 0;
-    for (int j = 0; j < CP_CHUNKS; ++j) {
+    for (int j = 0; j < p.chunks; ++j) {
         const int64_t s0 = start + (int64_t)j * CT_WAVE_SPAN;
         if (s0 >= p.a.n) break;
         const uint64_t bits = step_mask(p.a, s0, lane);
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_cp_emit(CpArgs p)
     if (c == 0) return;
     const int64_t base = p.pref[u];
     if (base >= p.a.capacity) return;
-    const int64_t start = u * CP_SPAN;
+    const int64_t start = u * p.span;
     if (c <= (uint32_t)CP_SLOTS) {
         for (uint32_t j = lane; j < c; j += 64)
             emit_row(p.a, start + p.slot[u * CP_SLOTS + j], base + j);
@@ -347,7 +352,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_cp_emit(CpArgs p)
     }
     // more accepts than kept offsets: stream the unit again, in order
     int64_t total = 0;
-    for (int j = 0; j < CP_CHUNKS; ++j) {
+    for (int j = 0; j < p.chunks; ++j) {
         const int64_t s0 = start + (int64_t)j * CT_WAVE_SPAN;
         if (s0 >= p.a.n || base + total >= p.a.capacity) break;
         const uint64_t bits = step_mask(p.a, s0, lane);
@@ -486,7 +491,13 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
     // stream's buffer
     CpArgs p{};
     p.a = a;
-    p.units = (n + CP_SPAN - 1) / CP_SPAN;
+    p.chunks = CP_CHUNKS;
+    if (n < CP_SHORT) {
+        const int64_t c = (n + CT_WAVE_SPAN * 64 - 1) / (CT_WAVE_SPAN * 64);  // about 64 units
+        p.chunks = c < 1 ? 1 : (int32_t)c;
+    }
+    p.span = (int64_t)CT_WAVE_SPAN * p.chunks;
+    p.units = (n + p.span - 1) / p.span;
     const int64_t units = p.units > 0 ? p.units : 1;
     void* mem = nullptr;
     const size_t bytes = sizeof(int64_t) * (size_t)units + sizeof(uint32_t) * (size_t)units +

@@ -80,10 +80,28 @@ __global__ __launch_bounds__(256) void k_nk_minmax(const float* dist, int64_t n,
         mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
         cnt += __shfl_xor(cnt, off, 64);
     }
-    if ((threadIdx.x & 63) == 0 && cnt) {
-        atomicMin(&c->kmin, mn);
-        atomicMax(&c->kmax, mx);
-        atomicAdd(&c->finite, (unsigned long long)cnt);
+    // one set of device atomics per workgroup: the same three addresses from
+    // every wavefront serialise
+    __shared__ uint32_t smn[4], smx[4];
+    __shared__ uint64_t scnt[4];
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smn[wv] = mn;
+        smx[wv] = mx;
+        scnt[wv] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            mn = min(mn, smn[w]);
+            mx = max(mx, smx[w]);
+            cnt += scnt[w];
+        }
+        if (cnt) {
+            atomicMin(&c->kmin, mn);
+            atomicMax(&c->kmax, mx);
+            atomicAdd(&c->finite, (unsigned long long)cnt);
+        }
     }
 }
 
@@ -274,9 +292,11 @@ __global__ __launch_bounds__(256) void k_rows_place(const double* d, const int64
         for (int j = 0; j < 8; ++j) out_theta[8 * pos + j] = theta[8 * q + j];
 }
 
+// workgroups of the grid-stride passes: about 16 samples per thread, so a
+// short input does not pay for hundreds of LDS histogram clears and merges
 static unsigned nk_grid(int64_t n)
 {
-    const int64_t g = (n + 255) / 256;
+    const int64_t g = (n + 4095) / 4096;
     return (unsigned)(g < NK_GRID ? (g > 0 ? g : 1) : NK_GRID);
 }
 
