@@ -174,9 +174,10 @@ def single_country_leg(args):
 
 
 def batched_leg(args):
-    """The 64-uneven-series workload: one persistent hipGraph-captured launch per
-    round of 2^22 samples until every series has 1000 accepted samples, launch
-    shape from the autotuner."""
+    """The 64-uneven-series workload: one persistent launch per round of 2^22
+    samples, rounds planned on the device and overlapping on two streams,
+    until every series has 1000 accepted samples; launch shape from the
+    autotuner."""
     import numpy as np
     import torch
 
@@ -288,7 +289,7 @@ def learned_leg(args, batched):
     prev_shape, prev_refill = abc.get_launch_config(), abc.get_refill_min()
     tune = autotune.tune_batch(sers, eps, seed=2, quota=Q, round_size=1 << 22, use_cache=False,
                                mix=mix, lam=args.lam, inflate=args.inflate)
-    abc.batch_run(sers, eps, 2, Q, **kw)  # warm-up (graph capture, code paths)
+    abc.batch_run(sers, eps, 2, Q, **kw)  # warm-up (scratch, code paths)
     walls = []
     for rep in range(args.batch_reps):
         torch.cuda.synchronize()
