@@ -207,7 +207,8 @@ def test_distance_fp32_accuracy_statement(A):
 
 
 @pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 16383, 16384, 16385, 65536 + 4096 * 3 + 17,
-                               1_000_003, (1 << 25) + 4096 * 5 + 3])
+                               600_001, 1_000_003, (1 << 20) - 1, 1 << 20,
+                               (1 << 25) + 4096 * 5 + 3])
 def test_compact_matches_brute_force(A, n):
     rng = np.random.default_rng(n)
     dist = rng.exponential(size=n).astype(np.float32)
