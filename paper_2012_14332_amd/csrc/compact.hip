@@ -230,6 +230,12 @@ constexpr int CP_WAVES = 4;                          // wavefronts per workgroup
 // short input spreads over many wavefronts instead of a few walking 16 steps
 // each; the order of the rows does not depend on the unit size.
 constexpr int64_t CP_SHORT = (int64_t)1 << 20;
+// Up to this many samples pass 1 also keeps each step's count and pass 2 runs
+// one wavefront per step: a unit with more accepts than kept offsets is then
+// written by all its steps at once instead of one wavefront streaming it
+// again (high acceptance, as in the SMC generations). Larger inputs keep one
+// wavefront per unit, as most of those extra wavefronts would find nothing.
+constexpr int64_t CP_STEP_EMIT = (int64_t)1 << 22;
 
 struct CpArgs {
     CompactArgs a;
@@ -239,6 +245,7 @@ struct CpArgs {
     uint32_t* cnt;   // [units]
     uint32_t* slot;  // [units][CP_SLOTS]
     int64_t* pref;   // [units]
+    uint32_t* scnt;  // [units][chunks] accepts per step, or null (one emit wavefront per unit)
 };
 
 // Accept mask of one 4096-sample step of a unit: bit 4 q + c for sample
@@ -300,10 +307,13 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_cp_count(CpArgs p)
         const int64_t s0 = start + (int64_t)j * CT_WAVE_SPAN;
         if (s0 >= p.a.n) break;
         const uint64_t bits = step_mask(p.a, s0, lane);
-        if (__ballot(bits != 0ull) == 0ull) continue;
-        total += step_visit(bits, s0, lane, total, [&](int64_t k, int64_t r) {
-            if (r < CP_SLOTS) slot[r] = (uint32_t)(k - start);
-        });
+        int c = 0;
+        if (__ballot(bits != 0ull) != 0ull)
+            c = step_visit(bits, s0, lane, total, [&](int64_t k, int64_t r) {
+                if (r < CP_SLOTS) slot[r] = (uint32_t)(k - start);
+            });
+        total += c;
+        if (p.scnt && lane == 0) p.scnt[u * p.chunks + j] = (uint32_t)c;
     }
     if (lane == 0) p.cnt[u] = (uint32_t)total;
 }
@@ -361,6 +371,38 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_cp_emit(CpArgs p)
             emit_row(p.a, k, base + r);
         });
     }
+}
+
+// Pass 2 with one wavefront per step (inputs below CP_STEP_EMIT): a unit
+// within its kept offsets is written by its first step's wavefront; otherwise
+// each step's wavefront writes that step's accepts after those of the unit's
+// earlier steps.
+__global__ __launch_bounds__(64 * CP_WAVES) void k_cp_emit_steps(CpArgs p)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
+    const int64_t u = w / p.chunks;
+    const int j = (int)(w - u * p.chunks);
+    if (u >= p.units) return;
+    const uint32_t c = p.cnt[u];
+    if (c == 0) return;
+    const int64_t base = p.pref[u];
+    if (base >= p.a.capacity) return;
+    const int64_t start = u * p.span;
+    if (c <= (uint32_t)CP_SLOTS) {
+        if (j != 0) return;
+        for (uint32_t q = lane; q < c; q += 64)
+            emit_row(p.a, start + p.slot[u * CP_SLOTS + q], base + q);
+        return;
+    }
+    const int64_t s0 = start + (int64_t)j * CT_WAVE_SPAN;
+    if (s0 >= p.a.n) return;
+    const uint32_t* sc = p.scnt + u * p.chunks;
+    int64_t off = 0;
+    for (int q = 0; q < j; ++q) off += sc[q];
+    if (sc[j] == 0u || base + off >= p.a.capacity) return;
+    const uint64_t bits = step_mask(p.a, s0, lane);
+    step_visit(bits, s0, lane, 0, [&](int64_t k, int64_t r) { emit_row(p.a, k, base + off + r); });
 }
 
 }  // namespace abc
@@ -499,13 +541,16 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
     p.span = (int64_t)CT_WAVE_SPAN * p.chunks;
     p.units = (n + p.span - 1) / p.span;
     const int64_t units = p.units > 0 ? p.units : 1;
+    const bool steps = n < CP_STEP_EMIT;
     void* mem = nullptr;
     const size_t bytes = sizeof(int64_t) * (size_t)units + sizeof(uint32_t) * (size_t)units +
-                         sizeof(uint32_t) * (size_t)CP_SLOTS * (size_t)units;
+                         sizeof(uint32_t) * (size_t)CP_SLOTS * (size_t)units +
+                         (steps ? sizeof(uint32_t) * (size_t)p.chunks * (size_t)units : 0);
     if ((rc = stream_scratch(s, bytes, &mem))) return rc;
     p.pref = static_cast<int64_t*>(mem);
     p.cnt = reinterpret_cast<uint32_t*>(p.pref + units);
     p.slot = p.cnt + units;
+    p.scnt = steps ? p.slot + (size_t)CP_SLOTS * (size_t)units : nullptr;
     const unsigned grid = (unsigned)((units + CP_WAVES - 1) / CP_WAVES);
     if (p.units > 0) {
         hipLaunchKernelGGL(k_cp_count, dim3(grid), dim3(64 * CP_WAVES), 0, s, p);
@@ -514,8 +559,15 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
     hipLaunchKernelGGL(k_cp_scan, dim3(1), dim3(1024), 0, s, p);  // also writes the count
     if ((rc = check_launch("k_cp_scan"))) return rc;
     if (p.units > 0 && capacity > 0) {
-        hipLaunchKernelGGL(k_cp_emit, dim3(grid), dim3(64 * CP_WAVES), 0, s, p);
-        rc = check_launch("k_cp_emit");
+        if (steps) {
+            const int64_t waves = p.units * p.chunks;
+            hipLaunchKernelGGL(k_cp_emit_steps, dim3((unsigned)((waves + CP_WAVES - 1) / CP_WAVES)),
+                               dim3(64 * CP_WAVES), 0, s, p);
+            rc = check_launch("k_cp_emit_steps");
+        } else {
+            hipLaunchKernelGGL(k_cp_emit, dim3(grid), dim3(64 * CP_WAVES), 0, s, p);
+            rc = check_launch("k_cp_emit");
+        }
     }
     return rc;
 }
