@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
 
 // ---------------------------------------------------------------------------
 // Two-pass compaction (abc_accept_compact). Each wavefront owns a unit of
-// consecutive samples (16 steps of 4096; fewer below CP_SHORT samples). Pass 1 streams the unit's distances once and,
+// consecutive samples (16 steps of 4096; fewer below CP_STEP_EMIT samples). Pass 1 streams the unit's distances once and,
 // with no dependency on any other wavefront, counts its accepted samples and
 // keeps the unit offsets of the first CP_SLOTS of them in sample order. A
 // single workgroup then forms the exclusive prefix of the unit counts, and
@@ -226,15 +226,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_compact(CompactArgs a)
 constexpr int CP_CHUNKS = 16;                        // 4096-sample steps per unit
 constexpr int CP_SLOTS = 64;                         // accepted offsets kept per unit
 constexpr int CP_WAVES = 4;                          // wavefronts per workgroup
-// Below this many samples the units shrink (down to one step), so that a
-// short input spreads over many wavefronts instead of a few walking 16 steps
-// each; the order of the rows does not depend on the unit size.
-constexpr int64_t CP_SHORT = (int64_t)1 << 20;
-// Up to this many samples pass 1 also keeps each step's count and pass 2 runs
-// one wavefront per step: a unit with more accepts than kept offsets is then
-// written by all its steps at once instead of one wavefront streaming it
-// again (high acceptance, as in the SMC generations). Larger inputs keep one
-// wavefront per unit, as most of those extra wavefronts would find nothing.
+// Below this many samples the units shrink to about 256 per input (down to
+// one step), so that a short input spreads over many wavefronts instead of a
+// few walking 16 steps each, and pass 1 also keeps each step's count so that
+// pass 2 runs one wavefront per step: a unit with more accepts than kept
+// offsets is then written by all its steps at once instead of one wavefront
+// streaming it again (high acceptance, as in the SMC generations). Larger
+// inputs keep 16-step units and one emit wavefront per unit, as most extra
+// wavefronts would find nothing. The order of the rows does not depend on
+// either choice.
 constexpr int64_t CP_STEP_EMIT = (int64_t)1 << 22;
 
 struct CpArgs {
@@ -534,8 +534,8 @@ extern "C" abc_status abc_accept_compact(const float* dist, const float* theta,
     CpArgs p{};
     p.a = a;
     p.chunks = CP_CHUNKS;
-    if (n < CP_SHORT) {
-        const int64_t c = (n + CT_WAVE_SPAN * 64 - 1) / (CT_WAVE_SPAN * 64);  // about 64 units
+    if (n < CP_STEP_EMIT) {
+        const int64_t c = (n + CT_WAVE_SPAN * 256 - 1) / (CT_WAVE_SPAN * 256);  // about 256 units
         p.chunks = c < 1 ? 1 : (int32_t)c;
     }
     p.span = (int64_t)CT_WAVE_SPAN * p.chunks;

@@ -207,7 +207,7 @@ def test_distance_fp32_accuracy_statement(A):
 
 
 @pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 16383, 16384, 16385, 65536 + 4096 * 3 + 17,
-                               600_001, 1_000_003, (1 << 20) - 1, 1 << 20,
+                               600_001, 1_000_003, (1 << 20) + 5, (1 << 22) - 1, 1 << 22,
                                (1 << 25) + 4096 * 5 + 3])
 def test_compact_matches_brute_force(A, n):
     rng = np.random.default_rng(n)
