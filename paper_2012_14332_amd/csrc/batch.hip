@@ -496,20 +496,23 @@ struct FinalArgs {
     int32_t* band_next;  // chunk counter of k_batch_band (zeroed with band_n)
 };
 
-// bitonic sort of (idx, dist) pairs in LDS, ascending by idx
+// bitonic sort of (idx, dist) pairs in LDS, ascending by idx. Each step
+// compares element t with t ^ j; the threads walk the n_pow2 / 2 pairs
+// directly (pair i gives t by inserting a zero at bit log2 j), so no lane
+// idles on the upper element of a pair.
 __device__ void bitonic_sort(int64_t* key, float* val, int n_pow2)
 {
+    const int half = n_pow2 >> 1;
     for (int k = 2; k <= n_pow2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < n_pow2; t += blockDim.x) {
-                const int p = t ^ j;
-                if (p > t) {
-                    const bool up = (t & k) == 0;
-                    const int64_t a = key[t], b = key[p];
-                    if ((a > b) == up) {
-                        key[t] = b; key[p] = a;
-                        const float v = val[t]; val[t] = val[p]; val[p] = v;
-                    }
+            for (int i = threadIdx.x; i < half; i += blockDim.x) {
+                const int t = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const int p = t | j;
+                const bool up = (t & k) == 0;
+                const int64_t a = key[t], b = key[p];
+                if ((a > b) == up) {
+                    key[t] = b; key[p] = a;
+                    const float v = val[t]; val[t] = val[p]; val[p] = v;
                 }
             }
             __syncthreads();
@@ -637,7 +640,12 @@ static size_t band_lds_bytes(int maxT, int R)
                         sizeof(RowWalk) + sizeof(int32_t) * 3 * ROW_WINDOW + sizeof(float) * 8);
 }
 
-__global__ __launch_bounds__(256) void k_batch_final(FinalArgs f)
+// Finalisation: one workgroup per series sorts its candidates by index and
+// writes the first quota kept rows. The sort is bound by LDS latency, so the
+// workgroup is as large as allowed (16 wavefronts; 82 VGPRs, no spills).
+constexpr int FINAL_BLOCK = 1024;
+
+__global__ __launch_bounds__(FINAL_BLOCK) void k_batch_final(FinalArgs f)
 {
     extern __shared__ unsigned char lds_f8[];
     const BatchArgs& a = f.b;
@@ -1076,7 +1084,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     const int band_per_cu = std::min(16, std::max(1, (int)(163840 / (lds_band + sizeof(int) * (BT_MAX_SERIES + 1)))));
     hipLaunchKernelGGL(k_batch_band, dim3((unsigned)(num_cu * band_per_cu)), dim3(64), lds_band, s, f,
                        band_rows, maxT);
-    hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(256), lds_f, s, f);
+    hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(FINAL_BLOCK), lds_f, s, f);
     hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, f.out_w, out_count,
                        quota, out_mean, out_cov);
     if ((rc = check_launch("k_batch finalisation"))) return rc;
