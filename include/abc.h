@@ -313,6 +313,15 @@ ABC_API abc_status abc_get_launch_config(int32_t* spl, int32_t* block, int32_t* 
 ABC_API abc_status abc_set_refill_min(int32_t lanes);
 ABC_API int32_t abc_get_refill_min(void);
 
+/* Margin of abc_batch_run's first target for the calling thread: every series
+ * takes samples until its float32 accepts reach quota + margin (at least 1),
+ * then the run is finalised; a series left with fewer than quota rows after
+ * the float64 band decision continues its stream (see abc_batch_run).
+ * 0 selects the default max(4, quota / 64). A negative margin makes the
+ * first finalisation come early, so that the continuation runs; results
+ * never depend on it. Errors: ABC_EINVAL unless |margin| <= 2^20. */
+ABC_API abc_status abc_set_batch_margin(int32_t margin);
+
 /* One observed series of a batch: as abc_series, plus its tolerance and its
  * stream series id (counter word 2; give every series of a batch its own). */
 typedef struct {
@@ -331,6 +340,7 @@ typedef struct {
     int64_t rechecked;     /* candidates decided in float64 */
     int32_t grid, block, spl, lds_bytes;
     float rounds_ms;       /* wall time of the rounds (host waits included) */
+    int32_t phases;        /* finalisations run (more than 1 when one kept fewer than quota rows) */
 } abc_batch_stats;
 
 /*
@@ -338,7 +348,7 @@ typedef struct {
  * launch per round (Sec. 3.1: repeat until the target number of accepted
  * samples; Sec. 3.2: accept-reject on the device), until every series has
  * `quota` accepted samples. Each round hands round_size samples, split evenly,
- * to the series still below quota; series j consumes its stream indices
+ * to the series still short of their target; series j consumes its stream indices
  * 0, 1, 2, ... as a prefix (theta drawn from `prior` on stream (seed, domain,
  * series[j].series)). Each round is planned on the device from the counts of
  * the rounds up to two before it, so consecutive rounds overlap (they
@@ -362,7 +372,12 @@ typedef struct {
  * (0 = max(4 quota, 256), at most 16384, and the finalisation sorts them in LDS: about
  * 12 B per row must fit, so 8192 rows at most on gfx950). Each round caps a series' share so
  * that the running round's and its own expected candidates stay within half the free capacity,
- * at an upper bound of the candidate rate so far ((sqrt(c + 1) + 2)^2 candidates for c counted).
+ * at an upper bound of the candidate rate so far ((sqrt(c + 1) + 2)^2 candidates for c counted),
+ * and to the samples its target still needs at a lower bound of its accept rate. A series'
+ * target counts float32 accepts (d <= eps), first quota + max(4, quota / 64); when the
+ * finalisation keeps fewer than quota rows of a series (float64 decisions moved accepts
+ * across eps), its target rises by the shortfall and the margin and the rounds continue
+ * its stream before a further finalisation (at most 8 in all; stats->phases counts them).
  * Launch shape: abc_set_launch_config (spl 1, 2, 4 or 8). Blocks the calling host thread until
  * done; the caller's stream is ordered before and after the work. stats may be NULL.
  */

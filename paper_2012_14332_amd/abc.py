@@ -66,7 +66,8 @@ class _BatchStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
                 ("sample_days", ctypes.c_int64), ("rechecked", ctypes.c_int64),
                 ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("spl", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("rounds_ms", ctypes.c_float)]
+                ("lds_bytes", ctypes.c_int32), ("rounds_ms", ctypes.c_float),
+                ("phases", ctypes.c_int32)]
 
 
 _lib = None
@@ -167,6 +168,8 @@ def lib():
         L.abc_set_refill_min.argtypes = [ctypes.c_int32]
         L.abc_set_refill_min.restype = ctypes.c_int32
         L.abc_get_refill_min.argtypes = []
+        L.abc_set_batch_margin.argtypes = [ctypes.c_int32]
+        L.abc_set_batch_margin.restype = ctypes.c_int32
         L.abc_get_refill_min.restype = ctypes.c_int32
         L.abc_trajectory_bands.argtypes = [vp, i64, ctypes.c_int32, vp, ctypes.c_int32, vp, vp]
         L.abc_trajectory_bands.restype = ctypes.c_int32
@@ -652,6 +655,11 @@ def set_refill_min(lanes: int):
 
 def get_refill_min() -> int:
     return int(lib().abc_get_refill_min())
+
+
+def set_batch_margin(margin: int):
+    """First target of batch_run's float32 accepts: quota + margin (0: default)."""
+    _check(lib().abc_set_batch_margin(int(margin)))
 
 
 def trajectory_bands(traj: torch.Tensor, quantiles=(0.05, 0.5, 0.95)) -> torch.Tensor:

@@ -4,9 +4,11 @@
 // point abc_batch_run.
 //
 // Round structure (all decisions on the device):
-//   k_batch_plan   one workgroup: series whose certain-accept count is below
-//                  the quota share the round's samples evenly; each gets the
-//                  next contiguous index range of its own stream. Plan p sees
+//   k_batch_plan   one workgroup: series whose float32 accepts (d <= eps)
+//                  are below their target (first Q + margin) share the
+//                  round's samples evenly, each capped by what its target
+//                  still needs; each gets the next contiguous index range
+//                  of its own stream. Plan p sees
 //                  the counts of rounds up to p - 2 only, so round p - 1 can
 //                  still run while it plans, and round p starts on the
 //                  workgroup slots round p - 1 frees at its end: the rounds
@@ -17,12 +19,14 @@
 //                  observed series of the whole batch sit in LDS, so a lane
 //                  never waits for the rest of its wave to change series.
 //                  A finished sample with d <= eps (1 + w) is appended to its
-//                  series' candidate list; d <= eps (1 - w) also counts as a
-//                  certain accept.
+//                  series' candidate list; d <= eps also counts as a
+//                  float32 accept.
 // Because each series consumes its indices as a prefix, the first Q
-// accepted samples by index are exact once Q certain accepts exist: the
-// finalisation decides the band candidates in float64, sorts by index and
-// keeps the first Q. The outcome does not depend on the launch shape.
+// accepted samples by index are exact once Q accepts exist among the
+// candidates: the finalisation decides the band candidates in float64, sorts
+// by index and keeps the first Q; a series left short continues its stream
+// with a higher target and is finalised again. The outcome does not depend
+// on the launch shape.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -52,15 +56,19 @@ struct SeriesDesc {         // device, per series, constant over the run
 };
 
 constexpr int BT_SLOTS = 3;  // round p counts into slot p % 3 until plan p + 2 folds it
+constexpr int BT_MAX_PHASES = 8;  // finalisations of one run (see abc_batch_run)
+thread_local int32_t g_batch_margin = 0;  // abc_set_batch_margin; 0: the default
 
 struct SeriesState {        // device, per series
     int64_t next;           // next sample index of the stream (assigned to some round)
     int64_t done;           // samples of the folded rounds
-    int32_t certain;        // accepts with d <= eps (1 - w) so far (every finished sample)
+    int32_t acc;            // samples with float32 d <= eps so far (every finished sample)
     int32_t cand;           // candidate rows handed out so far (may exceed capacity)
-    int32_t certain_f;      // certain accepts of the folded rounds
+    int32_t acc_f;          // float32 accepts of the folded rounds
     int32_t cand_f;         // candidates of the folded rounds
-    int32_t rc_certain[BT_SLOTS];  // per-round counts, by slot
+    int32_t target;         // the series takes samples until acc reaches this
+    int32_t pad;
+    int32_t rc_acc[BT_SLOTS];      // per-round counts, by slot
     int32_t rc_cand[BT_SLOTS];
     int64_t n_slot[BT_SLOTS];      // samples assigned to the round of each slot
 };
@@ -79,6 +87,7 @@ struct RoundTable {
 struct BatchArgs {
     int32_t m;
     int32_t quota;
+    int32_t target0;        // first target of every series' float32 accepts (quota + margin)
     int64_t round_size;
     int64_t max_samples;    // per series
     int32_t cand_cap;       // candidate rows per series
@@ -135,7 +144,28 @@ __global__ void k_batch_init(BatchArgs a)
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < a.m) {
         SeriesState z{};
+        z.target = a.target0;
         a.state[s] = z;
+    }
+}
+
+// after a finalisation that kept fewer than Q rows of some series (float64
+// decisions of band rows took more accepts away than the margin covered):
+// raise their targets so that the next rounds continue their streams, by the
+// shortfall over the series' observed ratio of kept rows to float32 accepts
+// (at least 1/16), and the margin
+__global__ void k_batch_retarget(BatchArgs a, const int64_t* count, int32_t margin)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < a.m) {
+        SeriesState& st = a.state[s];
+        const int64_t c = count[s];
+        if (c >= 0 && c < a.quota && st.next < a.max_samples) {
+            const double kept = (double)(c > 1 ? c : 1);
+            double per = st.acc > 0 ? (double)st.acc / kept : 1.0;  // float32 accepts per kept row
+            per = per < 1.0 ? 1.0 : (per > 16.0 ? 16.0 : per);
+            st.target = st.acc + (int32_t)ceil((double)(a.quota - c) * per) + margin;
+        }
     }
 }
 
@@ -166,24 +196,26 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
     const int p = a.round;
     bool active = false;
     int64_t next = 0, done = 0, inflight = 0;
-    int32_t cand_f = 0;
+    int32_t cand_f = 0, acc_f = 0, target = 0;
     if (tid < a.m) {
         SeriesState& st = a.state[s];
         if (p >= 2) {
             // round p - 2 has finished (this plan runs after it): fold its counts
             const int f = (p - 2) % BT_SLOTS;
-            st.certain_f += st.rc_certain[f];
+            st.acc_f += st.rc_acc[f];
             st.cand_f += st.rc_cand[f];
             st.done += st.n_slot[f];
-            st.rc_certain[f] = 0;
+            st.rc_acc[f] = 0;
             st.rc_cand[f] = 0;
             st.n_slot[f] = 0;
         }
         next = st.next;
         done = st.done;
         cand_f = st.cand_f;
+        acc_f = st.acc_f;
+        target = st.target;
         inflight = p >= 1 ? st.n_slot[(p - 1) % BT_SLOTS] : 0;  // round p - 1 may still run
-        active = st.certain_f < a.quota && next < a.max_samples;
+        active = acc_f < target && next < a.max_samples;
     }
     const uint64_t bal = __ballot(active);
     const int rank_w = __popcll(bal & ((1ull << lane) - 1ull));
@@ -216,6 +248,21 @@ __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_plan(BatchArgs a)
             int64_t lim = half > 0.0 ? (int64_t)(half / rate) : 0;
             if (lim < 64) lim = 64;
             if (n_s > lim) n_s = lim;
+            // and no more samples than the target still needs: the running
+            // round's samples and this round's must bring the float32
+            // accepts to the target at a lower bound of their rate,
+            // (sqrt(c) - 1)^2 per finished sample for c accepts (about two
+            // Poisson standard deviations below the count). Without this, a
+            // series' last rounds get a full share of the round, and the two
+            // rounds planned before its count is known simulate samples past
+            // its quota's last accept.
+            if (acc_f >= 4) {
+                const double cl = sqrt((double)acc_f) - 1.0;
+                const double rlo = cl * cl / (double)done;
+                const double left = (double)(target - acc_f) - rlo * (double)inflight;
+                const int64_t need = left > 0.0 ? (int64_t)(left / rlo) + 64 : 64;
+                if (n_s > need) n_s = need;
+            }
         } else {
             // no finished round yet: every sample assigned so far may be a
             // candidate, so the series' samples stay within the capacity,
@@ -444,9 +491,9 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                             a.cand_idx[(int64_t)l.series * a.cand_cap + pos] = l.i;
                             a.cand_dist[(int64_t)l.series * a.cand_cap + pos] = dd;
                         }
-                        if (dd <= ds.eps_lo) {
-                            atomicAdd(&st.certain, 1);
-                            atomicAdd(&st.rc_certain[a.round % BT_SLOTS], 1);
+                        if (dd <= ds.eps) {
+                            atomicAdd(&st.acc, 1);
+                            atomicAdd(&st.rc_acc[a.round % BT_SLOTS], 1);
                         }
                     }
                 }
@@ -464,14 +511,15 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
     }
 }
 
-// 1 once every series has its quota of certain accepts or used its maximum
+// 1 once every series has reached its target of float32 accepts or used its
+// maximum
 __global__ __launch_bounds__(BT_MAX_SERIES) void k_batch_flag(BatchArgs a)
 {
     __shared__ int open;
     if (threadIdx.x == 0) open = 0;
     __syncthreads();
     const int s = threadIdx.x;
-    if (s < a.m && a.state[s].certain < a.quota && a.state[s].next < a.max_samples)
+    if (s < a.m && a.state[s].acc < a.state[s].target && a.state[s].next < a.max_samples)
         atomicAdd(&open, 1);
     __syncthreads();
     if (threadIdx.x == 0) *a.flag_dev = open == 0 ? 1 : 0;
@@ -494,6 +542,7 @@ struct FinalArgs {
     int32_t* band_n;     // [m] band rows of each series (zeroed before k_band_collect)
     int32_t* band_q;     // [m][cand_cap] their positions in the candidate list
     int32_t* band_next;  // chunk counter of k_batch_band (zeroed with band_n)
+    int32_t* band_from;  // [m] candidates decided by earlier finalisations (zeroed once)
 };
 
 // bitonic sort of (idx, dist) pairs in LDS, ascending by idx. Each step
@@ -538,12 +587,13 @@ __global__ __launch_bounds__(256) void k_band_collect(FinalArgs f)
     const int s = blockIdx.x / COLLECT_GROUPS, g = blockIdx.x % COLLECT_GROUPS;
     const int cand = a.state[s].cand;
     const int n = cand < a.cand_cap ? cand : a.cand_cap;
+    const int q0 = f.band_from[s];  // earlier finalisations decided the rows before q0
     const float lo = a.desc[s].eps_lo;
     const float* cdist = a.cand_dist + (int64_t)s * a.cand_cap;
     int32_t* bq = f.band_q + (int64_t)s * a.cand_cap;
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
-    for (int base = (g * 4 + (int)(threadIdx.x >> 6)) * 64; base < n; base += COLLECT_GROUPS * 256) {
+    for (int base = q0 + (g * 4 + (int)(threadIdx.x >> 6)) * 64; base < n; base += COLLECT_GROUPS * 256) {
         const int q = base + lane;
         const bool inb = q < n && cdist[q] > lo;
         const uint64_t m = __ballot(inb);
@@ -688,6 +738,7 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_batch_final(FinalArgs f)
     if (threadIdx.x == 0) {
         f.out_count[s] = cand > a.cand_cap ? -(int64_t)cand : (int64_t)nkeep;
         f.out_used[s] = a.state[s].next;
+        f.band_from[s] = n;
     }
 }
 
@@ -896,7 +947,8 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     const size_t o_days = carve.take(sizeof(unsigned long long));
     const size_t o_order = carve.take(sizeof(int32_t) * m);
     const size_t o_mixtab = carve.take(prop ? sizeof(MixTable) * m : 0);
-    const size_t o_re = carve.take(sizeof(int32_t) * (2 * (size_t)m + 1));  // rechecked, band_n, counter
+    // rechecked, band_n, chunk counter (cleared by every finalisation), band_from
+    const size_t o_re = carve.take(sizeof(int32_t) * (3 * (size_t)m + 1));
     const size_t o_bq = carve.take(sizeof(int32_t) * (size_t)m * cand_cap);
     void* arena = nullptr;
     if ((rc = stream_scratch(user, carve.off, &arena, SCRATCH_BATCH))) return rc;
@@ -934,6 +986,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     BatchArgs a{};
     a.m = m;
     a.quota = quota;
+    a.target0 = std::max(1, quota + (g_batch_margin != 0 ? g_batch_margin : std::max(4, quota / 64)));
     a.round_size = round_size;
     a.max_samples = max_samples;
     a.cand_cap = cand_cap;
@@ -972,6 +1025,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     hipLaunchKernelGGL(k_batch_init, dim3((m + 255) / 256), dim3(256), 0, s, a);
     if ((rc = check_launch("k_batch setup"))) return rc;
     ABC_HIP(hipMemsetAsync(b_days.p, 0, sizeof(unsigned long long), s));
+    ABC_HIP(hipMemsetAsync(b_re.p, 0, sizeof(int32_t) * (3 * (size_t)m + 1), s));
 
     // Rounds alternate between two streams; plan p runs on s after plan
     // p - 1 and after round p - 2, round p after plan p, so round p - 1 can
@@ -1019,45 +1073,6 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         ~TimerFree() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } timer_free{t0, t1};
     ABC_HIP(hipEventRecord(t0, s));
-    int64_t rounds = 0, polls = 0, stop_at = -1;
-    while (rounds < max_rounds && (stop_at < 0 || rounds <= stop_at)) {
-        const int64_t p = rounds;
-        const int e = (int)(p % BT_EVR);
-        BatchArgs ap = a;
-        ap.table = tables + (p & 1);
-        ap.round = (int32_t)p;
-        ap.flag_dev = flags_dev + e;
-        if (p >= 2) ABC_HIP(hipStreamWaitEvent(s, ev_round[(p - 2) % BT_EVR], 0));
-        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(BT_MAX_SERIES), 0, s, ap);
-        ABC_HIP(hipEventRecord(ev_plan[e], s));
-        hipStream_t r = rs[p & 1];
-        ABC_HIP(hipStreamWaitEvent(r, ev_plan[e], 0));
-        switch (spl) {
-        case 1: launch_round<1>(ap, grid, block, lds, r); break;
-        case 2: launch_round<2>(ap, grid, block, lds, r); break;
-        case 4: launch_round<4>(ap, grid, block, lds, r); break;
-        case 8: launch_round<8>(ap, grid, block, lds, r); break;
-        }
-        hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(BT_MAX_SERIES), 0, r, ap);
-        ABC_HIP(hipMemcpyAsync(flag_host + e, ap.flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, r));
-        ABC_HIP(hipEventRecord(ev_round[e], r));
-        if ((rc = check_launch("k_batch round"))) return rc;
-        ++rounds;
-        if (p >= L && stop_at < 0) {
-            const int64_t q = p - L;
-            ABC_HIP(hipEventSynchronize(ev_round[q % BT_EVR]));
-            ++polls;
-            if (flag_host[q % BT_EVR]) stop_at = q + 2;
-        }
-    }
-    // the last two rounds are on the two round streams
-    for (int64_t q = rounds - 2; q < rounds; ++q)
-        if (q >= 0) ABC_HIP(hipStreamWaitEvent(s, ev_round[q % BT_EVR], 0));
-    ABC_HIP(hipEventRecord(t1, s));
-    ABC_HIP(hipEventSynchronize(t1));
-    float rounds_ms = 0.0f;
-    ABC_HIP(hipEventElapsedTime(&rounds_ms, t0, t1));
-
     FinalArgs f{};
     f.b = a;
     f.obs = reinterpret_cast<const int32_t* const*>(b_ptrs.p);
@@ -1071,6 +1086,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     f.out_rechecked = reinterpret_cast<int32_t*>(b_re.p);
     f.band_n = f.out_rechecked + m;
     f.band_next = f.band_n + m;
+    f.band_from = f.band_next + 1;
     f.band_q = reinterpret_cast<int32_t*>(b_bq.p);
     const int npow = npow_cap;
     const size_t lds_f = sizeof(int64_t) * npow + sizeof(float) * (npow + 1) + 16;
@@ -1078,22 +1094,89 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     const int band_rows = ROWS_PER_WAVE_MAX;
     const size_t lds_band = band_lds_bytes(maxT, band_rows);
     ABC_REQUIRE(lds_band <= (size_t)max_lds, "horizon too long for the band decision");
-    ABC_HIP(hipMemsetAsync(b_re.p, 0, sizeof(int32_t) * (2 * (size_t)m + 1), s));
-    hipLaunchKernelGGL(k_band_collect, dim3((unsigned)m * COLLECT_GROUPS), dim3(256), 0, s, f);
-    // one-wavefront workgroups: as many as the LDS holds per CU, at most 16
-    const int band_per_cu = std::min(16, std::max(1, (int)(163840 / (lds_band + sizeof(int) * (BT_MAX_SERIES + 1)))));
-    hipLaunchKernelGGL(k_batch_band, dim3((unsigned)(num_cu * band_per_cu)), dim3(64), lds_band, s, f,
-                       band_rows, maxT);
-    hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(FINAL_BLOCK), lds_f, s, f);
+    // A series stops taking samples once its float32 accepts (d <= eps)
+    // reach its target, first Q + margin. Float64 decisions of band rows can
+    // take a few of those accepts away (and add others); a finalisation that
+    // keeps fewer than Q rows of a series raises its target by the shortfall
+    // and the margin, and the rounds continue its stream: each phase only
+    // adds samples in index order, and the last finalisation decides every
+    // candidate, so the rows kept are still the first Q accepts.
+    const int32_t margin = std::max(4, quota / 64);  // of every later target
+    int64_t rounds = 0, polls = 0, stop_at = -1, phase0 = 0, rechecked = 0;
+    int32_t phases = 0;
+    std::vector<int64_t> cnt(m), used_h(m);
+    std::vector<int32_t> rech(m);
+    float rounds_ms = 0.0f;
+    for (;;) {
+        const int64_t round_cap = rounds + max_rounds;
+        while (rounds < round_cap && (stop_at < 0 || rounds <= stop_at)) {
+            const int64_t p = rounds;
+            const int e = (int)(p % BT_EVR);
+            BatchArgs ap = a;
+            ap.table = tables + (p & 1);
+            ap.round = (int32_t)p;
+            ap.flag_dev = flags_dev + e;
+            if (p >= 2) ABC_HIP(hipStreamWaitEvent(s, ev_round[(p - 2) % BT_EVR], 0));
+            hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(BT_MAX_SERIES), 0, s, ap);
+            ABC_HIP(hipEventRecord(ev_plan[e], s));
+            hipStream_t r = rs[p & 1];
+            ABC_HIP(hipStreamWaitEvent(r, ev_plan[e], 0));
+            switch (spl) {
+            case 1: launch_round<1>(ap, grid, block, lds, r); break;
+            case 2: launch_round<2>(ap, grid, block, lds, r); break;
+            case 4: launch_round<4>(ap, grid, block, lds, r); break;
+            case 8: launch_round<8>(ap, grid, block, lds, r); break;
+            }
+            hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(BT_MAX_SERIES), 0, r, ap);
+            ABC_HIP(hipMemcpyAsync(flag_host + e, ap.flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, r));
+            ABC_HIP(hipEventRecord(ev_round[e], r));
+            if ((rc = check_launch("k_batch round"))) return rc;
+            ++rounds;
+            if (p >= phase0 + L && stop_at < 0) {
+                const int64_t q = p - L;
+                ABC_HIP(hipEventSynchronize(ev_round[q % BT_EVR]));
+                ++polls;
+                if (flag_host[q % BT_EVR]) stop_at = q + 2;
+            }
+        }
+        // the last two rounds are on the two round streams
+        for (int64_t q = rounds - 2; q < rounds; ++q)
+            if (q >= 0) ABC_HIP(hipStreamWaitEvent(s, ev_round[q % BT_EVR], 0));
+        ABC_HIP(hipEventRecord(t1, s));
+        ABC_HIP(hipEventSynchronize(t1));
+        ABC_HIP(hipEventElapsedTime(&rounds_ms, t0, t1));
+
+        ABC_HIP(hipMemsetAsync(b_re.p, 0, sizeof(int32_t) * (2 * (size_t)m + 1), s));
+        hipLaunchKernelGGL(k_band_collect, dim3((unsigned)m * COLLECT_GROUPS), dim3(256), 0, s, f);
+        // one-wavefront workgroups: as many as the LDS holds per CU, at most 16
+        const int band_per_cu = std::min(16, std::max(1, (int)(163840 / (lds_band + sizeof(int) * (BT_MAX_SERIES + 1)))));
+        hipLaunchKernelGGL(k_batch_band, dim3((unsigned)(num_cu * band_per_cu)), dim3(64), lds_band, s, f,
+                           band_rows, maxT);
+        hipLaunchKernelGGL(k_batch_final, dim3(m), dim3(FINAL_BLOCK), lds_f, s, f);
+        if ((rc = check_launch("k_batch finalisation"))) return rc;
+        ABC_HIP(hipMemcpyAsync(rech.data(), b_re.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+        ABC_HIP(hipMemcpyAsync(cnt.data(), out_count, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+        ABC_HIP(hipMemcpyAsync(used_h.data(), out_used, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+        ABC_HIP(hipStreamSynchronize(s));
+        ++phases;
+        for (int s2 = 0; s2 < m; ++s2) rechecked += rech[s2];
+        bool overflow = false, short_q = false;
+        for (int s2 = 0; s2 < m; ++s2) {
+            overflow |= cnt[s2] < 0;
+            short_q |= cnt[s2] >= 0 && cnt[s2] < quota && used_h[s2] < max_samples;
+        }
+        const bool stopped = stop_at >= 0 && rounds > stop_at;
+        if (overflow || !short_q || !stopped || phases >= BT_MAX_PHASES) break;
+        hipLaunchKernelGGL(k_batch_retarget, dim3((m + 255) / 256), dim3(256), 0, s, a, out_count, margin);
+        if ((rc = check_launch("k_batch_retarget"))) return rc;
+        phase0 = rounds;
+        stop_at = -1;
+    }
     hipLaunchKernelGGL(k_batch_moments, dim3(m), dim3(256), 0, s, out_theta, f.out_w, out_count,
                        quota, out_mean, out_cov);
-    if ((rc = check_launch("k_batch finalisation"))) return rc;
-    std::vector<int32_t> rech(m);
+    if ((rc = check_launch("k_batch moments"))) return rc;
     unsigned long long days = 0;
-    ABC_HIP(hipMemcpyAsync(rech.data(), b_re.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
     ABC_HIP(hipMemcpyAsync(&days, b_days.p, sizeof(days), hipMemcpyDeviceToHost, s));
-    std::vector<int64_t> cnt(m);
-    ABC_HIP(hipMemcpyAsync(cnt.data(), out_count, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
     ABC_HIP(hipStreamSynchronize(s));
     ABC_HIP(hipEventRecord(ev, s));
     ABC_HIP(hipStreamWaitEvent(user, ev, 0));
@@ -1101,9 +1184,8 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         stats->rounds = rounds;
         stats->graph_replays = polls;
         stats->sample_days = (int64_t)days;
-        int64_t re = 0;
-        for (int s2 = 0; s2 < m; ++s2) re += rech[s2];
-        stats->rechecked = re;
+        stats->rechecked = rechecked;
+        stats->phases = phases;
         stats->grid = (int32_t)grid;
         stats->block = block;
         stats->spl = spl;
@@ -1115,9 +1197,10 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
             SeriesState st{};
             (void)hipMemcpy(&st, a.state + s2, sizeof(st), hipMemcpyDeviceToHost);
             return set_error(ABC_EOVERFLOW,
-                             "series %d: %lld candidates exceed the capacity %d (certain %d; folded: "
-                             "certain %d, candidates %d, samples %lld of %lld; %lld rounds, stop %lld)",
-                             s2, (long long)-cnt[s2], cand_cap, st.certain, st.certain_f, st.cand_f,
+                             "series %d: %lld candidates exceed the capacity %d (float32 accepts %d of "
+                             "target %d; folded: accepts %d, candidates %d, samples %lld of %lld; "
+                             "%lld rounds, stop %lld)",
+                             s2, (long long)-cnt[s2], cand_cap, st.acc, st.target, st.acc_f, st.cand_f,
                              (long long)st.done, (long long)st.next, (long long)rounds,
                              (long long)stop_at);
         }
@@ -1128,6 +1211,13 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     if (stop_at < 0 && (rounds == 0 || !flag_host[(rounds - 1) % BT_EVR]))
         return set_error(ABC_EOVERFLOW, "stopped after %lld rounds before every quota was met",
                          (long long)rounds);
+    return ABC_OK;
+}
+
+extern "C" abc_status abc_set_batch_margin(int32_t margin)
+{
+    ABC_REQUIRE(margin >= -(1 << 20) && margin <= (1 << 20), "margin must be within +-2^20");
+    g_batch_margin = margin;
     return ABC_OK;
 }
 

@@ -122,6 +122,9 @@ def test_host_validation_of_the_newer_entry_points(built):
     # refill threshold
     assert L.abc_set_refill_min(65) == -1 and L.abc_set_refill_min(-1) == -1
     assert L.abc_get_refill_min() == 8
+    # batch margin
+    assert L.abc_set_batch_margin((1 << 20) + 1) == -1 and L.abc_set_batch_margin(-(1 << 20) - 1) == -1
+    assert L.abc_set_batch_margin(-5) == 0 and L.abc_set_batch_margin(0) == 0
     # batched proposal: NULL proposal, lambda and inflate out of range
     bs = (abc._BatchSeries * 1)(abc._BatchSeries(1000000, 100, 0, 0, 10, 0x1000, 1.0, 0))
     bst = abc._BatchStats()

@@ -102,6 +102,27 @@ def test_batch_equals_plain_path(env):
         np.testing.assert_allclose(o["cov"][j].cpu().numpy(), rc, rtol=1e-9, atol=1e-12)
 
 
+def test_batch_continues_a_series_left_short(env):
+    """A first target far below the quota (margin -Q/2) makes the first
+    finalisation keep about half of each series' rows; the series continue
+    their streams and are finalised again. The rows kept are the default
+    run's, whatever the schedule."""
+    abc, _ = env
+    ss, sers, eps = _setup(env, 8, 5e-3)
+    quota = 40
+    ref = abc.batch_run(sers, eps, 9, quota, round_size=1 << 16)
+    for margin in (-quota // 2, -quota + 1):
+        try:
+            abc.set_batch_margin(margin)
+            o = abc.batch_run(sers, eps, 9, quota, round_size=1 << 16)
+        finally:
+            abc.set_batch_margin(0)
+        assert o["stats"]["phases"] >= 2, (margin, o["stats"])
+        for k in ("idx", "theta", "dist", "count"):
+            np.testing.assert_array_equal(o[k].cpu().numpy(), ref[k].cpu().numpy(), err_msg=k)
+        np.testing.assert_allclose(o["mean"].cpu().numpy(), ref["mean"].cpu().numpy(), rtol=1e-13)
+
+
 def test_batch_limits(env):
     abc, _ = env
     ss, sers, eps = _setup(env, 4, 1e-3)
