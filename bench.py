@@ -328,9 +328,9 @@ def learned_leg(args, batched):
     # posteriors of some series are heavy-tailed, so their sds need far more
     # samples than 1e4 to be known to 5 %)
     Qc = args.compare_quota
-    # candidates (within the float64 band around eps) per certain accept can
-    # exceed 2 where the distance distribution is steep near eps: 4x headroom,
-    # within the 8192 rows the finalisation sorts in LDS
+    # candidates (d <= eps (1 + w)) per accept can approach 2 where the
+    # distance distribution is steep near eps: 4x headroom, within the 8192
+    # rows the finalisation sorts in LDS
     cap_c = min(4 * Qc, 8192)
 
     def sampler(runs_kw):
