@@ -374,7 +374,7 @@ typedef struct {
  * that the running round's and its own expected candidates stay within half the free capacity,
  * at an upper bound of the candidate rate so far ((sqrt(c + 1) + 2)^2 candidates for c counted),
  * and to the samples its target still needs at a lower bound of its accept rate. A series'
- * target counts float32 accepts (d <= eps), first quota + max(4, quota / 64); when the
+ * target counts float32 accepts (d <= eps (1 - 1e-5)), first quota + max(4, quota / 64); when the
  * finalisation keeps fewer than quota rows of a series (float64 decisions moved accepts
  * across eps), its target rises by the shortfall and the margin and the rounds continue
  * its stream before a further finalisation (at most 8 in all; stats->phases counts them).

@@ -52,17 +52,23 @@ struct SeriesDesc {         // device, per series, constant over the run
     float exit2;            // early-exit bound on the log2-unit sum
     float eps_hi, eps_lo, eps;
     uint32_t u0, b1;        // wave-uniform Philox words of this series
-    uint32_t pad;
+    float eps_cnt;          // float32 accepts with d <= eps_cnt count toward the target
 };
 
 constexpr int BT_SLOTS = 3;  // round p counts into slot p % 3 until plan p + 2 folds it
 constexpr int BT_MAX_PHASES = 8;  // finalisations of one run (see abc_batch_run)
+// Float32 accepts within this relative distance below eps do not count
+// toward a series' target. Float32 and float64 distances differ by a few
+// 1e-6 relative near eps, and identical trajectories (an atom of the distance
+// distribution) share one distance: when eps is an atom's float32 distance,
+// float64 puts all of the atom on one side of eps, often the far one.
+constexpr double BT_TIE = 1e-5;
 thread_local int32_t g_batch_margin = 0;  // abc_set_batch_margin; 0: the default
 
 struct SeriesState {        // device, per series
     int64_t next;           // next sample index of the stream (assigned to some round)
     int64_t done;           // samples of the folded rounds
-    int32_t acc;            // samples with float32 d <= eps so far (every finished sample)
+    int32_t acc;            // samples with float32 d <= eps_cnt so far (every finished sample)
     int32_t cand;           // candidate rows handed out so far (may exceed capacity)
     int32_t acc_f;          // float32 accepts of the folded rounds
     int32_t cand_f;         // candidates of the folded rounds
@@ -491,7 +497,7 @@ __global__ __launch_bounds__(1024 / SPL) void k_batch_round(BatchArgs a)
                             a.cand_idx[(int64_t)l.series * a.cand_cap + pos] = l.i;
                             a.cand_dist[(int64_t)l.series * a.cand_cap + pos] = dd;
                         }
-                        if (dd <= ds.eps) {
+                        if (dd <= ds.eps_cnt) {
                             atomicAdd(&st.acc, 1);
                             atomicAdd(&st.rc_acc[a.round % BT_SLOTS], 1);
                         }
@@ -884,11 +890,11 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
         d.eps_hi = (float)hi;
         d.eps_lo = (float)((double)b.eps * (1.0 - (double)band_w));
         d.eps = b.eps;
+        d.eps_cnt = (float)((double)b.eps * (1.0 - BT_TIE));
         d.exit2 = (float)(hi * hi * 2.08136898100560809980 * (1.0 + 0x1p-18));
         const uint64_t p1 = (uint64_t)PH_M1 * (uint64_t)b.series;
         d.u0 = (uint32_t)(p1 >> 32) ^ key.k0;
         d.b1 = (uint32_t)p1 ^ (key.k0 + PH_W0);
-        d.pad = 0;
         obs_words += 3 * b.T;
         obs_ptr[s] = b.obs;
         if (b.T > maxT) maxT = b.T;
