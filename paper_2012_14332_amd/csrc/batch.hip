@@ -4,8 +4,8 @@
 // point abc_batch_run.
 //
 // Round structure (all decisions on the device):
-//   k_batch_plan   one workgroup: series whose float32 accepts (d <= eps)
-//                  are below their target (first Q + margin) share the
+//   k_batch_plan   one workgroup: series whose float32 accepts (d a hair
+//                  below eps) are below their target (first Q + margin) share the
 //                  round's samples evenly, each capped by what its target
 //                  still needs; each gets the next contiguous index range
 //                  of its own stream. Plan p sees
@@ -19,8 +19,8 @@
 //                  observed series of the whole batch sit in LDS, so a lane
 //                  never waits for the rest of its wave to change series.
 //                  A finished sample with d <= eps (1 + w) is appended to its
-//                  series' candidate list; d <= eps also counts as a
-//                  float32 accept.
+//                  series' candidate list; d <= eps (1 - 1e-5) also counts
+//                  as a float32 accept toward the series' target.
 // Because each series consumes its indices as a prefix, the first Q
 // accepted samples by index are exact once Q accepts exist among the
 // candidates: the finalisation decides the band candidates in float64, sorts
