@@ -4,9 +4,9 @@
 // point abc_batch_run.
 //
 // Round structure (all decisions on the device):
-//   k_batch_plan   one workgroup: series whose float32 accepts (d a hair
-//                  below eps) are below their target (first Q + margin) share the
-//                  round's samples evenly, each capped by what its target
+//   k_batch_plan   one workgroup: series whose float32 accepts
+//                  (d <= eps (1 - 1e-5)) are below their target (first
+//                  Q + margin) share the round's samples evenly, each capped by what its target
 //                  still needs; each gets the next contiguous index range
 //                  of its own stream. Plan p sees
 //                  the counts of rounds up to p - 2 only, so round p - 1 can
