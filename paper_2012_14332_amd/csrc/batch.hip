@@ -6,10 +6,10 @@
 // Round structure (all decisions on the device):
 //   k_batch_plan   one workgroup: series whose float32 accepts
 //                  (d <= eps (1 - 1e-5)) are below their target (first
-//                  Q + margin) share the round's samples evenly, each capped by what its target
-//                  still needs; each gets the next contiguous index range
-//                  of its own stream. Plan p sees
-//                  the counts of rounds up to p - 2 only, so round p - 1 can
+//                  Q + margin) share the round's samples evenly, each
+//                  capped by what its target still needs; each gets the
+//                  next contiguous index range of its own stream. Plan p
+//                  sees the counts of rounds up to p - 2 only, so round p - 1 can
 //                  still run while it plans, and round p starts on the
 //                  workgroup slots round p - 1 frees at its end: the rounds
 //                  alternate between two streams and overlap their tails.
