@@ -317,7 +317,7 @@ ABC_API int32_t abc_get_refill_min(void);
  * takes samples until its float32 accepts reach quota + margin (at least 1),
  * then the run is finalised; a series left with fewer than quota rows after
  * the float64 band decision continues its stream (see abc_batch_run).
- * 0 selects the default max(4, quota / 64). A negative margin makes the
+ * 0 selects the default max(4, quota / 256). A negative margin makes the
  * first finalisation come early, so that the continuation runs; results
  * never depend on it. Errors: ABC_EINVAL unless |margin| <= 2^20. */
 ABC_API abc_status abc_set_batch_margin(int32_t margin);
@@ -374,7 +374,7 @@ typedef struct {
  * that the running round's and its own expected candidates stay within half the free capacity,
  * at an upper bound of the candidate rate so far ((sqrt(c + 1) + 2)^2 candidates for c counted),
  * and to the samples its target still needs at a lower bound of its accept rate. A series'
- * target counts float32 accepts (d <= eps (1 - 1e-5)), first quota + max(4, quota / 64); when the
+ * target counts float32 accepts (d <= eps (1 - 1e-5)), first quota + max(4, quota / 256); when the
  * finalisation keeps fewer than quota rows of a series (float64 decisions moved accepts
  * across eps), its target rises by the shortfall and the margin and the rounds continue
  * its stream before a further finalisation (at most 8 in all; stats->phases counts them).

@@ -992,7 +992,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     BatchArgs a{};
     a.m = m;
     a.quota = quota;
-    a.target0 = std::max(1, quota + (g_batch_margin != 0 ? g_batch_margin : std::max(4, quota / 64)));
+    a.target0 = std::max(1, quota + (g_batch_margin != 0 ? g_batch_margin : std::max(4, quota / 256)));
     a.round_size = round_size;
     a.max_samples = max_samples;
     a.cand_cap = cand_cap;
@@ -1107,7 +1107,7 @@ static abc_status batch_run(const abc_batch_series* series, int32_t m, const abc
     // and the margin, and the rounds continue its stream: each phase only
     // adds samples in index order, and the last finalisation decides every
     // candidate, so the rows kept are still the first Q accepts.
-    const int32_t margin = std::max(4, quota / 64);  // of every later target
+    const int32_t margin = std::max(4, quota / 256);  // of every later target
     int64_t rounds = 0, polls = 0, stop_at = -1, phase0 = 0, rechecked = 0;
     int32_t phases = 0;
     std::vector<int64_t> cnt(m), used_h(m);
