@@ -614,21 +614,23 @@ __global__ __launch_bounds__(256) void k_band_collect(FinalArgs f)
 __global__ __launch_bounds__(64) void k_batch_band(FinalArgs f, int rows_max, int max_T)
 {
     extern __shared__ double lds_band[];
-    __shared__ int pre[BT_MAX_SERIES + 1];  // first chunk of each series
+    __shared__ int pre[BT_MAX_SERIES + 1];  // first chunk of each series, in planning order
     const BatchArgs& a = f.b;
     const int lane = threadIdx.x;
-    // chunks of series s: ceil(band_n[s] / rows_max), laid out in series order
+    // chunks of series order[j]: ceil(band_n / rows_max), laid out in the
+    // planning order (longest horizon first), so that the longest walks are
+    // taken first and the short ones fill in around them
     int total = 0;
-    for (int s0 = 0; s0 < a.m; s0 += 64) {
-        const int s = s0 + lane;
-        const int c = s < a.m ? (f.band_n[s] + rows_max - 1) / rows_max : 0;
+    for (int b0 = 0; b0 < a.m; b0 += 64) {
+        const int j = b0 + lane;
+        const int c = j < a.m ? (f.band_n[a.order[j]] + rows_max - 1) / rows_max : 0;
         int incl = c;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int o = __shfl_up(incl, off, 64);
             if (lane >= off) incl += o;
         }
-        if (s < a.m) pre[s + 1] = total + incl;
+        if (j < a.m) pre[j + 1] = total + incl;
         total += __shfl(incl, 63, 64);
     }
     if (lane == 0) pre[0] = 0;
@@ -647,16 +649,16 @@ __global__ __launch_bounds__(64) void k_batch_band(FinalArgs f, int rows_max, in
         if (lane == 0) c = atomicAdd(f.band_next, 1);
         c = __shfl(c, 0, 64);
         if (c >= total) break;
-        // the series whose chunks hold c: pre[s] <= c < pre[s + 1]
+        // the series whose chunks hold c: pre[j] <= c < pre[j + 1], s = order[j]
         int lo = 0, hi = a.m;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (pre[mid] <= c) lo = mid;
             else hi = mid;
         }
-        const int s = lo;
+        const int s = a.order[lo];
         const SeriesDesc d = a.desc[s];
-        const int j0 = (c - pre[s]) * rows_max;
+        const int j0 = (c - pre[lo]) * rows_max;
         const int nb = f.band_n[s];
         const int nr = nb - j0 < rows_max ? nb - j0 : rows_max;
         int64_t* cidx = a.cand_idx + (int64_t)s * a.cand_cap;
