@@ -751,63 +751,95 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_batch_final(FinalArgs f)
 }
 
 // Float64 mean and covariance of each series' accepted theta: one workgroup
-// per series, two passes (mean, then centred products), fixed reduction order.
-__device__ double block_sum_f64(double v, double* red)
+// per series, fixed reduction order.
+
+// V sums at once: each is reduced by a butterfly within the wavefront, then
+// over the wavefronts in order (a fixed order); red holds [waves][V]
+template <int V>
+__device__ void block_sum_f64_v(double (&v)[V], double* red)
 {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int i = 0; i < V; ++i) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) red[wave] = v;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) red[wave * V + i] = v[i];
+    }
     __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    return t;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w * V + i];
+        v[i] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_batch_moments(const float* theta, const float* weight,
                                                        const int64_t* count, int quota, double* mean,
                                                        double* cov)
 {
-    __shared__ double red[4];
+    __shared__ double red[4 * 36];
     const int s = blockIdx.x;
     const int64_t n = count[s] > 0 ? (count[s] < quota ? count[s] : quota) : 0;
     const float* th = theta + (int64_t)s * quota * 8;
     const float* w = weight ? weight + (int64_t)s * quota : nullptr;
     // unweighted: mean and the unbiased (n - 1) covariance; weighted: sum w theta / V1
-    // and sum w (theta - mean)(theta - mean)^T / (V1 - V2 / V1)
+    // and sum w (theta - mean)(theta - mean)^T / (V1 - V2 / V1). One pass over
+    // the rows per stage (weights, means, centred products), every sum of a
+    // stage reduced together.
     double v1 = (double)n, v2 = (double)n;
     if (w) {
-        double a1 = 0.0, a2 = 0.0;
+        double a[2] = {0.0, 0.0};
         for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
             const double x = (double)w[r];
-            a1 += x;
-            a2 += x * x;
+            a[0] += x;
+            a[1] += x * x;
         }
-        v1 = block_sum_f64(a1, red);
-        v2 = block_sum_f64(a2, red);
+        block_sum_f64_v(a, red);
+        v1 = a[0];
+        v2 = a[1];
     }
     double mu[8];
-    for (int j = 0; j < 8; ++j) {
-        double v = 0.0;
-        for (int64_t r = threadIdx.x; r < n; r += blockDim.x)
-            v += (w ? (double)w[r] : 1.0) * (double)th[8 * r + j];
-        mu[j] = block_sum_f64(v, red) / v1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) mu[j] = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const double x = w ? (double)w[r] : 1.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) mu[j] += x * (double)th[8 * r + j];
     }
+    block_sum_f64_v(mu, red);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) mu[j] /= v1;
     const double denom = w ? v1 - v2 / v1 : (double)(n - 1);
-    for (int j = 0; j < 8; ++j)
-        for (int l = j; l < 8; ++l) {
-            double v = 0.0;
-            for (int64_t r = threadIdx.x; r < n; r += blockDim.x)
-                v += (w ? (double)w[r] : 1.0) * (((double)th[8 * r + j] - mu[j]) * ((double)th[8 * r + l] - mu[l]));
-            const double c = block_sum_f64(v, red) / denom;
-            if (threadIdx.x == 0) {
+    double cv[36];
+#pragma unroll
+    for (int q = 0; q < 36; ++q) cv[q] = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const double x = w ? (double)w[r] : 1.0;
+        double d[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) d[j] = (double)th[8 * r + j] - mu[j];
+        int q = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int l = j; l < 8; ++l) cv[q++] += x * (d[j] * d[l]);
+    }
+    block_sum_f64_v(cv, red);
+    if (threadIdx.x == 0) {
+        int q = 0;
+        for (int j = 0; j < 8; ++j)
+            for (int l = j; l < 8; ++l) {
+                const double c = cv[q++] / denom;
                 cov[(int64_t)s * 64 + 8 * j + l] = c;
                 cov[(int64_t)s * 64 + 8 * l + j] = c;
             }
-        }
-    if (threadIdx.x == 0)
         for (int j = 0; j < 8; ++j) mean[(int64_t)s * 8 + j] = n > 0 ? mu[j] : NAN;
+    }
 }
 
 static size_t batch_lds_bytes(int m, int obs_words, int block)
