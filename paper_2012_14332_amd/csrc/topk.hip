@@ -272,8 +272,20 @@ __global__ __launch_bounds__(256) void k_rows_rank(const double* d, const int64_
     if (q >= n) return;
     const double dq = d[q];
     const int64_t iq = idx[q];
-    int64_t r = 0;
-    for (int64_t j = 0; j < n; ++j) r += row_less(d[j], idx[j], dq, iq) ? 1 : 0;
+    // eight rows' loads in flight at a time (a short row set is latency-bound)
+    int64_t r = 0, j = 0;
+    for (; j + 8 <= n; j += 8) {
+        double dj[8];
+        int64_t ij[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dj[u] = d[j + u];
+            ij[u] = idx[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r += row_less(dj[u], ij[u], dq, iq) ? 1 : 0;
+    }
+    for (; j < n; ++j) r += row_less(d[j], idx[j], dq, iq) ? 1 : 0;
     rank[q] = r < k ? (int32_t)r : -1;
 }
 
@@ -284,8 +296,20 @@ __global__ __launch_bounds__(256) void k_rows_place(const double* d, const int64
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n || rank[q] < 0) return;
     const int64_t iq = idx[q];
-    int64_t pos = 0;  // selected rows with a smaller sample index
-    for (int64_t j = 0; j < n; ++j) pos += (rank[j] >= 0 && (idx[j] < iq || (idx[j] == iq && j < q))) ? 1 : 0;
+    int64_t pos = 0, j = 0;  // selected rows with a smaller sample index
+    for (; j + 8 <= n; j += 8) {
+        int32_t rj[8];
+        int64_t ij[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            rj[u] = rank[j + u];
+            ij[u] = idx[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            pos += (rj[u] >= 0 && (ij[u] < iq || (ij[u] == iq && j + u < q))) ? 1 : 0;
+    }
+    for (; j < n; ++j) pos += (rank[j] >= 0 && (idx[j] < iq || (idx[j] == iq && j < q))) ? 1 : 0;
     out_idx[pos] = iq;
     if (out_d) out_d[pos] = d[q];
     if (out_theta)
